@@ -1,0 +1,160 @@
+/*
+ * qcw.h -- C ABI of the MI355X (gfx950) gate-sweep library.
+ *
+ * The library applies QCWAVE's k-qubit operators (Tabakin & Julia-Diaz,
+ * "QCWAVE - a Mathematica quantum computer simulation update",
+ * arXiv:1101.1785) to complex FP64 state vectors held in GPU memory.
+ *
+ * Conventions shared by every call (paper §2c Eq. staten; §3a-§3c):
+ *   - A state of nq qubits is 2^nq amplitudes of qcw_c64 (16 bytes, re then
+ *     im), contiguous, amplitude C_n at offset n, where
+ *     n = sum_i q_i 2^(nq-i).  Qubit 1 is the MOST significant bit of n, so
+ *     qubit `is` owns bit nq - is and has stride 2^(nq-is).
+ *   - Qubits are numbered 1..nq, as in the paper's Op1/Op2/Op3 calls.
+ *   - A k-qubit gate (k = 1, 2, 3) is an m x m complex matrix, m = 2^k,
+ *     row-major, U[r*m + c] = <r|U|c>.  The local index r lists the values
+ *     of the targets in ARGUMENT order, the first target most significant:
+ *     r = sum_j q_{is_j} 2^(k-j).  For k = 2 this is V_{ij;kl} = <ij|V|kl>
+ *     with i the value of is1 (§3b, Eq. resmat2); k = 3 extends it the same
+ *     way (§3c omits the derivation).  Any order of distinct targets is
+ *     allowed: CNOT with control 3 and target 1 is qcw_op2(CNOT, 3, 1, ...).
+ *   - Matrices need not be unitary: the sweep is linear in U, and noise or
+ *     Kraus operators are scaled unitaries.  States are never renormalised.
+ *
+ * Memory and ownership:
+ *   - `psi`, `psi_in`, `psi_out` are DEVICE pointers owned by the caller;
+ *     each must lie inside one device allocation that holds all 2^nq
+ *     amplitudes (checked; a buffer that is too short is rejected).
+ *   - Gate matrices, gate lists and target arrays are HOST pointers; they
+ *     are consumed before the call returns and may be freed right after.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     asynchronously on it; the call does not synchronise.
+ *
+ * Errors: every call returns QCW_OK or a negative code synchronously and
+ * raises no exception.  QCW_EINVAL: null pointer, nq outside [1, 34],
+ * k outside {1, 2, 3} or k > nq, a target outside [1, nq], repeated targets,
+ * a pointer that is not device memory or a buffer shorter than the state,
+ * or partially overlapping input and output.  QCW_EHIP: a HIP runtime call
+ * or kernel launch failed.  Faults inside kernels surface at the caller's
+ * next synchronisation of the stream.  qcw_last_error() returns a
+ * thread-local description of the most recent failure.
+ *
+ * Threading: calls on different streams may run from different threads.
+ */
+#ifndef QCW_H
+#define QCW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} qcw_c64; /* same layout as complex128 / hipDoubleComplex */
+
+enum {
+  QCW_OK = 0,
+  QCW_EINVAL = -1,
+  QCW_ENOMEM = -2,
+  QCW_EHIP = -3,
+  QCW_EAGAIN = -4
+};
+
+/* Human-readable name of an error code (static string). */
+const char *qcw_strerror(int code);
+/* Description of the calling thread's most recent failure ("" if none). */
+const char *qcw_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int qcw_version(void);
+
+/*
+ * Op1 (§3a, Eqs. oneopres and resmat1): for each of the 2^nq / 2 partner
+ * pairs (n0, n1 = n0 + 2^(nq-is)), (C_n0, C_n1) <- U (C_n0, C_n1), in place.
+ * U: host, 2 x 2.  The paper's psi_f = Op1[U, is, psi_0].
+ */
+int qcw_op1(const qcw_c64 *U, int is, qcw_c64 *psi, int nq, void *stream);
+
+/*
+ * Op2 (§3b, Eqs. twoopA and resmat2): for each of the 2^nq / 4 amplitude
+ * quartets (n00, n01, n10, n11), with n01 = n00 + 2^(nq-is2) and
+ * n10 = n00 + 2^(nq-is1), the quartet is multiplied by the 4 x 4 V, in place.
+ */
+int qcw_op2(const qcw_c64 *V, int is1, int is2, qcw_c64 *psi, int nq,
+            void *stream);
+
+/*
+ * Op3 (§3c and §4c): the 8 x 8 W on each of the 2^nq / 8 amplitude octets of
+ * qubits is1, is2, is3 (local index 4 q_is1 + 2 q_is2 + q_is3), in place.
+ */
+int qcw_op3(const qcw_c64 *W, int is1, int is2, int is3, qcw_c64 *psi, int nq,
+            void *stream);
+
+/* Op_k for k = 1, 2, 3 with targets[0..k-1]; in place. */
+int qcw_opk(int k, const int *targets, const qcw_c64 *U, qcw_c64 *psi, int nq,
+            void *stream);
+
+/*
+ * Functional form psi_out = Op_k(psi_in), as the paper's commands return a
+ * new state (§3a footnote).  psi_in == psi_out is allowed (in place); any
+ * other overlap of the two buffers is rejected.
+ */
+int qcw_opk_to(int k, const int *targets, const qcw_c64 *U,
+               const qcw_c64 *psi_in, qcw_c64 *psi_out, int nq, void *stream);
+
+/* OmegaALL[U, psi] (§4a): the same 2 x 2 U on every qubit, qubit 1 first. */
+int qcw_omega_all(const qcw_c64 *U, qcw_c64 *psi, int nq, void *stream);
+
+/*
+ * A gate of a circuit: k targets q[0..k-1] (1-based; unused entries
+ * ignored) and the offset, in qcw_c64 elements, of its m x m matrix inside
+ * the circuit's `mats` array.
+ */
+typedef struct {
+  int32_t k;
+  int32_t q[3];
+  int64_t mat;
+} qcw_gate;
+
+/*
+ * A circuit: the gates applied in list order, i.e. the operator product read
+ * right to left (CNOT_12 H_1 |00> applies H_1 first; §5).  Plain form: one
+ * sweep per gate on `stream`.  gates, mats: host arrays; nmats is the length
+ * of mats in qcw_c64 elements (every gate's matrix must lie inside it).
+ */
+int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                const qcw_c64 *mats, int64_t nmats, void *stream);
+
+/*
+ * Pick_k as computed by the device (§4a-§4c): writes (2^nq / m) * m labels to
+ * the HOST array out_host, group after group in ascending base label, the
+ * members of a group in ascending local index.  nq <= 26.  Synchronous.
+ * For testing the device's index arithmetic.
+ */
+int qcw_debug_pick_device(int nq, int k, const int *targets, uint64_t *out_host);
+
+/*
+ * Kernel timing.  While enabled, every kernel the library launches is
+ * bracketed by HIP events recorded on the stream it is launched on.
+ * qcw_timing_read synchronises those events and returns, for one kernel
+ * family, the number of launches and their summed duration in milliseconds
+ * since the last reset.  Families: QCW_KERNEL_SWEEP1..3 (one-gate sweeps of
+ * k = 1, 2, 3).  Not thread-safe against concurrent launches.
+ */
+enum {
+  QCW_KERNEL_SWEEP1 = 1,
+  QCW_KERNEL_SWEEP2 = 2,
+  QCW_KERNEL_SWEEP3 = 3,
+  QCW_KERNEL_COUNT = 8
+};
+int qcw_timing_enable(int on);
+int qcw_timing_reset(void);
+int qcw_timing_read(int kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCW_H */

@@ -1,0 +1,213 @@
+"""ctypes binding of libqcw.so: argument marshalling only.
+
+Every function here has the name and argument order of its C counterpart in
+include/qcw.h.  States are torch complex128 tensors on the GPU (torch supplies
+device memory and the current stream); matrices and gate lists are numpy
+arrays on the host.  Nothing is computed here: if the library is missing,
+importing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqcw.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1101_1785_amd.build`")
+
+_L = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int
+_i64 = ctypes.c_int64
+
+QCW_OK, QCW_EINVAL, QCW_ENOMEM, QCW_EHIP, QCW_EAGAIN = 0, -1, -2, -3, -4
+QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3 = 1, 2, 3
+
+
+class QcwError(RuntimeError):
+    def __init__(self, code: int, fn: str):
+        self.code = code
+        msg = _L.qcw_last_error().decode(errors="replace")
+        super().__init__(f"{fn}: {_L.qcw_strerror(code).decode()} ({code}): {msg}")
+
+
+class qcw_gate(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("q", ctypes.c_int32 * 3), ("mat", ctypes.c_int64)]
+
+
+GATE_DTYPE = np.dtype([("k", np.int32), ("q", np.int32, (3,)), ("mat", np.int64)], align=True)
+assert GATE_DTYPE.itemsize == ctypes.sizeof(qcw_gate) == 24
+
+_SIGS = {
+    "qcw_strerror": ([_i32], ctypes.c_char_p),
+    "qcw_last_error": ([], ctypes.c_char_p),
+    "qcw_version": ([], _i32),
+    "qcw_op1": ([_P, _i32, _P, _i32, _P], _i32),
+    "qcw_op2": ([_P, _i32, _i32, _P, _i32, _P], _i32),
+    "qcw_op3": ([_P, _i32, _i32, _i32, _P, _i32, _P], _i32),
+    "qcw_opk": ([_i32, _P, _P, _P, _i32, _P], _i32),
+    "qcw_opk_to": ([_i32, _P, _P, _P, _P, _i32, _P], _i32),
+    "qcw_omega_all": ([_P, _P, _i32, _P], _i32),
+    "qcw_circuit": ([_P, _i32, _P, _i32, _P, _i64, _P], _i32),
+    "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),
+    "qcw_timing_enable": ([_i32], _i32),
+    "qcw_timing_reset": ([], _i32),
+    "qcw_timing_read": ([_i32, _P, _P], _i32),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_L, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def lib():
+    return _L
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+# ------------------------------------------------------------------ marshalling
+def _check(rc: int, fn: str) -> None:
+    if rc != QCW_OK:
+        raise QcwError(rc, fn)
+
+
+def _mat(U, k: int | None = None) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    if U.ndim != 2 or U.shape[0] != U.shape[1]:
+        raise ValueError("gate matrix must be square")
+    if k is not None and U.shape[0] != (1 << k):
+        raise ValueError(f"gate matrix must be {1 << k} x {1 << k}")
+    return U
+
+
+def _hptr(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+def _dptr(t):
+    """Device pointer of a torch complex128 GPU tensor (contiguous)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError("state must be a torch.complex128 tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("state tensor must be contiguous")
+    return _P(t.data_ptr())
+
+
+def _nq_of(t, nq):
+    if nq is not None:
+        return int(nq)
+    n = t.numel()
+    if n <= 0 or n & (n - 1):
+        raise ValueError("state length must be a power of two")
+    return n.bit_length() - 1
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return _P(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _P(stream)
+    return _P(stream.cuda_stream)
+
+
+def _targets(targets) -> np.ndarray:
+    t = np.zeros(3, dtype=np.int32)
+    t[:len(targets)] = targets
+    return t
+
+
+# ------------------------------------------------------------------ entry points
+def qcw_op1(U, is_, psi, nq=None, stream=None):
+    U = _mat(U, 1)
+    _check(_L.qcw_op1(_hptr(U), int(is_), _dptr(psi), _nq_of(psi, nq), _stream(stream)), "qcw_op1")
+
+
+def qcw_op2(V, is1, is2, psi, nq=None, stream=None):
+    V = _mat(V, 2)
+    _check(_L.qcw_op2(_hptr(V), int(is1), int(is2), _dptr(psi), _nq_of(psi, nq),
+                      _stream(stream)), "qcw_op2")
+
+
+def qcw_op3(W, is1, is2, is3, psi, nq=None, stream=None):
+    W = _mat(W, 3)
+    _check(_L.qcw_op3(_hptr(W), int(is1), int(is2), int(is3), _dptr(psi), _nq_of(psi, nq),
+                      _stream(stream)), "qcw_op3")
+
+
+def qcw_opk(k, targets, U, psi, nq=None, stream=None):
+    U = _mat(U, k)
+    t = _targets(targets)
+    _check(_L.qcw_opk(int(k), _hptr(t), _hptr(U), _dptr(psi), _nq_of(psi, nq), _stream(stream)),
+           "qcw_opk")
+
+
+def qcw_opk_to(k, targets, U, psi_in, psi_out, nq=None, stream=None):
+    U = _mat(U, k)
+    t = _targets(targets)
+    _check(_L.qcw_opk_to(int(k), _hptr(t), _hptr(U), _dptr(psi_in), _dptr(psi_out),
+                         _nq_of(psi_in, nq), _stream(stream)), "qcw_opk_to")
+
+
+def qcw_omega_all(U, psi, nq=None, stream=None):
+    U = _mat(U, 1)
+    _check(_L.qcw_omega_all(_hptr(U), _dptr(psi), _nq_of(psi, nq), _stream(stream)),
+           "qcw_omega_all")
+
+
+def pack_circuit(circ):
+    """Circuit (qcw_inputs.Circuit) -> (gates structured array, mats complex array)."""
+    G = len(circ)
+    gates = np.zeros(G, dtype=GATE_DTYPE)
+    mats = []
+    off = 0
+    for g, (k, t, U) in enumerate(zip(circ.ks, circ.targets, circ.mats)):
+        gates[g]["k"] = k
+        gates[g]["q"][:k] = t
+        gates[g]["mat"] = off
+        mats.append(np.ascontiguousarray(U, dtype=np.complex128).reshape(-1))
+        off += U.size
+    M = np.concatenate(mats) if mats else np.zeros(1, np.complex128)
+    return gates, np.ascontiguousarray(M)
+
+
+def qcw_circuit(psi, nq, gates, ngates, mats, nmats, stream=None):
+    _check(_L.qcw_circuit(_dptr(psi), int(nq), _hptr(gates), int(ngates), _hptr(mats),
+                          int(nmats), _stream(stream)), "qcw_circuit")
+
+
+def circuit(psi, circ, stream=None):
+    """Apply a qcw_inputs.Circuit to psi in place with qcw_circuit."""
+    gates, mats = pack_circuit(circ)
+    qcw_circuit(psi, circ.nq, gates, len(circ), mats, mats.size, stream)
+
+
+def qcw_debug_pick_device(nq, targets):
+    k = len(targets)
+    out = np.empty(1 << nq, dtype=np.uint64)
+    t = _targets(targets)
+    _check(_L.qcw_debug_pick_device(int(nq), int(k), _hptr(t), _hptr(out)), "qcw_debug_pick_device")
+    return out.reshape(-1, 1 << k)
+
+
+def qcw_timing_enable(on: bool):
+    _check(_L.qcw_timing_enable(1 if on else 0), "qcw_timing_enable")
+
+
+def qcw_timing_reset():
+    _check(_L.qcw_timing_reset(), "qcw_timing_reset")
+
+
+def qcw_timing_read(kernel: int):
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(_L.qcw_timing_read(int(kernel), ctypes.byref(n), ctypes.byref(ms)), "qcw_timing_read")
+    return int(n.value), float(ms.value)

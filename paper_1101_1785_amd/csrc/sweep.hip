@@ -1,0 +1,155 @@
+// One-gate sweep: QCWAVE's Op1 / Op2 / Op3 (§3a-§3c) on a state in HBM.
+//
+// Each thread takes GPT groups (pairs, quartets or octets).  Group j's base
+// label comes from inserting zero bits at the sorted target positions; member
+// r adds off[r] (the strides of the targets whose value in r is 1).  Consecutive
+// lanes take consecutive j, so for every member the wavefront's 64 loads cover
+// contiguous 16-byte amplitudes whenever the lowest target bit is >= 6, and
+// whole cache lines across the members otherwise.  All loads of a thread are
+// issued before any arithmetic, so a thread keeps GPT * m loads in flight, and
+// each amplitude is read once and written once: 32 bytes of HBM traffic per
+// amplitude per gate.  The m x m matrix travels in the kernel arguments and is
+// read through the scalar cache (wave-uniform), never from a per-lane load.
+#include <hip/hip_runtime.h>
+
+#include "qcw_device.h"
+#include "qcw_host.h"
+
+namespace qcw {
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ double2 ld2(const double2 *p) {
+  v2d v;
+  if (NT)
+    v = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
+  else
+    v = *reinterpret_cast<const v2d *>(p);
+  return make_double2(v.x, v.y);
+}
+
+template <bool NT>
+__device__ __forceinline__ void st2(double2 *p, double2 a) {
+  v2d v = {a.x, a.y};
+  if (NT)
+    __builtin_nontemporal_store(v, reinterpret_cast<v2d *>(p));
+  else
+    *reinterpret_cast<v2d *>(p) = v;
+}
+
+template <int K>
+struct MatArg {
+  double2 u[(1 << K) * (1 << K)];
+};
+
+template <typename I>
+struct SweepArg {
+  I ngroups;
+  I off[8];
+  int sb0, sb1, sb2;
+};
+
+constexpr int kSweepBlock = 256;
+
+template <int K, int GPT, typename I, bool NT>
+__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const double2 *in, double2 *out,
+                                                            SweepArg<I> a, MatArg<K> U) {
+  constexpr int M = 1 << K;
+  double2 x[GPT][M];
+  I base[GPT];
+  const I j0 = (I)blockIdx.x * (I)(GPT * kSweepBlock) + (I)threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < GPT; ++i) {
+    const I j = j0 + (I)(i * kSweepBlock);
+    base[i] = insert_zeros<K, I>(j, a.sb0, a.sb1, a.sb2);
+    if (j < a.ngroups) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) x[i][r] = ld2<NT>(in + (base[i] + a.off[r]));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < GPT; ++i) {
+    const I j = j0 + (I)(i * kSweepBlock);
+    if (j < a.ngroups) {
+      double2 y[M];
+      group_matvec<M>(x[i], y, [&](int r, int c) { return U.u[r * M + c]; });
+#pragma unroll
+      for (int r = 0; r < M; ++r) st2<NT>(out + (base[i] + a.off[r]), y[r]);
+    }
+  }
+}
+
+// Pick_k labels as the sweep computes them (test support).
+template <int K>
+__global__ void pick_kernel(uint64_t *labels, SweepArg<uint64_t> a) {
+  constexpr int M = 1 << K;
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.ngroups) return;
+  const uint64_t base = insert_zeros<K, uint64_t>(j, a.sb0, a.sb1, a.sb2);
+#pragma unroll
+  for (int r = 0; r < M; ++r) labels[j * M + r] = base + a.off[r];
+}
+
+template <typename I>
+static SweepArg<I> sweep_arg(const Geom &g) {
+  SweepArg<I> a{};
+  a.ngroups = (I)((uint64_t)1 << (g.nq - g.k));
+  for (int r = 0; r < (1 << g.k); ++r) a.off[r] = (I)g.off[r];
+  a.sb0 = g.sb[0];
+  a.sb1 = g.sb[1];
+  a.sb2 = g.sb[2];
+  return a;
+}
+
+template <int K, int GPT, typename I>
+static int launch_k(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *out,
+                    hipStream_t s) {
+  MatArg<K> m;
+  for (int i = 0; i < (1 << K) * (1 << K); ++i) m.u[i] = make_double2(U[i].re, U[i].im);
+  SweepArg<I> a = sweep_arg<I>(g);
+  const uint64_t per_block = (uint64_t)GPT * kSweepBlock;
+  const uint64_t blocks = ((uint64_t)a.ngroups + per_block - 1) / per_block;
+  if (blocks > 0x7fffffffULL) return fail(QCW_EINVAL, "state too large for one launch");
+  TimedLaunch t(K, s);
+  hipLaunchKernelGGL((sweep_kernel<K, GPT, I, false>), dim3((unsigned)blocks), dim3(kSweepBlock),
+                     0, s, reinterpret_cast<const double2 *>(in),
+                     reinterpret_cast<double2 *>(out), a, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(QCW_EHIP, "sweep launch: %s", hipGetErrorString(e));
+  return QCW_OK;
+}
+
+int launch_sweep(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *out,
+                 hipStream_t s) {
+  // 32-bit labels while every label and shift fits (nq <= 31), 64-bit above.
+  const bool small = g.nq <= 31;
+  switch (g.k) {
+    case 1:
+      return small ? launch_k<1, 4, uint32_t>(g, U, in, out, s)
+                   : launch_k<1, 4, uint64_t>(g, U, in, out, s);
+    case 2:
+      return small ? launch_k<2, 2, uint32_t>(g, U, in, out, s)
+                   : launch_k<2, 2, uint64_t>(g, U, in, out, s);
+    case 3:
+      return small ? launch_k<3, 1, uint32_t>(g, U, in, out, s)
+                   : launch_k<3, 1, uint64_t>(g, U, in, out, s);
+  }
+  return fail(QCW_EINVAL, "k must be 1, 2 or 3");
+}
+
+int launch_pick(const Geom &g, uint64_t *labels_dev, hipStream_t s) {
+  SweepArg<uint64_t> a = sweep_arg<uint64_t>(g);
+  const unsigned blocks = (unsigned)((a.ngroups + 255) / 256);
+  switch (g.k) {
+    case 1: hipLaunchKernelGGL(pick_kernel<1>, dim3(blocks), dim3(256), 0, s, labels_dev, a); break;
+    case 2: hipLaunchKernelGGL(pick_kernel<2>, dim3(blocks), dim3(256), 0, s, labels_dev, a); break;
+    case 3: hipLaunchKernelGGL(pick_kernel<3>, dim3(blocks), dim3(256), 0, s, labels_dev, a); break;
+    default: return fail(QCW_EINVAL, "k must be 1, 2 or 3");
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(QCW_EHIP, "pick launch: %s", hipGetErrorString(e));
+  return QCW_OK;
+}
+
+}  // namespace qcw

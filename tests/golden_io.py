@@ -20,6 +20,7 @@ class Golden:
         self.circ = None
         self.expect = {}
         self.zero_elsewhere = False
+        self.exact_zeros = False
         with open(path) as f:
             for line in f:
                 line = line.split("#", 1)[0].strip()
@@ -38,6 +39,8 @@ class Golden:
                     self.expect[int(w[1])] = complex(float(w[2]), float(w[3]))
                 elif w[0] == "zero_elsewhere":
                     self.zero_elsewhere = True
+                elif w[0] == "exact_zeros":
+                    self.zero_elsewhere = self.exact_zeros = True
                 else:
                     raise ValueError(f"{path}: bad directive {w[0]}")
 
@@ -49,7 +52,10 @@ class Golden:
         if self.zero_elsewhere:
             mask = np.ones(psi.size, bool)
             mask[list(self.expect)] = False
-            assert np.all(psi[mask] == 0), (self.name, np.nonzero(psi[mask]))
+            if self.exact_zeros:
+                assert np.all(psi[mask] == 0), (self.name, np.nonzero(psi[mask]))
+            else:
+                assert np.all(np.abs(psi[mask]) <= tol), (self.name, np.abs(psi[mask]).max())
 
 
 def all_golden():
