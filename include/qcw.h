@@ -136,17 +136,75 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
 int qcw_debug_pick_device(int nq, int k, const int *targets, uint64_t *out_host);
 
 /*
+ * Batched form: many independent (state, circuit) instances -- the paper's
+ * independent multiverse paths, each evolved by its own gate sequence (§5,
+ * "The multiverse approach") -- advanced in ONE persistent launch.
+ *
+ * Instance i has nq qubits, its state at states + state_off (2^nq qcw_c64,
+ * in the device buffer `states` of nstates elements, caller-owned) and its
+ * circuit gates[gate_off .. gate_off + ngates - 1] (host array of ngates_total
+ * entries; each gate's matrix at mats + gate.mat, host array of nmats).
+ * Instances of up to 11 qubits keep their state in one wavefront's LDS for the
+ * whole circuit; larger ones run as plain sweeps in the same graph.  Instance
+ * states must not overlap.  A gate row may be shared by instances of equal nq.
+ *
+ * qcw_batch_create validates everything, copies gates and matrices to the
+ * device, chooses each instance's tile shape from `tune_table` (a file written
+ * by qcw_batch_autotune; NULL = built-in defaults; a table written for another
+ * GPU architecture is rejected), and captures the launch in a hipGraph on
+ * `stream` (NULL: a private stream).  qcw_batch_run replays the graph on
+ * `stream`: every instance's state advances by its whole circuit, in place.
+ * The handle owns its device copies and the graph; qcw_batch_destroy frees
+ * them (never the caller's states).  Results equal, bit for bit, those of
+ * qcw_circuit applied to each instance alone.
+ */
+typedef struct {
+  int32_t nq;
+  int32_t ngates;
+  int64_t state_off; /* in qcw_c64 elements */
+  int64_t gate_off;  /* index of the first gate */
+} qcw_instance;
+
+typedef struct qcw_batch qcw_batch;
+
+int qcw_batch_create(qcw_batch **out, const qcw_instance *inst, int n,
+                     const qcw_gate *gates, int64_t ngates_total, const qcw_c64 *mats,
+                     int64_t nmats, qcw_c64 *states, int64_t nstates,
+                     const char *tune_table, void *stream);
+int qcw_batch_run(qcw_batch *b, void *stream);
+/* The same work enqueued directly (no graph), e.g. inside a caller's capture. */
+int qcw_batch_run_eager(qcw_batch *b, void *stream);
+/* Launch shape: tile-shape variant used for instances of nq qubits, grid
+ * blocks and dynamic LDS bytes per block.  Any output pointer may be NULL. */
+int qcw_batch_info(const qcw_batch *b, int nq, int *variant, int *blocks, int *lds_bytes);
+int qcw_batch_destroy(qcw_batch *b);
+/* Name of a tile-shape variant ("amp8_sgpr", ...), as used in tune tables. */
+const char *qcw_batch_variant_name(int variant);
+
+/*
+ * Autotuner: for every qubit count in [nq_lo, nq_hi] (1 <= nq_lo <= nq_hi <=
+ * 11) times one persistent launch over `ninst` synthetic instances of that
+ * size (random circuits of gates_per_qubit * nq dense unitaries), once per
+ * tile-shape variant, and writes the fastest variant per size to out_path.
+ * Synchronises `stream`.
+ */
+int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, int ninst,
+                       int gates_per_qubit, void *stream);
+
+/*
  * Kernel timing.  While enabled, every kernel the library launches is
  * bracketed by HIP events recorded on the stream it is launched on.
  * qcw_timing_read synchronises those events and returns, for one kernel
  * family, the number of launches and their summed duration in milliseconds
  * since the last reset.  Families: QCW_KERNEL_SWEEP1..3 (one-gate sweeps of
- * k = 1, 2, 3).  Not thread-safe against concurrent launches.
+ * k = 1, 2, 3), QCW_KERNEL_BATCH (batch executions).  Launches recorded
+ * into a hipGraph are not timed individually.
  */
 enum {
   QCW_KERNEL_SWEEP1 = 1,
   QCW_KERNEL_SWEEP2 = 2,
   QCW_KERNEL_SWEEP3 = 3,
+  QCW_KERNEL_BATCH = 4, /* one batch execution (qcw_batch_run: the graph) */
   QCW_KERNEL_COUNT = 8
 };
 int qcw_timing_enable(int on);

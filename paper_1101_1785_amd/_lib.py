@@ -25,7 +25,7 @@ _i32 = ctypes.c_int
 _i64 = ctypes.c_int64
 
 QCW_OK, QCW_EINVAL, QCW_ENOMEM, QCW_EHIP, QCW_EAGAIN = 0, -1, -2, -3, -4
-QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3 = 1, 2, 3
+QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3, QCW_KERNEL_BATCH = 1, 2, 3, 4
 
 
 class QcwError(RuntimeError):
@@ -41,6 +41,9 @@ class qcw_gate(ctypes.Structure):
 
 GATE_DTYPE = np.dtype([("k", np.int32), ("q", np.int32, (3,)), ("mat", np.int64)], align=True)
 assert GATE_DTYPE.itemsize == ctypes.sizeof(qcw_gate) == 24
+INSTANCE_DTYPE = np.dtype([("nq", np.int32), ("ngates", np.int32), ("state_off", np.int64),
+                           ("gate_off", np.int64)], align=True)
+assert INSTANCE_DTYPE.itemsize == 24
 
 _SIGS = {
     "qcw_strerror": ([_i32], ctypes.c_char_p),
@@ -54,6 +57,13 @@ _SIGS = {
     "qcw_omega_all": ([_P, _P, _i32, _P], _i32),
     "qcw_circuit": ([_P, _i32, _P, _i32, _P, _i64, _P], _i32),
     "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),
+    "qcw_batch_create": ([_P, _P, _i32, _P, _i64, _P, _i64, _P, _i64, ctypes.c_char_p, _P], _i32),
+    "qcw_batch_run": ([_P, _P], _i32),
+    "qcw_batch_run_eager": ([_P, _P], _i32),
+    "qcw_batch_info": ([_P, _i32, _P, _P, _P], _i32),
+    "qcw_batch_destroy": ([_P], _i32),
+    "qcw_batch_variant_name": ([_i32], ctypes.c_char_p),
+    "qcw_batch_autotune": ([ctypes.c_char_p, _i32, _i32, _i32, _i32, _P], _i32),
     "qcw_timing_enable": ([_i32], _i32),
     "qcw_timing_reset": ([], _i32),
     "qcw_timing_read": ([_i32, _P, _P], _i32),
@@ -211,3 +221,99 @@ def qcw_timing_read(kernel: int):
     ms = ctypes.c_double(0.0)
     _check(_L.qcw_timing_read(int(kernel), ctypes.byref(n), ctypes.byref(ms)), "qcw_timing_read")
     return int(n.value), float(ms.value)
+
+
+# ------------------------------------------------------------------ batched form
+def pack_batch(instances):
+    """[(nq, Circuit), ...] -> (instance table, gates, mats, total state length).
+
+    States are packed back to back in list order."""
+    n = len(instances)
+    inst = np.zeros(n, dtype=INSTANCE_DTYPE)
+    gate_rows, mat_chunks = [], []
+    soff = goff = moff = 0
+    for i, (nq, circ) in enumerate(instances):
+        g, m = pack_circuit(circ)
+        g = g.copy()
+        g["mat"] += moff
+        inst[i] = (nq, len(circ), soff, goff)
+        gate_rows.append(g)
+        if len(circ):
+            mat_chunks.append(m)
+            moff += m.size
+        soff += 1 << nq
+        goff += len(circ)
+    gates = np.concatenate(gate_rows) if gate_rows else np.zeros(0, GATE_DTYPE)
+    mats = np.concatenate(mat_chunks) if mat_chunks else np.zeros(1, np.complex128)
+    return inst, np.ascontiguousarray(gates), np.ascontiguousarray(mats), soff
+
+
+def qcw_batch_create(inst, n, gates, ngates, mats, nmats, states, nstates, tune_table=None,
+                     stream=None):
+    h = _P()
+    tt = tune_table.encode() if tune_table else None
+    _check(_L.qcw_batch_create(ctypes.byref(h), _hptr(inst), int(n), _hptr(gates), int(ngates),
+                               _hptr(mats), int(nmats), _dptr(states), int(nstates), tt,
+                               _stream(stream)), "qcw_batch_create")
+    return h
+
+
+def qcw_batch_run(h, stream=None):
+    _check(_L.qcw_batch_run(h, _stream(stream)), "qcw_batch_run")
+
+
+def qcw_batch_run_eager(h, stream=None):
+    _check(_L.qcw_batch_run_eager(h, _stream(stream)), "qcw_batch_run_eager")
+
+
+def qcw_batch_info(h, nq):
+    v, b, l = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    _check(_L.qcw_batch_info(h, int(nq), ctypes.byref(v), ctypes.byref(b), ctypes.byref(l)),
+           "qcw_batch_info")
+    return v.value, b.value, l.value
+
+
+def qcw_batch_destroy(h):
+    _check(_L.qcw_batch_destroy(h), "qcw_batch_destroy")
+
+
+def qcw_batch_variant_name(v):
+    return _L.qcw_batch_variant_name(int(v)).decode()
+
+
+def qcw_batch_autotune(out_path, nq_lo, nq_hi, ninst, gates_per_qubit=4, stream=None):
+    _check(_L.qcw_batch_autotune(out_path.encode(), int(nq_lo), int(nq_hi), int(ninst),
+                                 int(gates_per_qubit), _stream(stream)), "qcw_batch_autotune")
+
+
+class Batch:
+    """Owns a qcw_batch handle over a packed device state tensor."""
+
+    def __init__(self, instances, states, tune_table=None, stream=None):
+        self.inst, self.gates, self.mats, total = pack_batch(instances)
+        if states.numel() < total:
+            raise ValueError("states tensor shorter than the packed instances")
+        self.states = states
+        self.h = qcw_batch_create(self.inst, len(self.inst), self.gates, self.gates.size,
+                                  self.mats, self.mats.size, states, states.numel(),
+                                  tune_table, stream)
+
+    def run(self, stream=None):
+        qcw_batch_run(self.h, stream)
+
+    def run_eager(self, stream=None):
+        qcw_batch_run_eager(self.h, stream)
+
+    def info(self, nq):
+        return qcw_batch_info(self.h, nq)
+
+    def close(self):
+        if self.h:
+            qcw_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,81 @@
+// Internal types of the batched (persistent, LDS-resident) gate path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qcw_host.h"
+
+namespace qcw {
+
+constexpr int kBatchBlock = 256;     // at most 4 wavefronts, each on its own instance
+constexpr int kBatchMaxNq = 12;      // largest instance kept in one wavefront's LDS
+constexpr int kKernelBatch = 4;      // timing family of the batch kernel
+
+// Tile-shape variants (see batch.hip).
+enum BatchVariant : int32_t {
+  kVarAmp4Sgpr = 0,
+  kVarAmp8Sgpr = 1,
+  kVarAmp16Sgpr = 2,
+  kVarAmp4Lds = 3,
+  kVarAmp8Lds = 4,
+  kVarCount = 5
+};
+const char *variant_name(int v);
+int variant_from_name(const char *s);
+
+struct BInst {  // device copy of qcw_instance
+  int32_t nq;
+  int32_t ngates;
+  int64_t state_off;
+  int64_t gate_off;
+};
+
+struct alignas(16) BGate {  // gate with its geometry precomputed on the host
+  int32_t k;
+  int32_t sb0, sb1, sb2;    // target bits sorted ascending
+  uint32_t off[8];          // member offsets, local index order
+  int64_t mat_off;          // in complex elements
+  int64_t pad;
+};
+static_assert(sizeof(BGate) == 64, "BGate layout");
+
+struct BItem {
+  int32_t inst;     // instance index
+  int32_t variant;  // BatchVariant
+  int32_t g_begin;  // gate range of this launch
+  int32_t g_end;
+};
+
+struct BatchLaunch {
+  const BItem *items;
+  int nitems;
+  const BInst *inst;
+  const BGate *gates;
+  const double2 *mats;
+  double2 *states;
+  int *counter;
+  int wave_amps;
+  size_t lds_bytes;
+  int threads;
+  unsigned blocks;
+};
+
+int launch_batch(const BatchLaunch &L, hipStream_t s);
+int batch_kernel_occupancy(size_t lds_bytes, int threads, int *blocks_per_cu);
+
+// Per-qubit-count variant choice, loaded from a tune table or the defaults.
+struct TuneTable {
+  int variant[kBatchMaxNq + 1];
+  bool from_file = false;
+};
+void tune_defaults(TuneTable *t);
+int tune_load(const char *path, TuneTable *t);
+
+// Geometry of a gate for the batch kernel; validates like make_geom.
+int make_bgate(int nq, const qcw_gate &g, int64_t nmats, BGate *out);
+
+// Sizes one persistent launch for instances of at most max_nq qubits.
+int plan_batch_launch(int max_nq, int nitems, BatchLaunch *L);
+
+}  // namespace qcw

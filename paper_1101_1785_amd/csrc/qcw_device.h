@@ -32,6 +32,20 @@ __device__ __forceinline__ void group_matvec(const double2 (&x)[M], double2 (&y)
   }
 }
 
+// The same products as group_matvec, each output row handed to `put(r, y_r)`
+// as soon as it is complete (fewer live registers; inputs must already be
+// loaded, which makes in-place updates safe).
+template <int M, typename MatFn, typename PutFn>
+__device__ __forceinline__ void group_matvec_put(const double2 (&x)[M], MatFn u, PutFn put) {
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc = cmad(acc, u(r, c), x[c]);
+    put(r, acc);
+  }
+}
+
 // Group index j -> lowest label of its group: a zero bit is inserted at each
 // target bit position, taken in ascending order (sb0 < sb1 < sb2).
 template <int K, typename I>

@@ -1,0 +1,202 @@
+"""GPU parity of the batched form (one persistent launch in a hipGraph).
+
+Every instance must equal, bit for bit, the plain path applied to that
+instance alone (both run the same group arithmetic in the same FMA order),
+and must match the oracle within the FP64 tolerance of the plain path.
+Graph replays are checked one by one with eager work in between.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import qcw_inputs as qi
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_1785_amd import _lib
+    return _lib
+
+
+def _pack_states(instances):
+    return np.concatenate([s for (_, s, _) in instances])
+
+
+def _plain(L, instances):
+    """Each instance alone through qcw_circuit."""
+    outs = []
+    for nq, psi0, c in instances:
+        psi = torch.from_numpy(psi0).to("cuda")
+        L.circuit(psi, c)
+        outs.append(psi)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+def _split(flat, instances):
+    out, off = [], 0
+    for nq, _, _ in instances:
+        out.append(flat[off:off + (1 << nq)])
+        off += 1 << nq
+    return out
+
+
+def _check_vs_oracle(outs, instances):
+    refs = oracle.circuit_batch(instances)
+    for o, r, (nq, _, c) in zip(outs, refs, instances):
+        n = np.linalg.norm(r)
+        assert np.linalg.norm(o - r) <= TOL * max(1, len(c) / 64) * n
+        assert np.max(np.abs(o - r)) <= TOL * n
+
+
+@pytest.mark.parametrize("lo,hi,count", [(3, 7, 300), (1, 11, 120), (9, 9, 64)])
+def test_batch_equals_plain_and_oracle(L, lo, hi, count):
+    print(f"[gpu] batch nq {lo}..{hi} x {count}", flush=True)
+    inst = qi.batch(2, count, lo, hi)
+    states = torch.from_numpy(_pack_states(inst)).to("cuda")
+    b = L.Batch([(nq, c) for nq, _, c in inst], states)
+    b.run()
+    torch.cuda.synchronize()
+    outs = _split(states.cpu().numpy(), inst)
+    plain = _plain(L, inst)
+    for i, (o, p) in enumerate(zip(outs, plain)):
+        assert np.array_equal(o, p), i
+    _check_vs_oracle(outs, inst)
+    b.close()
+
+
+def test_every_variant_bit_identical(L, tmp_path):
+    """Each tile shape gives the same bits (a table forcing one variant for all sizes)."""
+    inst = qi.batch(5, 80, 2, 9)
+    plain = _plain(L, inst)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    for v in range(5):
+        name = L.qcw_batch_variant_name(v)
+        table = tmp_path / f"t{v}.txt"
+        table.write_text(f"arch {arch}\n" + "".join(f"nq {q} variant {name}\n" for q in range(1, 12)))
+        states = torch.from_numpy(_pack_states(inst)).to("cuda")
+        b = L.Batch([(nq, c) for nq, _, c in inst], states, tune_table=str(table))
+        assert L.qcw_batch_variant_name(b.info(5)[0]) == name
+        b.run()
+        torch.cuda.synchronize()
+        for o, p in zip(_split(states.cpu().numpy(), inst), plain):
+            assert np.array_equal(o, p), name
+        b.close()
+
+
+def test_graph_replays_with_eager_work_between(L):
+    inst = qi.batch(6, 50, 3, 8)
+    states = torch.from_numpy(_pack_states(inst)).to("cuda")
+    b = L.Batch([(nq, c) for nq, _, c in inst], states)
+    expect = [s.copy() for (_, s, _) in inst]
+    for rep in range(3):
+        b.run()
+        torch.cuda.synchronize()
+        scratch = torch.randn(1 << 16, device="cuda").sum().item()   # unrelated eager work
+        assert np.isfinite(scratch)
+        got = _split(states.cpu().numpy(), inst)
+        nxt = []
+        for (nq, _, c), e in zip(inst, expect):
+            psi = torch.from_numpy(e).to("cuda")
+            L.circuit(psi, c)
+            nxt.append(psi.cpu().numpy())
+        expect = nxt
+        for i, (g, e) in enumerate(zip(got, expect)):
+            assert np.array_equal(g, e), (rep, i)
+    b.run_eager()
+    torch.cuda.synchronize()
+    got = _split(states.cpu().numpy(), inst)
+    for (nq, _, c), e, g in zip(inst, expect, got):
+        psi = torch.from_numpy(e).to("cuda")
+        L.circuit(psi, c)
+        assert np.array_equal(psi.cpu().numpy(), g)
+    b.close()
+
+
+def test_oversize_instances_run_as_sweeps(L):
+    """Instances above 11 qubits run as plain sweeps inside the same graph."""
+    inst = [(12, qi.state(7, 12, 1), qi.circuit(7, 12, 10, 1)),
+            (4, qi.state(7, 4, 2), qi.circuit(7, 4, 16, 2)),
+            (13, qi.state(7, 13, 3), qi.circuit(7, 13, 6, 3))]
+    states = torch.from_numpy(_pack_states(inst)).to("cuda")
+    b = L.Batch([(nq, c) for nq, _, c in inst], states)
+    b.run()
+    torch.cuda.synchronize()
+    outs = _split(states.cpu().numpy(), inst)
+    for o, p in zip(outs, _plain(L, inst)):
+        assert np.array_equal(o, p)
+    _check_vs_oracle(outs, inst)
+    b.close()
+
+
+def test_empty_and_gateless(L):
+    states = torch.zeros(8, dtype=torch.complex128, device="cuda")
+    b = L.Batch([], states)
+    b.run()
+    b.close()
+    psi0 = qi.state(1, 3)
+    states = torch.from_numpy(psi0.copy()).to("cuda")
+    b = L.Batch([(3, qi.Circuit(3))], states)
+    b.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(states.cpu().numpy(), psi0)
+    b.close()
+
+
+def test_batch_validation(L):
+    c = qi.circuit(0, 4, 4)
+    states = torch.zeros(16 * 3, dtype=torch.complex128, device="cuda")
+    inst, gates, mats, _ = L.pack_batch([(4, c), (4, c)])
+    inst[1]["state_off"] = 8                                         # overlaps instance 0
+    with pytest.raises(L.QcwError, match="overlap"):
+        L.qcw_batch_create(inst, 2, gates, gates.size, mats, mats.size, states, states.numel())
+    inst[1]["state_off"] = 40                                        # runs past the buffer
+    with pytest.raises(L.QcwError, match="outside the states"):
+        L.qcw_batch_create(inst, 2, gates, gates.size, mats, mats.size, states, states.numel())
+    inst[1]["state_off"] = 16
+    bad = gates.copy()
+    bad[2]["q"][0] = 9
+    with pytest.raises(L.QcwError, match="instance 0 gate 2"):
+        L.qcw_batch_create(inst, 2, bad, bad.size, mats, mats.size, states, states.numel())
+
+
+def test_tune_table_arch_checked(L, tmp_path):
+    t = tmp_path / "other.txt"
+    t.write_text("arch gfx000\nnq 3 variant amp4_sgpr\n")
+    states = torch.zeros(8, dtype=torch.complex128, device="cuda")
+    with pytest.raises(L.QcwError, match="gfx000"):
+        L.Batch([(3, qi.circuit(0, 3, 2))], states, tune_table=str(t))
+
+
+def test_autotune_writes_a_loadable_table(L, tmp_path):
+    out = tmp_path / "tune.txt"
+    L.qcw_batch_autotune(str(out), 3, 5, 64)
+    text = out.read_text()
+    assert "arch gfx" in text and "nq 5 variant" in text
+    inst = qi.batch(8, 40, 3, 5)
+    states = torch.from_numpy(_pack_states(inst)).to("cuda")
+    b = L.Batch([(nq, c) for nq, _, c in inst], states, tune_table=str(out))
+    b.run()
+    torch.cuda.synchronize()
+    for o, p in zip(_split(states.cpu().numpy(), inst), _plain(L, inst)):
+        assert np.array_equal(o, p)
+    b.close()
+
+
+def test_committed_tune_table_loads(L):
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1101_1785_amd", "tune", "gfx950.txt")
+    if not os.path.exists(path):
+        pytest.skip("no committed tune table")
+    states = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    b = L.Batch([(4, qi.circuit(0, 4, 3))], states, tune_table=path)
+    b.close()
