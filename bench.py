@@ -41,6 +41,13 @@ def _args():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-log2", type=int, default=26,
                    help="contiguous outputs per gate timed on the CPU oracle")
+    p.add_argument("--serve-seconds", type=float, default=10.0,
+                   help="length of the open-loop serving run (the full workload is 60 s)")
+    p.add_argument("--serve-rate", type=float, default=2000.0)
+    p.add_argument("--skip-extra", action="store_true",
+                   help="only the headline workload (no batched/serving sections)")
+    p.add_argument("--tune-table", default=os.path.join(ROOT, "paper_1101_1785_amd", "tune",
+                                                        "gfx950.txt"))
     return p.parse_args()
 
 
@@ -86,6 +93,153 @@ def cpu_baseline(circ, psi_host, sample_log2: int):
             "kind": "oracle",
             "sample": f"{S} contiguous outputs (2^{sample_log2}) of each of the {len(circ)} gates "
                       f"at nq={nq}, {dt:.2f} s of CPU work, scaled by 2^{nq}/{S} to one solve"}
+
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _flops_per_solve(circ):
+    """8m - 2 real flops per amplitude per gate (m complex products and m - 1 sums)."""
+    N = 1 << circ.nq
+    return sum(N * (8 * (1 << k) - 2) for k in circ.ks)
+
+
+def _time_batch(torch, b, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    b.run()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(torch, L, qi, seed, count, lo, hi, tune_table, reps=50, plain=True,
+                  check=256, label=""):
+    """One persistent launch over `count` instances vs sequential plain circuits."""
+    import oracle
+    print(f"[bench] batched {label}: generating {count} instances nq {lo}..{hi}",
+          file=sys.stderr, flush=True)
+    inst = qi.batch(seed, count, lo, hi)
+    flat = np.concatenate([p for _, p, _ in inst])
+    # error vs the oracle after exactly one application
+    states = torch.from_numpy(flat).to("cuda")
+    b = L.Batch([(nq, c) for nq, _, c in inst], states, tune_table=tune_table)
+    b.run()
+    torch.cuda.synchronize()
+    got = states.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([1 << nq for nq, _, _ in inst])])
+    sub = list(range(0, count, max(1, count // check)))[:check]
+    refs = oracle.circuit_batch([inst[i] for i in sub])
+    err = max(np.linalg.norm(got[offs[i]:offs[i + 1]] - r) / np.linalg.norm(r)
+              for i, r in zip(sub, refs))
+    ms = _time_batch(torch, b, reps)
+    info = b.info(hi)
+    b.close()
+    flops = sum(_flops_per_solve(c) for _, _, c in inst)
+    hbm = sum(32 * (1 << nq) + sum(16 * U.size + 64 for U in c.mats) for nq, _, c in inst)
+    out = {
+        "instances": count, "nq_range": [lo, hi], "gates_per_instance": "4*nq", "seed": seed,
+        "batched_solves_per_s": count / (ms * 1e-3), "batched_us_per_launch": ms * 1e3,
+        "fp64_tflops": flops / (ms * 1e-3) / 1e12,
+        "fp64_frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "hbm_gbs_algorithmic": hbm / (ms * 1e-3) / 1e9,
+        "max_rel_err_vs_oracle": err, "checked_instances": len(sub),
+        "tile_shape_at_max_nq": L.qcw_batch_variant_name(info[0]),
+        "grid_blocks": info[1], "lds_bytes_per_block": info[2],
+        "tune_table": os.path.relpath(tune_table, ROOT) if tune_table else None,
+    }
+    if plain:
+        packed = [L.pack_circuit(c) for _, _, c in inst]
+        psis = [torch.from_numpy(p).to("cuda") for _, p, _ in inst]
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for (nq, _, c), (g, m), ps in zip(inst, packed, psis):
+            L.qcw_circuit(ps, nq, g, len(c), m, m.size)
+        e1.record()
+        torch.cuda.synchronize()
+        pm = e0.elapsed_time(e1)
+        out["plain_solves_per_s"] = count / (pm * 1e-3)
+        out["batched_over_plain"] = out["batched_solves_per_s"] / out["plain_solves_per_s"]
+        pg = np.concatenate([p.cpu().numpy() for p in psis])
+        out["batched_equals_plain_bitwise"] = bool(np.array_equal(pg, got))
+    return out
+
+
+def bench_serving(L, qi, seed, rate, seconds, lo, hi, tune_table, pool=4096):
+    """Open-loop Poisson arrivals; latency from each request's scheduled arrival."""
+    import threading
+    arr = qi.poisson_arrivals(seed, rate, seconds)
+    print(f"[bench] serving: {arr.size} arrivals at {rate}/s for {seconds}s "
+          f"(request pool {pool})", file=sys.stderr, flush=True)
+    inst = qi.batch(seed, pool, lo, hi)
+    reqs = [(nq, p, *L.pack_circuit(c)) for nq, p, c in inst]
+    s = L.Server(hbm_budget_bytes=1 << 30, max_slots=1024, gates_per_tick=0, max_nq=hi,
+                 tune_table=tune_table)
+    # warm the path (kernel load, plan cache)
+    for nq, p, g, m in reqs[:64]:
+        s.wait(s.submit(nq, psi0=p, gates=g, mats=m), nq)
+    tickets = [None] * arr.size
+    done_ns = np.zeros(arr.size, np.int64)
+    status = np.zeros(arr.size, np.int64)
+    t0 = time.monotonic_ns() + 20_000_000
+    sched = t0 + (arr * 1e9).astype(np.int64)
+    ready = threading.Semaphore(0)
+
+    def client():
+        for i in range(arr.size):
+            dt = (sched[i] - time.monotonic_ns()) / 1e9
+            if dt > 0:
+                time.sleep(dt)
+            nq, p, g, m = reqs[i % pool]
+            tickets[i] = s.submit(nq, psi0=p, gates=g, mats=m)
+            ready.release()
+
+    def collector():
+        for i in range(arr.size):
+            ready.acquire()
+            nq = reqs[i % pool][0]
+            out, st = s.wait(tickets[i], nq, timeout_s=120.0)
+            done_ns[i] = st.t_done_ns
+            status[i] = 0 if out is not None else st.status
+
+    tc, tr = threading.Thread(target=client), threading.Thread(target=collector)
+    tc.start(); tr.start(); tc.join(); tr.join()
+    cnt = s.counters()
+    s.close()
+    lat = (done_ns - sched) / 1e6
+    span = (done_ns.max() - sched.min()) / 1e9
+    return {
+        "rate_per_s": rate, "seconds": seconds, "requests": int(arr.size),
+        "nq_range": [lo, hi], "gates_per_request": "4*nq", "seed": seed,
+        "request_pool": pool,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "max_ms": float(lat.max()), "solves_per_s": float(arr.size / span),
+        "failed": int(np.count_nonzero(status)), "ticks": int(cnt["ticks"]),
+        "peak_active": int(cnt["peak_active"]), "peak_pending": int(cnt["peak_pending"]),
+        "latency_from": "scheduled arrival to completion (open loop)",
+    }
+
+
+def bench_plain_small(torch, L, qi, nq, seed, reps=2000):
+    """Literal paper size: one nq-qubit state, one 4*nq-gate circuit per solve."""
+    psi = torch.from_numpy(qi.state(seed, nq)).to("cuda")
+    c = qi.circuit(seed, nq, 4 * nq)
+    g, m = L.pack_circuit(c)
+    L.qcw_circuit(psi, nq, g, len(c), m, m.size)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.qcw_circuit(psi, nq, g, len(c), m, m.size)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"nq": nq, "gates": len(c), "plain_solves_per_s": reps / dt,
+            "us_per_solve": dt / reps * 1e6}
 
 
 def main():
@@ -153,6 +307,18 @@ def main():
     if not a.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(circ, psi_host, a.cpu_sample_log2)
+    del psi, psi_host
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not a.skip_extra:
+        tt = a.tune_table if a.tune_table and os.path.exists(a.tune_table) else None
+        extra["batched_config2"] = bench_batched(torch, L, qi, 2, 4096, 3, 7, tt,
+                                                 label="4096 x nq 3..7")
+        extra["batched_config4"] = bench_batched(torch, L, qi, 4, 4096, 9, 9, tt,
+                                                 label="4096 x nq 9")
+        extra["plain_nq9"] = bench_plain_small(torch, L, qi, 9, 1)
+        extra["serving_config3"] = bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9, tt)
 
     out = {
         "metric": METRIC,
@@ -183,6 +349,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "checks": {"final_norm": norm, "wall_s": wall},
+        **extra,
     }
     print(json.dumps(out), flush=True)
 

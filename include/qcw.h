@@ -192,6 +192,70 @@ int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, int ninst,
                        int gates_per_qubit, void *stream);
 
 /*
+ * Serving: a continuous-batching request loop on one GPU.  Requests (one
+ * instance each: a state of nq <= cfg.max_nq <= 11 qubits and its circuit)
+ * are submitted from any thread; a scheduler thread admits them in arrival
+ * order whenever a slot and enough of the device-memory budget are free,
+ * keeps each admitted state resident in device memory until its circuit is
+ * done, and runs ticks: one persistent batch launch that advances every
+ * resident request by up to gates_per_tick gates (0 = all remaining gates).
+ * Requests that arrive while a tick runs join the next tick.  A request
+ * never leaves the queue except by completing or failing, and the queue head
+ * is never overtaken (no starvation).  Results equal, bit for bit, those of
+ * qcw_circuit run on the request alone.
+ *
+ * All request arrays are HOST pointers copied by qcw_server_submit, which
+ * does not block on the GPU.  A request that can never run (invalid gates,
+ * nq above the limit, more memory than the whole budget) is rejected with
+ * QCW_EINVAL at submit and affects no other request.
+ */
+typedef struct {
+  uint64_t hbm_budget_bytes; /* device arena for resident requests */
+  int max_slots;             /* most requests resident at once */
+  int gates_per_tick;        /* 0: run all remaining gates in one tick */
+  int max_nq;                /* largest request size, <= 11 */
+  const char *tune_table;    /* NULL: built-in tile shapes */
+} qcw_server_cfg;
+
+typedef struct {
+  int nq;
+  int ngates;
+  const qcw_gate *gates; /* matrix offsets relative to mats */
+  const qcw_c64 *mats;
+  int64_t nmats;
+  const qcw_c64 *psi0; /* 2^nq amplitudes */
+} qcw_request;
+
+typedef struct {
+  int status;          /* QCW_OK, QCW_EAGAIN (pending) or an error */
+  int ticks;           /* ticks the request was resident for */
+  uint64_t t_submit_ns; /* CLOCK_MONOTONIC nanoseconds */
+  uint64_t t_admit_ns;
+  uint64_t t_done_ns;
+} qcw_req_stats;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, ticks;
+  uint64_t peak_active, peak_pending, admit_waits;
+} qcw_server_counters;
+
+typedef struct qcw_server qcw_server;
+
+int qcw_server_create(qcw_server **out, const qcw_server_cfg *cfg);
+int qcw_server_submit(qcw_server *s, const qcw_request *r, uint64_t *ticket);
+/* QCW_OK: finished; the final state is copied to psi_out_host (may be NULL)
+ * and the ticket is released.  QCW_EAGAIN: still pending.  Another code: the
+ * request failed or the ticket is unknown.  st may be NULL. */
+int qcw_server_poll(qcw_server *s, uint64_t ticket, qcw_c64 *psi_out_host,
+                    qcw_req_stats *st);
+/* As poll, but blocks up to timeout_s seconds for completion. */
+int qcw_server_wait(qcw_server *s, uint64_t ticket, qcw_c64 *psi_out_host,
+                    qcw_req_stats *st, double timeout_s);
+int qcw_server_counters_get(qcw_server *s, qcw_server_counters *out);
+/* Stops the scheduler after the current tick; pending requests fail. */
+int qcw_server_destroy(qcw_server *s);
+
+/*
  * Kernel timing.  While enabled, every kernel the library launches is
  * bracketed by HIP events recorded on the stream it is launched on.
  * qcw_timing_read synchronises those events and returns, for one kernel

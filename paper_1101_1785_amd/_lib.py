@@ -19,6 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libqcw.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1101_1785_amd.build`")
 
+# torch ships its own HIP runtime.  Loading torch first makes libqcw.so bind to
+# that same runtime (same SONAME), so device pointers and streams from torch are
+# valid in the library; loading libqcw.so first would put a second HIP runtime
+# in the process.
+import torch  # noqa: E402,F401
+
 _L = ctypes.CDLL(LIB_PATH)
 _P = ctypes.c_void_p
 _i32 = ctypes.c_int
@@ -64,6 +70,12 @@ _SIGS = {
     "qcw_batch_destroy": ([_P], _i32),
     "qcw_batch_variant_name": ([_i32], ctypes.c_char_p),
     "qcw_batch_autotune": ([ctypes.c_char_p, _i32, _i32, _i32, _i32, _P], _i32),
+    "qcw_server_create": ([_P, _P], _i32),
+    "qcw_server_submit": ([_P, _P, _P], _i32),
+    "qcw_server_poll": ([_P, ctypes.c_uint64, _P, _P], _i32),
+    "qcw_server_wait": ([_P, ctypes.c_uint64, _P, _P, ctypes.c_double], _i32),
+    "qcw_server_counters_get": ([_P, _P], _i32),
+    "qcw_server_destroy": ([_P], _i32),
     "qcw_timing_enable": ([_i32], _i32),
     "qcw_timing_reset": ([], _i32),
     "qcw_timing_read": ([_i32, _P, _P], _i32),
@@ -310,6 +322,114 @@ class Batch:
     def close(self):
         if self.h:
             qcw_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+class qcw_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int),
+                ("gates_per_tick", ctypes.c_int), ("max_nq", ctypes.c_int),
+                ("tune_table", ctypes.c_char_p)]
+
+
+class qcw_request(ctypes.Structure):
+    _fields_ = [("nq", ctypes.c_int), ("ngates", ctypes.c_int), ("gates", _P), ("mats", _P),
+                ("nmats", ctypes.c_int64), ("psi0", _P)]
+
+
+class qcw_req_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("ticks", ctypes.c_int),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class qcw_server_counters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "ticks",
+                                                "peak_active", "peak_pending", "admit_waits")]
+
+
+def qcw_server_create(cfg):
+    h = _P()
+    _check(_L.qcw_server_create(ctypes.byref(h), ctypes.byref(cfg)), "qcw_server_create")
+    return h
+
+
+def qcw_server_submit(h, req):
+    t = ctypes.c_uint64(0)
+    _check(_L.qcw_server_submit(h, ctypes.byref(req), ctypes.byref(t)), "qcw_server_submit")
+    return t.value
+
+
+def qcw_server_poll(h, ticket, out=None):
+    st = qcw_req_stats()
+    rc = _L.qcw_server_poll(h, ctypes.c_uint64(ticket), _hptr(out) if out is not None else None,
+                            ctypes.byref(st))
+    if rc not in (QCW_OK, QCW_EAGAIN):
+        raise QcwError(rc, "qcw_server_poll")
+    return rc, st
+
+
+def qcw_server_wait(h, ticket, out=None, timeout_s=60.0):
+    st = qcw_req_stats()
+    rc = _L.qcw_server_wait(h, ctypes.c_uint64(ticket), _hptr(out) if out is not None else None,
+                            ctypes.byref(st), float(timeout_s))
+    if rc not in (QCW_OK, QCW_EAGAIN):
+        raise QcwError(rc, "qcw_server_wait")
+    return rc, st
+
+
+def qcw_server_counters_get(h):
+    c = qcw_server_counters()
+    _check(_L.qcw_server_counters_get(h, ctypes.byref(c)), "qcw_server_counters_get")
+    return {n: getattr(c, n) for n, _ in c._fields_}
+
+
+def qcw_server_destroy(h):
+    _check(_L.qcw_server_destroy(h), "qcw_server_destroy")
+
+
+class Server:
+    """Continuous-batching request loop on the current GPU."""
+
+    def __init__(self, hbm_budget_bytes=1 << 30, max_slots=1024, gates_per_tick=0, max_nq=11,
+                 tune_table=None):
+        self._tt = tune_table.encode() if tune_table else None
+        cfg = qcw_server_cfg(hbm_budget_bytes, max_slots, gates_per_tick, max_nq, self._tt)
+        self.h = qcw_server_create(cfg)
+
+    def submit(self, nq, circ=None, psi0=None, gates=None, mats=None):
+        """Copies the request (a qcw_inputs.Circuit or packed gates/mats) and returns a ticket."""
+        if circ is not None:
+            gates, mats = pack_circuit(circ)
+        psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+        if psi0.size != (1 << nq):
+            raise ValueError("psi0 must hold 2^nq amplitudes")
+        req = qcw_request(int(nq), int(len(gates)), _hptr(gates) if len(gates) else None,
+                          _hptr(mats), int(mats.size), _hptr(psi0))
+        return qcw_server_submit(self.h, req)
+
+    def poll(self, ticket, nq):
+        out = np.empty(1 << nq, np.complex128)
+        rc, st = qcw_server_poll(self.h, ticket, out)
+        return (out if rc == QCW_OK else None), st
+
+    def wait(self, ticket, nq, timeout_s=60.0):
+        out = np.empty(1 << nq, np.complex128)
+        rc, st = qcw_server_wait(self.h, ticket, out, timeout_s)
+        return (out if rc == QCW_OK else None), st
+
+    def counters(self):
+        return qcw_server_counters_get(self.h)
+
+    def close(self):
+        if self.h:
+            qcw_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

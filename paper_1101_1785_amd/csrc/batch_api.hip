@@ -442,14 +442,21 @@ extern "C" int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, in
     }
     const int64_t nstates = (int64_t)ninst << nq;
     qcw_c64 *states = nullptr;
-    if (hipMalloc(&states, (size_t)nstates * sizeof(qcw_c64)) != hipSuccess) {
+    hipError_t he = hipMalloc(&states, (size_t)nstates * sizeof(qcw_c64));
+    if (he != hipSuccess) {
       (void)hipGetLastError();
-      return fail(QCW_ENOMEM, "autotune: hipMalloc failed");
+      return fail(he == hipErrorOutOfMemory ? QCW_ENOMEM : QCW_EHIP,
+                  "autotune nq=%d: hipMalloc(%lld B): %s", nq,
+                  (long long)(nstates * (int64_t)sizeof(qcw_c64)), hipGetErrorString(he));
     }
     std::vector<qcw_c64> psi((size_t)nstates);
     const double amp = 1.0 / std::sqrt((double)(1 << nq));
     for (auto &z : psi) z = {amp, 0.0};
-    (void)hipMemcpy(states, psi.data(), psi.size() * sizeof(qcw_c64), hipMemcpyHostToDevice);
+    he = hipMemcpy(states, psi.data(), psi.size() * sizeof(qcw_c64), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      (void)hipFree(states);
+      return fail(QCW_EHIP, "autotune nq=%d: upload: %s", nq, hipGetErrorString(he));
+    }
     float best_ms = 1e30f;
     char line[256];
     std::string times;
@@ -474,9 +481,14 @@ extern "C" int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, in
         rc = launch_batch(b->L, s);
         (void)hipEventRecord(e1, s);
         if (rc) break;
-        (void)hipEventSynchronize(e1);
+        hipError_t ee = hipEventSynchronize(e1);
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ee == hipSuccess) ee = hipEventElapsedTime(&ms, e0, e1);
+        if (ee != hipSuccess) {
+          rc = fail(QCW_EHIP, "autotune nq=%d variant %s: %s", nq, variant_name(v),
+                    hipGetErrorString(ee));
+          break;
+        }
         if (rep > 0) ms_min = std::min(ms_min, ms);
       }
       (void)hipEventDestroy(e0);

@@ -13,44 +13,6 @@
 
 namespace qcw {
 
-static thread_local char g_err[512];
-
-int fail(int code, const char *fmt, ...) {
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(g_err, sizeof(g_err), fmt, ap);
-  va_end(ap);
-  return code;
-}
-
-void clear_error() { g_err[0] = 0; }
-
-int make_geom(int nq, int k, const int *targets, Geom *g) {
-  if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
-  if (k < 1 || k > 3) return fail(QCW_EINVAL, "k=%d outside {1, 2, 3}", k);
-  if (k > nq) return fail(QCW_EINVAL, "k=%d exceeds nq=%d", k, nq);
-  if (!targets) return fail(QCW_EINVAL, "targets is NULL");
-  for (int j = 0; j < k; ++j) {
-    if (targets[j] < 1 || targets[j] > nq)
-      return fail(QCW_EINVAL, "target %d outside [1, %d]", targets[j], nq);
-    for (int i = 0; i < j; ++i)
-      if (targets[i] == targets[j]) return fail(QCW_EINVAL, "target %d repeated", targets[j]);
-  }
-  g->k = k;
-  g->nq = nq;
-  for (int j = 0; j < 3; ++j) g->bit[j] = g->sb[j] = 0;
-  for (int j = 0; j < k; ++j) g->bit[j] = g->sb[j] = nq - targets[j];
-  std::sort(g->sb, g->sb + k);
-  // Member r: the first listed target is the most significant bit of r.
-  for (int r = 0; r < (1 << k); ++r) {
-    uint64_t o = 0;
-    for (int j = 0; j < k; ++j)
-      if ((r >> (k - 1 - j)) & 1) o |= (uint64_t)1 << g->bit[j];
-    g->off[r] = o;
-  }
-  return QCW_OK;
-}
-
 int check_device_range(const void *ptr, uint64_t bytes, const char *what) {
   if (!ptr) return fail(QCW_EINVAL, "%s is NULL", what);
   hipPointerAttribute_t attr;
@@ -155,7 +117,7 @@ const char *qcw_strerror(int code) {
   return "unknown error";
 }
 
-const char *qcw_last_error(void) { return g_err; }
+const char *qcw_last_error(void) { return last_error(); }
 
 int qcw_version(void) { return 100; }
 
@@ -221,7 +183,7 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const q
     int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
     if (rc) {
       char why[512];
-      snprintf(why, sizeof(why), "%s", g_err);
+      snprintf(why, sizeof(why), "%s", last_error());
       return fail(rc, "gate %d: %s", i, why);
     }
     const int64_t mm = (int64_t)1 << (2 * gates[i].k);

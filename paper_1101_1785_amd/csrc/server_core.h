@@ -1,0 +1,124 @@
+// Continuous-batching request loop (host only, no HIP): admission of requests
+// into device slots under an HBM budget, per-tick planning of which slots
+// advance by how many gates, and completion bookkeeping.  The device work is
+// behind the Executor interface, so the scheduling logic is the same whether
+// the executor drives the GPU or is a test double.
+#pragma once
+
+#include <stdint.h>
+
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "qcw.h"
+
+namespace qcw {
+
+struct ServeRequest {
+  int nq = 0;
+  int ngates = 0;
+  std::vector<qcw_gate> gates;  // matrix offsets relative to `mats`
+  std::vector<qcw_c64> mats;
+  std::vector<qcw_c64> psi0;
+  uint64_t ticket = 0;
+  uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+  int status = QCW_EAGAIN;
+  int ticks = 0;
+  std::vector<qcw_c64> result;
+};
+
+// Device bytes a request occupies while resident: state, gate table, matrices
+// (each region rounded to 256 bytes).
+uint64_t request_device_bytes(int nq, int ngates, int64_t nmats);
+
+struct TickItem {
+  int slot;
+  int g_begin, g_end;
+  bool finishes;
+};
+
+class Executor {
+ public:
+  virtual ~Executor() {}
+  // Copies an admitted request into the arena at `off` (its own region).
+  virtual int load(int slot, uint64_t off, const ServeRequest &r) = 0;
+  // Runs one tick: every listed slot advances over its gate range; the states
+  // of finishing slots are copied out.  Returns when the tick is complete.
+  virtual int tick(const std::vector<TickItem> &items) = 0;
+  // The final state of a slot that finished in the last tick.
+  virtual int fetch(int slot, int nq, qcw_c64 *out) = 0;
+  // Releases a slot (its arena region is free again).
+  virtual void release(int slot) = 0;
+};
+
+// First-fit allocator over [0, size) with coalescing; 256-byte granules.
+class ArenaAllocator {
+ public:
+  explicit ArenaAllocator(uint64_t size);
+  bool alloc(uint64_t bytes, uint64_t *off);
+  void free(uint64_t off, uint64_t bytes);
+  uint64_t free_bytes() const { return free_bytes_; }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;  // offset -> length
+  uint64_t free_bytes_;
+};
+
+struct ServerConfig {
+  uint64_t hbm_budget_bytes = 1ull << 30;
+  int max_slots = 1024;
+  int gates_per_tick = 0;  // 0: a slot runs its remaining gates in one tick
+  int max_nq = 11;
+};
+
+struct ServerCounters {
+  uint64_t submitted = 0, completed = 0, rejected = 0, ticks = 0;
+  uint64_t peak_active = 0, peak_pending = 0;
+  uint64_t admit_waits = 0;  // ticks in which the queue head could not be admitted
+};
+
+class ServerCore {
+ public:
+  ServerCore(const ServerConfig &cfg, std::unique_ptr<Executor> ex);
+  ~ServerCore();
+  int submit(const qcw_request &r, uint64_t *ticket);
+  // QCW_OK: done (result copied, ticket released); QCW_EAGAIN: pending;
+  // another code: the request failed (ticket released).
+  int poll(uint64_t ticket, qcw_c64 *psi_out, qcw_req_stats *st);
+  int wait(uint64_t ticket, qcw_c64 *psi_out, qcw_req_stats *st, double timeout_s);
+  ServerCounters counters();
+  void stop();
+  static uint64_t now_ns();
+
+ private:
+  void loop();
+  void admit_locked();
+  struct Slot {
+    bool used = false;
+    uint64_t ticket = 0;
+    uint64_t off = 0, bytes = 0;
+    int progress = 0;
+  };
+  ServerConfig cfg_;
+  std::unique_ptr<Executor> ex_;
+  std::mutex mu_;
+  std::condition_variable cv_work_, cv_done_;
+  std::deque<uint64_t> pending_;
+  std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> reqs_;
+  std::vector<Slot> slots_;
+  std::vector<int> free_slots_;
+  ArenaAllocator arena_;
+  uint64_t next_ticket_ = 1;
+  bool stop_ = false;
+  int active_ = 0;
+  ServerCounters ctr_;
+  std::thread thr_;
+};
+
+}  // namespace qcw

@@ -100,3 +100,16 @@ def test_pack_circuit_layout(L):
         assert gates[g]["k"] == k and tuple(gates[g]["q"][:k]) == t
         o = gates[g]["mat"]
         assert np.array_equal(mats[o:o + U.size].reshape(U.shape), U)
+
+
+def test_single_hip_runtime_in_process():
+    """Importing the binding alone must not load a second HIP runtime next to torch's."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1101_1785_amd import _lib\n"
+            "import torch\n"
+            "m = open('/proc/self/maps').read()\n"
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.stdout.strip() == "1", out.stdout + out.stderr
