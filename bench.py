@@ -5,12 +5,18 @@ A step is one solve: a random circuit of G = 4*nq dense gates (k = 1, 2, 3
 with probabilities .50/.35/.15, random ordered targets, random unitaries)
 applied in place to one nq-qubit complex FP64 state that is already resident
 in HBM.  The default workload is the largest single state the 64 GB device
-budget admits, nq = 31 (2^31 amplitudes, 32 GiB), seed 1.
+budget admits, nq = 31 (2^31 amplitudes, 32 GiB), seed 1, run by the fused
+multi-gate path (qcw_circuit_fused; --path plain for one sweep per gate).
 
 Prints ONE JSON line with the throughput (solves/s), the roofline of the
-dominant kernel (the one-gate sweep; algorithmic bytes 32 * 2^nq per launch,
-measured with HIP events recorded by the library on the launch stream) and
-the CPU oracle timed on a bounded sample of the same solve.
+dominant kernel (algorithmic bytes 32 * 2^nq per launch -- one pass reads and
+writes every amplitude once -- over its launch durations, measured with HIP
+events recorded by the library on the launch stream), the CPU oracle timed on
+a bounded sample of the same solve, and sections for the batched (4096
+instances) and served (open-loop Poisson) forms.
+
+--counters runs each kernel once at nq = 28 beside a plain copy of known size,
+for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; it prints what it launched.
 """
 from __future__ import annotations
 
@@ -38,6 +44,9 @@ def _args():
     p.add_argument("--nq", type=int, default=31)
     p.add_argument("--gates", type=int, default=0, help="gates per circuit (default 4*nq)")
     p.add_argument("--seed", type=int, default=1)
+    p.add_argument("--path", choices=["fused", "plain"], default="fused",
+                   help="fused multi-gate passes (default) or one sweep per gate")
+    p.add_argument("--tile-bits", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-log2", type=int, default=26,
                    help="contiguous outputs per gate timed on the CPU oracle")
@@ -46,32 +55,37 @@ def _args():
     p.add_argument("--serve-rate", type=float, default=2000.0)
     p.add_argument("--skip-extra", action="store_true",
                    help="only the headline workload (no batched/serving sections)")
+    p.add_argument("--counters", action="store_true",
+                   help="launch each kernel once at nq=28 next to a 2 GiB copy, then exit")
     p.add_argument("--tune-table", default=os.path.join(ROOT, "paper_1101_1785_amd", "tune",
                                                         "gfx950.txt"))
     return p.parse_args()
 
 
-def _source_hash() -> str:
+KERNEL_SOURCES = {"sweep": ("sweep.hip", "qcw_device.h"), "fused": ("fused.hip", "qcw_device.h")}
+
+
+def _source_hash(kernel: str) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1101_1785_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def _traffic(kernel: str, nq: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when the kernels changed since the counters were taken."""
+    """HBM bytes per launch from the committed rocprofv3 counter record (bytes per
+    amplitude measured at nq = 28, times 2^nq), or None when the kernel's sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
     e = d.get(kernel)
-    if not e or e.get("source_hash") != _source_hash() or e.get("nq") != nq:
+    if not e or e.get("source_hash") != _source_hash(kernel):
         return None
-    return e.get("bytes_per_launch")
+    return e["bytes_per_amplitude"] * float(1 << nq)
 
 
 def cpu_baseline(circ, psi_host, sample_log2: int):
@@ -242,6 +256,31 @@ def bench_plain_small(torch, L, qi, nq, seed, reps=2000):
             "us_per_solve": dt / reps * 1e6}
 
 
+def counters_run(torch, L, qi):
+    """One launch of each kernel family at a known size, for hardware counters."""
+    nq = 28
+    N = 1 << nq
+    src = torch.zeros(1 << 27, dtype=torch.complex128, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)                                   # copy: 2 GiB read + 2 GiB written
+    torch.cuda.synchronize()
+    del src, dst
+    psi = torch.from_numpy(qi.state(1, nq)).to("cuda")
+    rng = np.random.default_rng(0)
+    for k, t in ((1, (14,)), (2, (3, 20)), (3, (10, 4, 25))):
+        L.qcw_opk(k, t, qi.random_unitary(rng, 1 << k), psi)
+    c = qi.circuit(1, nq, 4 * nq)
+    g, m = L.pack_circuit(c)
+    L.qcw_circuit_fused(psi, nq, g, len(c), m, m.size)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": {
+        "copy_bytes_read": 16 << 27, "copy_bytes_written": 16 << 27,
+        "sweep_launches": 3, "sweep_bytes_per_launch": 32 * N,
+        "fused_passes": L.qcw_fused_pass_count(nq, g, len(c)),
+        "fused_bytes_per_pass": 32 * N, "nq": nq}}), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -255,6 +294,10 @@ def main():
     from paper_1101_1785_amd import _lib as L
     import qcw_inputs as qi
 
+    if a.counters:
+        counters_run(torch, L, qi)
+        return
+
     nq = a.nq
     G = a.gates or 4 * nq
     N = 1 << nq
@@ -267,12 +310,18 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
+    def solve():
+        if a.path == "fused":
+            L.qcw_circuit_fused(psi, nq, gates, G, mats, mats.size, a.tile_bits, stream)
+        else:
+            L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)
+
     print(f"[bench] warmup {a.warmup}", file=sys.stderr, flush=True)
     for _ in range(a.warmup):
-        L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)
+        solve()
     torch.cuda.synchronize()
 
-    print(f"[bench] timing {a.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] timing {a.steps} steps ({a.path})", file=sys.stderr, flush=True)
     L.qcw_timing_reset()
     L.qcw_timing_enable(True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -281,7 +330,7 @@ def main():
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(a.steps):
-        L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)
+        solve()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -289,19 +338,37 @@ def main():
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / a.steps
 
-    launches, kms = 0, 0.0
-    per_k = {}
-    for k, fam in ((1, L.QCW_KERNEL_SWEEP1), (2, L.QCW_KERNEL_SWEEP2), (3, L.QCW_KERNEL_SWEEP3)):
-        n, ms = L.qcw_timing_read(fam)
-        launches += n
-        kms += ms
-        if n:
-            per_k[f"k{k}"] = {"launches": n, "avg_ms": ms / n,
-                              "GB/s": 32.0 * N * n / (ms * 1e-3) / 1e9}
     bytes_per_launch = 32.0 * N
+    per_k = {}
+    if a.path == "fused":
+        launches, kms = L.qcw_timing_read(L.QCW_KERNEL_FUSED)
+        npass = L.qcw_fused_pass_count(nq, gates, G, a.tile_bits)
+        kernel = "qcw::fused_pass_kernel (one pass = a run of gates over the state in LDS tiles)"
+        unit_note = f"one pass over the state; {npass} passes per {G}-gate solve"
+    else:
+        launches, kms = 0, 0.0
+        for k, fam in ((1, L.QCW_KERNEL_SWEEP1), (2, L.QCW_KERNEL_SWEEP2), (3, L.QCW_KERNEL_SWEEP3)):
+            n, ms = L.qcw_timing_read(fam)
+            launches += n
+            kms += ms
+            if n:
+                per_k[f"k{k}"] = {"launches": n, "avg_ms": ms / n,
+                                  "GB/s": 32.0 * N * n / (ms * 1e-3) / 1e9}
+        npass = G
+        kernel = "qcw::sweep_kernel (k=1,2,3)"
+        unit_note = "one gate over the state"
     avg_ms = kms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     norm = torch.linalg.vector_norm(psi).item()
+
+    # the other path, for comparison (same state buffer, untimed by the events above)
+    other = {}
+    if a.path == "fused":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)
+        torch.cuda.synchronize()
+        other = {"plain_one_sweep_per_gate_solves_per_s": 1.0 / (time.perf_counter() - t1)}
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -334,18 +401,22 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"plain path, one {nq}-qubit complex FP64 state ({16 * N / 2**30:.0f} GiB) "
+            "workload": f"single {nq}-qubit complex FP64 state ({16 * N / 2**30:.0f} GiB) "
                         f"resident in HBM; a solve = one {G}-gate random circuit "
-                        f"(k=1/2/3 at .50/.35/.15, random ordered targets, random unitaries), "
-                        f"one in-place sweep per gate; seed {a.seed}",
-            "nq": nq, "gates": G, "seed": a.seed, "path": "qcw_circuit (one sweep per gate)",
+                        f"(k=1/2/3 at .50/.35/.15, random ordered targets, random unitaries); "
+                        f"seed {a.seed}",
+            "nq": nq, "gates": G, "seed": a.seed,
+            "path": "qcw_circuit_fused" if a.path == "fused" else "qcw_circuit",
+            "passes_per_solve": npass,
+            **other,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic("sweep", nq),
-            "kernel": "qcw::sweep_kernel (k=1,2,3)", "launches": launches,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": _traffic("fused" if a.path == "fused" else "sweep", nq),
+            "kernel": kernel, "unit_of_work": unit_note, "launches": launches,
             "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-            "per_k": per_k,
+            "per_k": per_k or None,
         },
         "cpu_baseline": cpu,
         "checks": {"final_norm": norm, "wall_s": wall},

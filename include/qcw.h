@@ -128,6 +128,21 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                 const qcw_c64 *mats, int64_t nmats, void *stream);
 
 /*
+ * The same circuit with the same result, bit for bit, in fewer passes over
+ * HBM: consecutive gates whose targets fit, together with the lowest 5 label
+ * bits, in `tile_bits` bits (8..13; 0 = the tuned default, 12) form one pass.  A pass loads each
+ * tile of 2^tile_bits amplitudes (fixed values of the other bits) into LDS,
+ * applies every gate of the run there with the one-gate sweep's arithmetic,
+ * and stores it back, so a run of gates costs one read and one write of the
+ * state instead of one per gate.  States below 9 qubits use one sweep per
+ * gate.  Synchronises `stream` once, to hand the pass plan to the device.
+ */
+int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                      const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream);
+/* Number of passes qcw_circuit_fused makes for this gate list (host only). */
+int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits);
+
+/*
  * Pick_k as computed by the device (§4a-§4c): writes (2^nq / m) * m labels to
  * the HOST array out_host, group after group in ascending base label, the
  * members of a group in ascending local index.  nq <= 26.  Synchronous.
@@ -261,7 +276,8 @@ int qcw_server_destroy(qcw_server *s);
  * qcw_timing_read synchronises those events and returns, for one kernel
  * family, the number of launches and their summed duration in milliseconds
  * since the last reset.  Families: QCW_KERNEL_SWEEP1..3 (one-gate sweeps of
- * k = 1, 2, 3), QCW_KERNEL_BATCH (batch executions).  Launches recorded
+ * k = 1, 2, 3), QCW_KERNEL_BATCH (batch executions), QCW_KERNEL_FUSED
+ * (fused passes).  Launches recorded
  * into a hipGraph are not timed individually.
  */
 enum {
@@ -269,6 +285,7 @@ enum {
   QCW_KERNEL_SWEEP2 = 2,
   QCW_KERNEL_SWEEP3 = 3,
   QCW_KERNEL_BATCH = 4, /* one batch execution (qcw_batch_run: the graph) */
+  QCW_KERNEL_FUSED = 5, /* one fused pass */
   QCW_KERNEL_COUNT = 8
 };
 int qcw_timing_enable(int on);

@@ -32,6 +32,7 @@ _i64 = ctypes.c_int64
 
 QCW_OK, QCW_EINVAL, QCW_ENOMEM, QCW_EHIP, QCW_EAGAIN = 0, -1, -2, -3, -4
 QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3, QCW_KERNEL_BATCH = 1, 2, 3, 4
+QCW_KERNEL_FUSED = 5
 
 
 class QcwError(RuntimeError):
@@ -62,6 +63,8 @@ _SIGS = {
     "qcw_opk_to": ([_i32, _P, _P, _P, _P, _i32, _P], _i32),
     "qcw_omega_all": ([_P, _P, _i32, _P], _i32),
     "qcw_circuit": ([_P, _i32, _P, _i32, _P, _i64, _P], _i32),
+    "qcw_circuit_fused": ([_P, _i32, _P, _i32, _P, _i64, _i32, _P], _i32),
+    "qcw_fused_pass_count": ([_i32, _P, _i32, _i32], _i32),
     "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),
     "qcw_batch_create": ([_P, _P, _i32, _P, _i64, _P, _i64, _P, _i64, ctypes.c_char_p, _P], _i32),
     "qcw_batch_run": ([_P, _P], _i32),
@@ -210,6 +213,24 @@ def circuit(psi, circ, stream=None):
     """Apply a qcw_inputs.Circuit to psi in place with qcw_circuit."""
     gates, mats = pack_circuit(circ)
     qcw_circuit(psi, circ.nq, gates, len(circ), mats, mats.size, stream)
+
+
+def qcw_circuit_fused(psi, nq, gates, ngates, mats, nmats, tile_bits=0, stream=None):
+    _check(_L.qcw_circuit_fused(_dptr(psi), int(nq), _hptr(gates), int(ngates), _hptr(mats),
+                                int(nmats), int(tile_bits), _stream(stream)), "qcw_circuit_fused")
+
+
+def circuit_fused(psi, circ, tile_bits=0, stream=None):
+    """Apply a qcw_inputs.Circuit in place with qcw_circuit_fused."""
+    gates, mats = pack_circuit(circ)
+    qcw_circuit_fused(psi, circ.nq, gates, len(circ), mats, mats.size, tile_bits, stream)
+
+
+def qcw_fused_pass_count(nq, gates, ngates, tile_bits=0):
+    n = _L.qcw_fused_pass_count(int(nq), _hptr(gates), int(ngates), int(tile_bits))
+    if n < 0:
+        raise QcwError(n, "qcw_fused_pass_count")
+    return n
 
 
 def qcw_debug_pick_device(nq, targets):

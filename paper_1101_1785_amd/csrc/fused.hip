@@ -1,0 +1,451 @@
+// Fused multi-gate passes: one HBM read and one write of the state for a run
+// of consecutive gates (Op1/Op2/Op3 of §3a-§3c applied in circuit order).
+//
+// A pass picks T "tile bits": the lowest L bits of the label (so a tile is
+// made of contiguous 2^L-amplitude chunks and loads stay coalesced) plus the
+// target bits of every gate in the run.  The state splits into 2^(nq-T)
+// tiles, one per value of the other bits; every gate of the run touches only
+// tile bits, so each tile can be loaded into LDS, advanced through the whole
+// run, and stored back, independently of all other tiles.  Inside the tile a
+// gate is the same group update as the one-gate sweep (same member order, same
+// FMA sequence), so the results equal the one-sweep-per-gate path bit for bit.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "qcw_device.h"
+#include "qcw_host.h"
+
+namespace qcw {
+
+constexpr int kFusedMaxFree = 8;  // tile bits above the contiguous low bits
+constexpr int kFusedDefaultTile = 12;
+
+// Threads per block for a tile of 2^T amplitudes: eight amplitudes per thread
+// from T = 11 up, so larger tiles also get more waves for their gates.
+constexpr int fused_block(int T) { return T <= 11 ? 256 : (1 << (T - 3)); }
+
+struct alignas(16) FusedGate {
+  int32_t k;
+  int32_t sb0, sb1, sb2;  // local (tile-index) target bits, ascending
+  uint32_t off[8];        // local member offsets, local index order
+  double2 u[64];          // m x m matrix, row-major
+};
+
+struct alignas(16) FusedPass {
+  int32_t ngates;
+  int32_t gate_off;        // first gate in the gate table
+  int32_t T, L;            // tile bits, contiguous low bits
+  int32_t n_outer;         // number of non-tile bits
+  int32_t pad[3];
+  uint64_t chunk_off[1 << kFusedMaxFree];  // label offset of chunk c within the tile
+  uint8_t outer_pos[40];   // positions of the non-tile bits, ascending
+};
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <int K, int NT>
+__device__ __forceinline__ void tile_gate(double2 *S, int T, const FusedGate &g) {
+  constexpr int M = 1 << K;
+  const uint32_t ngroups = 1u << (T - K);
+  for (uint32_t j = threadIdx.x; j < ngroups; j += NT) {
+    const uint32_t base = insert_zeros<K, uint32_t>(j, g.sb0, g.sb1, g.sb2);
+    double2 x[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) x[r] = S[base + g.off[r]];
+    group_matvec_put<M>(x, [&](int r, int c) { return g.u[r * M + c]; },
+                        [&](int r, double2 y) { S[base + g.off[r]] = y; });
+  }
+}
+
+// Each thread stages 2^T / NT amplitudes of the tile.
+template <int T, int L, int NT = fused_block(T)>
+__global__ __launch_bounds__(NT) void fused_pass_kernel(double2 *psi,
+                                                                 const FusedPass *__restrict__ passes,
+                                                                 const FusedGate *__restrict__ gates,
+                                                                 int p) {
+  extern __shared__ double2 S[];
+  constexpr int N_TILE = 1 << T;
+  constexpr int PER = N_TILE / NT;
+  const FusedPass &P = passes[p];
+  // Label of the tile's first amplitude: block index bits deposited at the
+  // non-tile bit positions.
+  uint64_t tile_base = 0;
+  {
+    uint64_t b = blockIdx.x;
+    for (int j = 0; j < P.n_outer; ++j) tile_base |= ((b >> j) & 1ull) << P.outer_pos[j];
+  }
+  v2d v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = q * NT + threadIdx.x;
+    const uint64_t lab = tile_base + P.chunk_off[i >> L] + (uint32_t)(i & ((1 << L) - 1));
+    v[q] = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(psi + lab));
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = q * NT + threadIdx.x;
+    S[i] = make_double2(v[q].x, v[q].y);
+  }
+  __syncthreads();
+  for (int gi = 0; gi < P.ngates; ++gi) {
+    const FusedGate &g = gates[P.gate_off + gi];
+    switch (g.k) {
+      case 1: tile_gate<1, NT>(S, T, g); break;
+      case 2: tile_gate<2, NT>(S, T, g); break;
+      default: tile_gate<3, NT>(S, T, g); break;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = q * NT + threadIdx.x;
+    const uint64_t lab = tile_base + P.chunk_off[i >> L] + (uint32_t)(i & ((1 << L) - 1));
+    const double2 a = S[i];
+    v2d w = {a.x, a.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2d *>(psi + lab));
+  }
+}
+
+// Persistent, software-pipelined form for large tiles (one or two blocks per
+// CU): each block walks tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the
+// global loads of the next tile are issued into registers before the current
+// tile's gates run in LDS, so HBM reads overlap the LDS work and the stores.
+template <int T, int L, int NT = fused_block(T)>
+__global__ __launch_bounds__(NT) void fused_persistent_kernel(double2 *psi,
+                                                              const FusedPass *__restrict__ passes,
+                                                              const FusedGate *__restrict__ gates,
+                                                              int p, uint64_t ntiles) {
+  extern __shared__ double2 S[];
+  constexpr int PER = (1 << T) / NT;
+  const FusedPass &P = passes[p];
+  auto base_of = [&](uint64_t t) {
+    uint64_t b = 0;
+    for (int j = 0; j < P.n_outer; ++j) b |= ((t >> j) & 1ull) << P.outer_pos[j];
+    return b;
+  };
+  uint64_t lab[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = q * NT + threadIdx.x;
+    lab[q] = P.chunk_off[i >> L] + (uint32_t)(i & ((1 << L) - 1));
+  }
+  uint64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  v2d v[PER];
+  uint64_t base = base_of(t);
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    v[q] = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(psi + base + lab[q]));
+  for (;;) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) S[q * NT + threadIdx.x] = make_double2(v[q].x, v[q].y);
+    __syncthreads();
+    const uint64_t tn = t + gridDim.x;
+    const bool more = tn < ntiles;
+    const uint64_t base_n = more ? base_of(tn) : 0;
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        v[q] = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(psi + base_n + lab[q]));
+    }
+    for (int gi = 0; gi < P.ngates; ++gi) {
+      const FusedGate &g = gates[P.gate_off + gi];
+      switch (g.k) {
+        case 1: tile_gate<1, NT>(S, T, g); break;
+        case 2: tile_gate<2, NT>(S, T, g); break;
+        default: tile_gate<3, NT>(S, T, g); break;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const double2 a = S[q * NT + threadIdx.x];
+      v2d w = {a.x, a.y};
+      __builtin_nontemporal_store(w, reinterpret_cast<v2d *>(psi + base + lab[q]));
+    }
+    if (!more) break;
+    __syncthreads();  // every thread has read its part of S before it is refilled
+    t = tn;
+    base = base_n;
+  }
+}
+
+// ------------------------------------------------------------------ planning
+struct FusedShape {
+  int T, L;
+};
+
+static int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+// Greedy: extend the current run while the union of target bits and the low
+// L bits fits in T bits; then widen every pass's tile with the lowest unused
+// bits (larger contiguous chunks).
+static int plan_passes(int nq, const std::vector<Geom> &geo, const qcw_gate *gates,
+                       const qcw_c64 *mats, FusedShape sh, std::vector<FusedPass> &passes,
+                       std::vector<FusedGate> &fg) {
+  const int T = std::min(sh.T, nq);
+  const int L = std::min(sh.L, T);
+  const uint64_t low = (L >= 64) ? ~0ull : ((1ull << L) - 1);
+  std::vector<std::pair<int, uint64_t>> runs;  // (first gate, tile mask)
+  uint64_t cur = low;
+  int first = 0;
+  for (int g = 0; g < (int)geo.size(); ++g) {
+    uint64_t m = 0;
+    for (int j = 0; j < geo[g].k; ++j) m |= 1ull << geo[g].bit[j];
+    if (popcount64(cur | m) > T) {
+      runs.push_back({first, cur});
+      first = g;
+      cur = low | m;
+    } else {
+      cur |= m;
+    }
+  }
+  if (!geo.empty()) runs.push_back({first, cur});
+  passes.clear();
+  fg.clear();
+  for (size_t r = 0; r < runs.size(); ++r) {
+    const int g0 = runs[r].first;
+    const int g1 = (r + 1 < runs.size()) ? runs[r + 1].first : (int)geo.size();
+    uint64_t mask = runs[r].second;
+    for (int b = 0; b < nq && popcount64(mask) < T; ++b) mask |= 1ull << b;
+    FusedPass P;
+    memset(&P, 0, sizeof P);
+    P.ngates = g1 - g0;
+    P.gate_off = (int)fg.size();
+    P.T = T;
+    P.L = L;
+    // local index of each tile bit, and the non-tile bit positions
+    int local_of[64];
+    int nl = 0, no = 0;
+    for (int b = 0; b < nq; ++b) {
+      if ((mask >> b) & 1) {
+        local_of[b] = nl++;
+      } else {
+        local_of[b] = -1;
+        P.outer_pos[no++] = (uint8_t)b;
+      }
+    }
+    P.n_outer = no;
+    // chunk c: its free (non-low) tile bits, deposited at their label positions
+    int free_pos[kFusedMaxFree];
+    int nf = 0;
+    for (int b = L; b < nq; ++b)
+      if ((mask >> b) & 1) free_pos[nf++] = b;
+    if (nf != T - L || nf > kFusedMaxFree) return fail(QCW_EINVAL, "fused tile planning failed");
+    for (int c = 0; c < (1 << nf); ++c) {
+      uint64_t o = 0;
+      for (int j = 0; j < nf; ++j)
+        if ((c >> j) & 1) o |= 1ull << free_pos[j];
+      P.chunk_off[c] = o;
+    }
+    for (int g = g0; g < g1; ++g) {
+      FusedGate G;
+      memset(&G, 0, sizeof G);
+      G.k = geo[g].k;
+      int lb[3] = {0, 0, 0};
+      for (int j = 0; j < G.k; ++j) lb[j] = local_of[geo[g].bit[j]];
+      int sl[3] = {lb[0], lb[1], lb[2]};
+      std::sort(sl, sl + G.k);
+      G.sb0 = sl[0];
+      G.sb1 = sl[1];
+      G.sb2 = sl[2];
+      for (int rr = 0; rr < (1 << G.k); ++rr) {
+        uint32_t o = 0;
+        for (int j = 0; j < G.k; ++j)
+          if ((rr >> (G.k - 1 - j)) & 1) o |= 1u << lb[j];
+        G.off[rr] = o;
+      }
+      const qcw_c64 *U = mats + gates[g].mat;
+      for (int e = 0; e < (1 << (2 * G.k)); ++e) G.u[e] = make_double2(U[e].re, U[e].im);
+      fg.push_back(G);
+    }
+    passes.push_back(P);
+  }
+  return QCW_OK;
+}
+
+// Per-stream device buffer for plans; a stream's previous plan is overwritten
+// only by work ordered after that stream's earlier kernels.
+namespace {
+struct PlanBuf {
+  void *dev = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_plan_mu;
+std::unordered_map<hipStream_t, PlanBuf> g_plan_bufs;
+}  // namespace
+
+template <int T, int L>
+static int launch_passes_t(qcw_c64 *psi, int nq, const FusedPass *dp, const FusedGate *dg,
+                           int npass, hipStream_t s) {
+  const size_t lds = sizeof(double2) << T;
+  const uint64_t ntiles = 1ull << (nq - T);
+  constexpr int NT = fused_block(T);
+  // 2^13-amplitude tiles fill a CU's LDS with one block, so they run as
+  // persistent pipelined blocks; smaller tiles rely on several resident blocks
+  // per CU to overlap loads, LDS work and stores (measured faster for them).
+  constexpr bool persistent = T >= 13;
+  const void *fn = persistent ? (const void *)fused_persistent_kernel<T, L>
+                              : (const void *)fused_pass_kernel<T, L>;
+  static unsigned grid = 0;  // once per process and template instance
+  if (!grid) {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return fail(QCW_EHIP, "LDS of %zu B per block: %s", lds, hipGetErrorString(e));
+    }
+    int bpc = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, fn, NT, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(QCW_EHIP, "fused occupancy query failed");
+    }
+    if (bpc < 1) return fail(QCW_EHIP, "fused kernel with %zu B of LDS does not fit a CU", lds);
+    grid = (unsigned)(bpc * ncu);
+  }
+  for (int p = 0; p < npass; ++p) {
+    TimedLaunch t(QCW_KERNEL_FUSED, s);
+    if (persistent) {
+      const unsigned blocks = (unsigned)std::min<uint64_t>(grid, ntiles);
+      hipLaunchKernelGGL((fused_persistent_kernel<T, L>), dim3(blocks), dim3(NT), lds, s,
+                         reinterpret_cast<double2 *>(psi), dp, dg, p, ntiles);
+    } else {
+      hipLaunchKernelGGL((fused_pass_kernel<T, L>), dim3((unsigned)ntiles), dim3(NT), lds, s,
+                         reinterpret_cast<double2 *>(psi), dp, dg, p);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(QCW_EHIP, "fused launch: %s", hipGetErrorString(e));
+  }
+  return QCW_OK;
+}
+
+int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
+              int tile_bits, hipStream_t s) {
+  std::vector<Geom> geo(ngates);
+  for (int i = 0; i < ngates; ++i) {
+    int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
+    if (rc) return rc;
+  }
+  if (ngates == 0) return QCW_OK;
+  // Small states: the whole state is one tile; use the one-gate sweep when a
+  // tile would not reach a full block of work.
+  const int T = std::min(tile_bits, nq);
+  const int L = 5;
+  if (T < 8 || nq < 9) {
+    for (int i = 0; i < ngates; ++i) {
+      int rc = launch_sweep(geo[i], mats + gates[i].mat, psi, psi, s);
+      if (rc) return rc;
+    }
+    return QCW_OK;
+  }
+  std::vector<FusedPass> passes;
+  std::vector<FusedGate> fg;
+  int rc = plan_passes(nq, geo, gates, mats, FusedShape{T, L}, passes, fg);
+  if (rc) return rc;
+  const size_t pbytes = passes.size() * sizeof(FusedPass);
+  const size_t need = pbytes + fg.size() * sizeof(FusedGate);
+  void *dev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    PlanBuf &b = g_plan_bufs[s];
+    if (b.bytes < need) {
+      if (b.dev) {
+        // the old buffer may still be read by queued kernels of this stream
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(QCW_EHIP, "plan buffer sync");
+        (void)hipFree(b.dev);
+        b.dev = nullptr;
+      }
+      size_t nb = std::max<size_t>(need, 1 << 20);
+      if (hipMalloc(&b.dev, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        b.bytes = 0;
+        return fail(QCW_ENOMEM, "fused plan buffer (%zu B)", nb);
+      }
+      b.bytes = nb;
+    }
+    dev = b.dev;
+  }
+  std::vector<char> blob(need);
+  memcpy(blob.data(), passes.data(), pbytes);
+  memcpy(blob.data() + pbytes, fg.data(), fg.size() * sizeof(FusedGate));
+  if (hipMemcpyAsync(dev, blob.data(), need, hipMemcpyHostToDevice, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QCW_EHIP, "fused plan upload");
+  }
+  // the host blob must outlive the (possibly staged) copy
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(QCW_EHIP, "fused plan upload sync");
+  const FusedPass *dp = (const FusedPass *)dev;
+  const FusedGate *dg = (const FusedGate *)((char *)dev + pbytes);
+  const int np = (int)passes.size();
+  switch (T) {
+    case 8: return launch_passes_t<8, 5>(psi, nq, dp, dg, np, s);
+    case 9: return launch_passes_t<9, 5>(psi, nq, dp, dg, np, s);
+    case 10: return launch_passes_t<10, 5>(psi, nq, dp, dg, np, s);
+    case 11: return launch_passes_t<11, 5>(psi, nq, dp, dg, np, s);
+    case 12: return launch_passes_t<12, 5>(psi, nq, dp, dg, np, s);
+    default: return launch_passes_t<13, 5>(psi, nq, dp, dg, np, s);
+  }
+}
+
+int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits) {
+  std::vector<Geom> geo(ngates);
+  for (int i = 0; i < ngates; ++i)
+    if (make_geom(nq, gates[i].k, gates[i].q, &geo[i])) return -1;
+  const int T = std::min(tile_bits, nq);
+  if (T < 8 || nq < 9) return ngates;
+  std::vector<FusedPass> passes;
+  std::vector<FusedGate> fg;
+  std::vector<qcw_c64> zero(64);
+  std::vector<qcw_gate> g0(gates, gates + ngates);
+  for (auto &g : g0) g.mat = 0;
+  if (plan_passes(nq, geo, g0.data(), zero.data(), FusedShape{T, 5}, passes, fg)) return -1;
+  return (int)passes.size();
+}
+
+}  // namespace qcw
+
+using namespace qcw;
+
+extern "C" {
+
+int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                      const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream) {
+  clear_error();
+  if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
+  if (ngates < 0) return fail(QCW_EINVAL, "ngates < 0");
+  if (ngates > 0 && (!gates || !mats)) return fail(QCW_EINVAL, "gates or mats is NULL");
+  if (tile_bits == 0) tile_bits = kFusedDefaultTile;
+  if (tile_bits < 8 || tile_bits > 13) return fail(QCW_EINVAL, "tile_bits=%d outside [8, 13]", tile_bits);
+  for (int i = 0; i < ngates; ++i) {
+    Geom g;
+    int rc = make_geom(nq, gates[i].k, gates[i].q, &g);
+    if (rc) {
+      char why[400];
+      snprintf(why, sizeof why, "%s", last_error());
+      return fail(rc, "gate %d: %s", i, why);
+    }
+    const int64_t mm = (int64_t)1 << (2 * gates[i].k);
+    if (gates[i].mat < 0 || gates[i].mat + mm > nmats)
+      return fail(QCW_EINVAL, "gate %d: matrix offset outside mats", i);
+  }
+  int rc = check_device_range(psi, ((uint64_t)1 << nq) * sizeof(qcw_c64), "psi");
+  if (rc) return rc;
+  return run_fused(psi, nq, gates, ngates, mats, tile_bits, (hipStream_t)stream);
+}
+
+int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits) {
+  clear_error();
+  if (tile_bits == 0) tile_bits = kFusedDefaultTile;
+  if (nq < 1 || nq > kMaxQubits || ngates < 0 || (ngates > 0 && !gates) || tile_bits < 8 ||
+      tile_bits > 13)
+    return fail(QCW_EINVAL, "invalid arguments");
+  int n = fused_pass_count(nq, gates, ngates, tile_bits);
+  return n < 0 ? fail(QCW_EINVAL, "invalid gate") : n;
+}
+
+}  // extern "C"
