@@ -207,6 +207,56 @@ int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, int ninst,
                        int gates_per_qubit, void *stream);
 
 /*
+ * Multiverse density-matrix step (§5, "The multiverse approach").
+ *
+ * rho is a DEVICE array of 2^nq x 2^nq qcw_c64 (nq <= 17), row-major:
+ * element (n, m) = <n|rho|m> at n * 2^nq + m.  Read as a vector it is a
+ * 2nq-qubit state whose qubits 1..nq are the row qubits and nq+1..2nq the
+ * column qubits.
+ *
+ * qcw_rho_conjugate: rho <- U rho U^dagger for a k-qubit algorithm gate (the
+ * Omega_A factors of Eq. rhoE4): the one-gate sweep of U on the row targets,
+ * then of conj(U) on the column targets.
+ *
+ * A channel is the ensemble average over noisy paths, Eq. rhoE1:
+ *     rho_out = p_keep * rho_in + sum_t weight_t K_t rho_in K_t^dagger,
+ * where path t's operator K_t is one 2 x 2 operator on qubit q[0] (nops = 1,
+ * a single hit) or the product of two 2 x 2 operators on distinct qubits q[0],
+ * q[1] (nops = 2, a double hit).  In Eq. rhoE4 the weight of a path is
+ * eps * p_s / n_p and p_keep = 1 - eps (the paper's p; the printed equation
+ * omits it, but its trace then exceeds 1, while Eq. rhoE1 and the trace
+ * argument that follows it keep it).  The operators are fixed once drawn
+ * (§5, caption of the denE listing), so a channel is created once, copied to
+ * the device, and applied at every step.  rho_in and rho_out must not overlap.
+ *
+ * qcw_rho_observables (synchronous) writes to out_host, 4 + 3 nq doubles:
+ * Tr rho (re, im); Tr rho^2 as sum |rho_nm|^2 (equal for Hermitian rho); the
+ * fidelity Tr sqrt(sqrt(rho0) rho sqrt(rho0)) = sqrt(<psi0|rho|psi0>) against
+ * the pure reference rho0 = |psi0><psi0| (psi0_host: 2^nq host amplitudes, or
+ * NULL, then NaN); and for qubit q = 1..nq the polarisation Tr[sigma_x,y,z^(q)
+ * rho] (§5, the ideal and noisy channels).
+ */
+typedef struct {
+  int32_t nops;   /* 1 or 2 */
+  int32_t q[2];   /* qubits, 1-based */
+  int32_t pad;
+  int64_t mat[2]; /* offsets of the 2 x 2 operators in mats */
+  double weight;
+} qcw_kraus_term;
+
+typedef struct qcw_channel qcw_channel;
+
+int qcw_rho_conjugate(int k, const int *targets, const qcw_c64 *U, qcw_c64 *rho, int nq,
+                      void *stream);
+int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus_term *terms,
+                       int nterms, const qcw_c64 *mats, int64_t nmats);
+int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out,
+                      void *stream);
+int qcw_channel_destroy(qcw_channel *c);
+int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
+                        double *out_host, void *stream);
+
+/*
  * Serving: a continuous-batching request loop on one GPU.  Requests (one
  * instance each: a state of nq <= cfg.max_nq <= 11 qubits and its circuit)
  * are submitted from any thread; a scheduler thread admits them in arrival
@@ -286,6 +336,7 @@ enum {
   QCW_KERNEL_SWEEP3 = 3,
   QCW_KERNEL_BATCH = 4, /* one batch execution (qcw_batch_run: the graph) */
   QCW_KERNEL_FUSED = 5, /* one fused pass */
+  QCW_KERNEL_CHANNEL = 6, /* one channel application */
   QCW_KERNEL_COUNT = 8
 };
 int qcw_timing_enable(int on);

@@ -33,6 +33,7 @@ _i64 = ctypes.c_int64
 QCW_OK, QCW_EINVAL, QCW_ENOMEM, QCW_EHIP, QCW_EAGAIN = 0, -1, -2, -3, -4
 QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3, QCW_KERNEL_BATCH = 1, 2, 3, 4
 QCW_KERNEL_FUSED = 5
+QCW_KERNEL_CHANNEL = 6
 
 
 class QcwError(RuntimeError):
@@ -73,6 +74,11 @@ _SIGS = {
     "qcw_batch_destroy": ([_P], _i32),
     "qcw_batch_variant_name": ([_i32], ctypes.c_char_p),
     "qcw_batch_autotune": ([ctypes.c_char_p, _i32, _i32, _i32, _i32, _P], _i32),
+    "qcw_rho_conjugate": ([_i32, _P, _P, _P, _i32, _P], _i32),
+    "qcw_channel_create": ([_P, _i32, ctypes.c_double, _P, _i32, _P, _i64], _i32),
+    "qcw_channel_apply": ([_P, _P, _P, _P], _i32),
+    "qcw_channel_destroy": ([_P], _i32),
+    "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_server_create": ([_P, _P], _i32),
     "qcw_server_submit": ([_P, _P, _P], _i32),
     "qcw_server_poll": ([_P, ctypes.c_uint64, _P, _P], _i32),
@@ -458,3 +464,82 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ density matrix
+KRAUS_DTYPE = np.dtype([("nops", np.int32), ("q", np.int32, (2,)), ("pad", np.int32),
+                        ("mat", np.int64, (2,)), ("weight", np.float64)], align=True)
+assert KRAUS_DTYPE.itemsize == 40
+
+
+def _rho_nq(rho, nq):
+    if nq is not None:
+        return int(nq)
+    n = rho.numel()
+    b = n.bit_length() - 1
+    if n <= 0 or n & (n - 1) or b % 2:
+        raise ValueError("rho must hold 4^nq elements")
+    return b // 2
+
+
+def qcw_rho_conjugate(k, targets, U, rho, nq=None, stream=None):
+    U = _mat(U, k)
+    t = _targets(targets)
+    _check(_L.qcw_rho_conjugate(int(k), _hptr(t), _hptr(U), _dptr(rho), _rho_nq(rho, nq),
+                                _stream(stream)), "qcw_rho_conjugate")
+
+
+def pack_terms(terms):
+    """[(weight, {qubit: 2x2}), ...] -> (term table, mats)."""
+    tab = np.zeros(len(terms), dtype=KRAUS_DTYPE)
+    mats = []
+    off = 0
+    for i, (w, ops) in enumerate(terms):
+        if not 1 <= len(ops) <= 2:
+            raise ValueError("a term has one or two one-qubit operators")
+        tab[i]["nops"] = len(ops)
+        tab[i]["weight"] = w
+        for j, (q, K) in enumerate(ops.items()):
+            tab[i]["q"][j] = q
+            tab[i]["mat"][j] = off
+            mats.append(np.ascontiguousarray(K, dtype=np.complex128).reshape(4))
+            off += 4
+    M = np.concatenate(mats) if mats else np.zeros(4, np.complex128)
+    return tab, M
+
+
+class Channel:
+    """Ensemble-average channel rho -> p rho + sum w K rho K^dagger on the GPU."""
+
+    def __init__(self, nq, p_keep, terms):
+        tab, mats = pack_terms(terms)
+        h = _P()
+        _check(_L.qcw_channel_create(ctypes.byref(h), int(nq), float(p_keep),
+                                     _hptr(tab) if len(tab) else None, len(tab), _hptr(mats),
+                                     mats.size), "qcw_channel_create")
+        self.h, self.nq = h, nq
+
+    def apply(self, rho_in, rho_out, stream=None):
+        _check(_L.qcw_channel_apply(self.h, _dptr(rho_in), _dptr(rho_out), _stream(stream)),
+               "qcw_channel_apply")
+
+    def close(self):
+        if self.h:
+            _check(_L.qcw_channel_destroy(self.h), "qcw_channel_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qcw_rho_observables(rho, nq=None, psi0=None, stream=None):
+    nq = _rho_nq(rho, nq)
+    out = np.empty(4 + 3 * nq, dtype=np.float64)
+    p = np.ascontiguousarray(psi0, dtype=np.complex128) if psi0 is not None else None
+    _check(_L.qcw_rho_observables(_dptr(rho), nq, _hptr(p) if p is not None else None,
+                                  _hptr(out), _stream(stream)), "qcw_rho_observables")
+    return {"trace": complex(out[0], out[1]), "purity": float(out[2]),
+            "fidelity": float(out[3]), "polarization": out[4:].reshape(nq, 3)}

@@ -1,0 +1,189 @@
+"""GPU parity of the multiverse density-matrix step against the density oracle.
+
+Tolerance: elementwise |rho_gpu - rho_oracle| <= 1e-12 (rho has unit trace,
+so its elements are at most 1); observables within 1e-12.
+"""
+import numpy as np
+import pytest
+
+import qcw_inputs as qi
+from oracle import density as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_1785_amd import _lib
+    return _lib
+
+
+def dev(r):
+    return torch.from_numpy(np.ascontiguousarray(r, dtype=np.complex128).reshape(-1)).to("cuda")
+
+
+def host(t, nq):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().reshape(1 << nq, 1 << nq)
+
+
+def _rand_rho(rng, nq, rank=3):
+    A = rng.normal(size=(1 << nq, rank)) + 1j * rng.normal(size=(1 << nq, rank))
+    r = A @ A.conj().T
+    return r / np.trace(r)
+
+
+def _terms(rng, nq, n_p, eps, unitary=True):
+    terms = []
+    for s, ps in ((1, 0.95), (2, 0.05)):
+        if s == 2 and nq < 2:
+            continue
+        for _ in range(n_p):
+            qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
+            ops = {q: (qi.random_unitary(rng, 2) if unitary else qi.random_matrix(rng, 2))
+                   for q in qs}
+            terms.append((eps * ps / n_p, ops))
+    return terms
+
+
+@pytest.mark.parametrize("nq", [1, 2, 3, 5, 7])
+def test_conjugate_matches_oracle(L, nq):
+    rng = np.random.default_rng(nq)
+    rho0 = _rand_rho(rng, nq)
+    for k in range(1, min(3, nq) + 1):
+        t = tuple(int(x) + 1 for x in rng.choice(nq, k, replace=False))
+        U = qi.random_unitary(rng, 1 << k)
+        r = dev(rho0)
+        L.qcw_rho_conjugate(k, t, U, r)
+        assert np.max(np.abs(host(r, nq) - D.conjugate(rho0, U, t))) <= TOL
+
+
+@pytest.mark.parametrize("nq", [1, 2, 4, 6, 8])
+@pytest.mark.parametrize("unitary", [True, False])
+def test_channel_matches_oracle(L, nq, unitary):
+    rng = np.random.default_rng(10 * nq + unitary)
+    rho0 = _rand_rho(rng, nq)
+    terms = _terms(rng, nq, 8, 0.2, unitary)
+    ch = L.Channel(nq, 0.8, terms)
+    a, b = dev(rho0), torch.empty(1 << (2 * nq), dtype=torch.complex128, device="cuda")
+    ch.apply(a, b)
+    assert np.max(np.abs(host(b, nq) - D.channel(rho0, 0.8, terms))) <= TOL
+    ch.close()
+
+
+@pytest.mark.parametrize("nq", [1, 3, 6])
+def test_observables_match_oracle(L, nq):
+    rng = np.random.default_rng(20 + nq)
+    rho = _rand_rho(rng, nq)
+    psi0 = qi.state(2, nq)
+    got = L.qcw_rho_observables(dev(rho), psi0=psi0)
+    ref = D.observables(rho, psi0)
+    assert abs(got["trace"] - ref["trace"]) <= TOL
+    assert abs(got["purity"] - ref["purity"]) <= TOL
+    assert abs(got["fidelity"] - ref["fidelity"]) <= TOL
+    assert np.max(np.abs(got["polarization"] - ref["polarization"])) <= TOL
+    assert np.isnan(L.qcw_rho_observables(dev(rho))["fidelity"])
+
+
+def _run_sequence(L, nq, psi0, schedule, p_keep, terms):
+    """schedule: list of gates (U, targets) or 'noise'; returns per-step observables
+    from the GPU and the oracle."""
+    rho_o = D.pure(psi0)
+    a = dev(rho_o)
+    b = torch.empty_like(a)
+    ch = L.Channel(nq, p_keep, terms)
+    gpu, orc = [], []
+    for step in schedule:
+        if step == "noise":
+            ch.apply(a, b)
+            a, b = b, a
+            rho_o = D.channel(rho_o, p_keep, terms)
+        else:
+            U, t = step
+            L.qcw_rho_conjugate(len(t), t, U, a)
+            rho_o = D.conjugate(rho_o, U, t)
+        gpu.append(L.qcw_rho_observables(a, psi0=psi0))
+        orc.append(D.observables(rho_o, psi0))
+    ch.close()
+    return gpu, orc, host(a, nq), rho_o
+
+
+def test_mv1_sequence(L):
+    """§5 MV1-Noise: |0>, H at step 1, noise, H at step 3, then noise; without
+    noise the fidelity is 1/sqrt2 after the first H and 1 after the second."""
+    psi0 = qi.basis_state(1, 0)
+    sched = [(qi.H, (1,)), "noise", (qi.H, (1,))] + ["noise"] * 6
+    xyz = [(0.2 / 3, {1: s}) for s in (D.SX, D.SY, D.SZ)]
+    gpu, orc, r_g, r_o = _run_sequence(L, 1, psi0, sched, 0.8, xyz)
+    for g, o in zip(gpu, orc):
+        assert abs(g["fidelity"] - o["fidelity"]) <= TOL
+        assert abs(g["purity"] - o["purity"]) <= TOL
+    assert np.max(np.abs(r_g - r_o)) <= TOL
+    gpu0, _, _, _ = _run_sequence(L, 1, psi0, sched, 1.0, [])
+    assert abs(gpu0[0]["fidelity"] - 2 ** -0.5) <= 4e-16
+    assert abs(gpu0[2]["fidelity"] - 1.0) <= 4e-16
+
+
+def test_mv2_sequence(L):
+    """§5 MV2-Noise: Bell circuit, noise, inverse Bell, noise (X/Y/Z single and
+    double hits)."""
+    rng = np.random.default_rng(5)
+    psi0 = qi.basis_state(2, 0)
+    sched = [(qi.H, (1,)), "noise", (qi.CNOT, (1, 2)), "noise", (qi.CNOT, (1, 2)),
+             (qi.H, (1,))] + ["noise"] * 4
+    paulis = (D.SX, D.SY, D.SZ)
+    terms = [(0.2 * 0.95 / 8, {int(rng.integers(1, 3)): paulis[i % 3]}) for i in range(8)] + \
+            [(0.2 * 0.05 / 8, {1: paulis[i % 3], 2: paulis[(i + 1) % 3]}) for i in range(8)]
+    gpu, orc, r_g, r_o = _run_sequence(L, 2, psi0, sched, 0.8, terms)
+    for g, o in zip(gpu, orc):
+        assert abs(g["fidelity"] - o["fidelity"]) <= TOL
+        assert np.max(np.abs(g["polarization"] - o["polarization"])) <= TOL
+    assert np.max(np.abs(r_g - r_o)) <= TOL
+
+
+def test_mvn_ghz_with_noise(L):
+    """§5 MVn-Noise: five qubits, H_1 then the CNOT_1j chain, noise between steps."""
+    rng = np.random.default_rng(6)
+    nq = 5
+    psi0 = qi.basis_state(nq, 0)
+    sched = [(qi.H, (1,)), "noise"]
+    for t in range(2, nq + 1):
+        sched += [(qi.CNOT, (1, t)), "noise"]
+    terms = _terms(rng, nq, 16, 0.2)
+    gpu, orc, r_g, r_o = _run_sequence(L, nq, psi0, sched, 0.8, terms)
+    assert np.max(np.abs(r_g - r_o)) <= TOL
+    assert abs(gpu[-1]["purity"] - orc[-1]["purity"]) <= TOL
+
+
+def test_large_rho_properties(L):
+    """nq = 12 (16M elements): trace and hermiticity preserved by the channel."""
+    nq = 12
+    rng = np.random.default_rng(7)
+    v = qi.state(3, nq)
+    a = dev(np.outer(v, v.conj()))
+    b = torch.empty_like(a)
+    ch = L.Channel(nq, 0.8, _terms(rng, nq, 16, 0.2))
+    ch.apply(a, b)
+    ob = L.qcw_rho_observables(b)
+    assert abs(ob["trace"] - 1) <= 1e-12
+    assert ob["purity"] < 1.0
+    m = b.reshape(1 << nq, 1 << nq)
+    assert torch.max(torch.abs(m - m.conj().T)).item() <= 1e-15
+    ch.close()
+
+
+def test_channel_validation(L):
+    with pytest.raises(L.QcwError):
+        L.Channel(3, 0.5, [(0.5, {4: D.SX})])
+    with pytest.raises(L.QcwError):
+        L.Channel(18, 0.5, [])
+    ch = L.Channel(2, 1.0, [])
+    a = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    with pytest.raises(L.QcwError, match="overlap"):
+        ch.apply(a, a)
+    ch.close()
