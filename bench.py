@@ -240,6 +240,57 @@ def bench_serving(L, qi, seed, rate, seconds, lo, hi, tune_table, pool=4096):
     }
 
 
+def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
+    """Multiverse density-matrix steps (Eq. rhoE4): channel of n_p single-hit and
+    n_p double-hit Pauli paths (weights eps*p_s/n_p, p1=.95, p2=.05, p_keep=1-eps),
+    then one algorithm gate (H_1 or a CNOT of the GHZ chain) by conjugation."""
+    rng = np.random.default_rng([seed, 7])
+    P = [qi.X, qi.Y, qi.Z]
+    terms = []
+    for s, ps in ((1, 0.95), (2, 0.05)):
+        for _ in range(n_p):
+            qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
+            terms.append((eps * ps / n_p, {q: P[int(rng.integers(3))] for q in qs}))
+    ch = L.Channel(nq, 1 - eps, terms)
+    psi0 = qi.basis_state(nq, 0)
+    a = torch.from_numpy(np.outer(psi0, psi0.conj()).reshape(-1)).to("cuda")
+    b2 = torch.empty_like(a)
+    gates = [(qi.H, (1,))] + [(qi.CNOT, (1, t)) for t in range(2, nq + 1)]
+
+    def step(i, x, y):
+        ch.apply(x, y)
+        U, t = gates[i % len(gates)]
+        L.qcw_rho_conjugate(len(t), t, U, y)
+
+    step(0, a, b2)
+    torch.cuda.synchronize()
+    L.qcw_timing_reset()
+    L.qcw_timing_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    x, y = a, b2
+    for i in range(steps):
+        step(i, x, y)
+        x, y = y, x
+    e1.record()
+    torch.cuda.synchronize()
+    L.qcw_timing_enable(False)
+    ms = e0.elapsed_time(e1) / steps
+    n, cms = L.qcw_timing_read(L.QCW_KERNEL_CHANNEL)
+    ob = L.qcw_rho_observables(x, psi0=psi0)
+    NN = 1 << (2 * nq)
+    fl = ch.flops_per_element() * NN
+    cavg = cms / max(n, 1)
+    ch.close()
+    return {"nq": nq, "paths": 2 * n_p, "steps_per_s": 1e3 / ms, "ms_per_step": ms,
+            "channel_ms": cavg, "channel_fp64_tflops": fl / (cavg * 1e-3) / 1e12,
+            "channel_fp64_frac": fl / (cavg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "channel_flops_per_element": ch_flops if (ch_flops := fl // NN) else None,
+            "trace_after": ob["trace"].real, "purity_after": ob["purity"],
+            "fidelity_after": ob["fidelity"]}
+
+
 def bench_plain_small(torch, L, qi, nq, seed, reps=2000):
     """Literal paper size: one nq-qubit state, one 4*nq-gate circuit per solve."""
     psi = torch.from_numpy(qi.state(seed, nq)).to("cuda")
@@ -385,6 +436,8 @@ def main():
         extra["batched_config4"] = bench_batched(torch, L, qi, 4, 4096, 9, 9, tt,
                                                  label="4096 x nq 9")
         extra["plain_nq9"] = bench_plain_small(torch, L, qi, 9, 1)
+        extra["multiverse_nq12"] = bench_multiverse(torch, L, qi, 12, 5)
+        extra["multiverse_nq5"] = bench_multiverse(torch, L, qi, 5, 5, steps=200)
         extra["serving_config3"] = bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9, tt)
 
     out = {

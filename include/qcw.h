@@ -253,6 +253,10 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
 int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out,
                       void *stream);
 int qcw_channel_destroy(qcw_channel *c);
+/* Real FP64 operations per output element of one application: 8 per complex
+ * multiply-add (4 per single-hit term, 16 per double-hit term), 4 for each
+ * weighted sum, 2 for p_keep * rho.  For roofline accounting. */
+int64_t qcw_channel_flops_per_element(const qcw_channel *c);
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
 

@@ -78,6 +78,7 @@ _SIGS = {
     "qcw_channel_create": ([_P, _i32, ctypes.c_double, _P, _i32, _P, _i64], _i32),
     "qcw_channel_apply": ([_P, _P, _P, _P], _i32),
     "qcw_channel_destroy": ([_P], _i32),
+    "qcw_channel_flops_per_element": ([_P], _i64),
     "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_server_create": ([_P, _P], _i32),
     "qcw_server_submit": ([_P, _P, _P], _i32),
@@ -522,6 +523,9 @@ class Channel:
     def apply(self, rho_in, rho_out, stream=None):
         _check(_L.qcw_channel_apply(self.h, _dptr(rho_in), _dptr(rho_out), _stream(stream)),
                "qcw_channel_apply")
+
+    def flops_per_element(self):
+        return int(_L.qcw_channel_flops_per_element(self.h))
 
     def close(self):
         if self.h:

@@ -60,6 +60,26 @@ __device__ __forceinline__ void lds_gate(double2 *S, int nq, const BGate &g, con
   }
 }
 
+// Copies an instance's 2^nq amplitudes from HBM into the wave's LDS region,
+// eight loads in flight per lane before any LDS store when 2^nq >= 512.
+__device__ __forceinline__ void load_state(double2 *S, const double2 *st, uint32_t N, int lane) {
+  uint32_t n0 = 0;
+  for (; n0 + 512 <= N; n0 += 512) {
+    double2 v0 = st[n0 + lane], v1 = st[n0 + 64 + lane], v2 = st[n0 + 128 + lane],
+            v3 = st[n0 + 192 + lane], v4 = st[n0 + 256 + lane], v5 = st[n0 + 320 + lane],
+            v6 = st[n0 + 384 + lane], v7 = st[n0 + 448 + lane];
+    S[n0 + lane] = v0;
+    S[n0 + 64 + lane] = v1;
+    S[n0 + 128 + lane] = v2;
+    S[n0 + 192 + lane] = v3;
+    S[n0 + 256 + lane] = v4;
+    S[n0 + 320 + lane] = v5;
+    S[n0 + 384 + lane] = v6;
+    S[n0 + 448 + lane] = v7;
+  }
+  for (uint32_t n = n0 + lane; n < N; n += 64) S[n] = st[n];
+}
+
 template <int AMP, bool MAT_LDS>
 __device__ void run_instance(const BInst &in, const BGate *__restrict__ gates,
                              const double2 *__restrict__ mats, double2 *__restrict__ states,
@@ -67,28 +87,41 @@ __device__ void run_instance(const BInst &in, const BGate *__restrict__ gates,
   const int nq = in.nq;
   const uint32_t N = 1u << nq;
   double2 *st = states + in.state_off;
-  for (uint32_t n = lane; n < N; n += 64) S[n] = st[n];
-  wave_lds_sync();
+  load_state(S, st, N, lane);
+  if (g_begin >= g_end) {
+    wave_lds_sync();
+    return;
+  }
+  // The next gate's matrix is fetched while the current gate runs (lane e
+  // holds entry e in flight) and staged into one of two LDS slots; reading the
+  // next descriptor's k and matrix offset also brings its cache line in.
+  int nk = gates[in.gate_off + g_begin].k;
+  int64_t nmat = gates[in.gate_off + g_begin].mat_off;
+  double2 mreg = make_double2(0.0, 0.0);
+  if (MAT_LDS && lane < (1 << (2 * nk))) mreg = mats[nmat + lane];
   for (int gi = g_begin; gi < g_end; ++gi) {
+    double2 *Ub = Ul + ((gi - g_begin) & 1) * 64;
+    if (MAT_LDS && lane < (1 << (2 * nk))) Ub[lane] = mreg;
+    wave_lds_sync();
     const BGate g = gates[in.gate_off + gi];
     const double2 *U = mats + g.mat_off;
-    if (MAT_LDS) {
-      const int mm = 1 << (2 * g.k);
-      for (int e = lane; e < mm; e += 64) Ul[e] = U[e];
-      wave_lds_sync();
+    if (gi + 1 < g_end) {
+      nk = gates[in.gate_off + gi + 1].k;
+      nmat = gates[in.gate_off + gi + 1].mat_off;
+      if (MAT_LDS && lane < (1 << (2 * nk))) mreg = mats[nmat + lane];
     }
     switch (g.k) {
-      case 1: lds_gate<1, AMP, MAT_LDS>(S, nq, g, U, Ul, lane); break;
-      case 2: lds_gate<2, AMP, MAT_LDS>(S, nq, g, U, Ul, lane); break;
-      default: lds_gate<3, AMP, MAT_LDS>(S, nq, g, U, Ul, lane); break;
+      case 1: lds_gate<1, AMP, MAT_LDS>(S, nq, g, U, Ub, lane); break;
+      case 2: lds_gate<2, AMP, MAT_LDS>(S, nq, g, U, Ub, lane); break;
+      default: lds_gate<3, AMP, MAT_LDS>(S, nq, g, U, Ub, lane); break;
     }
-    wave_lds_sync();
   }
+  wave_lds_sync();
   for (uint32_t n = lane; n < N; n += 64) st[n] = S[n];
 }
 
 // One persistent launch over `nitems` work items.  Each wavefront owns
-// `wave_amps` amplitudes of dynamic LDS (plus 64 for a staged matrix).
+// `wave_amps` amplitudes of dynamic LDS plus two 64-entry matrix slots.
 __global__ __launch_bounds__(kBatchBlock) void batch_kernel(
     const BItem *__restrict__ items, int nitems, const BInst *__restrict__ inst,
     const BGate *__restrict__ gates, const double2 *__restrict__ mats,
@@ -96,14 +129,16 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(
   extern __shared__ double2 lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  double2 *S = lds + (size_t)wave * (wave_amps + 64);
+  double2 *S = lds + (size_t)wave * (wave_amps + 128);
   double2 *Ul = S + wave_amps;
   // The first item of every wave is static (items are ordered largest first);
   // only when items outnumber waves do waves pull more from the counter, so a
   // batch that fits the grid takes no atomics at all.
   const int waves_per_block = blockDim.x >> 6;
   const int total_waves = gridDim.x * waves_per_block;
-  int it = blockIdx.x * waves_per_block + wave;
+  // wave-uniform by construction; readfirstlane lets the compiler keep the
+  // item, instance and gate data in scalar registers
+  int it = __builtin_amdgcn_readfirstlane(blockIdx.x * waves_per_block + wave);
   while (it < nitems) {
     const BItem item = items[it];
     const BInst in = inst[item.inst];

@@ -95,7 +95,7 @@ int make_bgate(int nq, const qcw_gate &g, int64_t nmats, BGate *out) {
 
 int plan_batch_launch(int max_nq, int nitems, BatchLaunch *L) {
   const int wave_amps = 1 << std::max(max_nq, 1);
-  const size_t per_wave = (size_t)(wave_amps + 64) * sizeof(double2);
+  const size_t per_wave = (size_t)(wave_amps + 128) * sizeof(double2);
   // Each wave keeps its own LDS region; a block holds as many waves (up to
   // four) as fit in 64 KiB of dynamic LDS.
   const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kBatchBlock / 64, (64 * 1024) / per_wave));
@@ -119,8 +119,8 @@ int plan_batch_launch(int max_nq, int nitems, BatchLaunch *L) {
   return QCW_OK;
 }
 
-// Largest batch-resident instance: each wave needs (2^nq + 64) * 16 bytes of
-// LDS, 33 KiB at nq = 11.  Larger instances run as plain sweeps in the same graph.
+// Largest batch-resident instance: each wave needs (2^nq + 128) * 16 bytes of
+// LDS, 34 KiB at nq = 11.  Larger instances run as plain sweeps in the same graph.
 constexpr int kBatchResidentNq = 11;
 
 }  // namespace qcw

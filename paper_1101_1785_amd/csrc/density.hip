@@ -28,18 +28,44 @@ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -
 struct DevTerm {
   int32_t nops;
   int32_t bit0, bit1;  // bit positions (nq - qubit) of the operator qubits
-  int32_t pad;
+  int32_t coef_off;    // first coefficient of this term's table
   double weight;
-  double pad2;
+  double pad;
   double2 k0[4], k1[4];  // 2x2 operators, row-major
 };
+
+// Coefficient tables, built once on the device when a channel is created.
+// Single hit: c[(r*2 + c) * 4 + a*2 + e] = K[r][a] conj(K[c][e]), so that
+// (K rho K^dagger)_{nm} = sum_{a,e} c[...] rho_{n(a), m(e)}.  Double hit: the
+// same with r, c, a, e running over the two qubits' values (16 x 16 entries),
+// coefficient K0[r0][a0] K1[r1][a1] conj(K0[c0][e0] K1[c1][e1]).
+__global__ void channel_coef_kernel(const DevTerm *__restrict__ terms, int nterms,
+                                    double2 *__restrict__ coef) {
+  const int t = blockIdx.x;
+  if (t >= nterms) return;
+  const DevTerm &T = terms[t];
+  if (T.nops == 1) {
+    for (int i = threadIdx.x; i < 16; i += blockDim.x) {
+      const int r = i >> 3 & 1, c = i >> 2 & 1, a = i >> 1 & 1, e = i & 1;
+      coef[T.coef_off + i] = cmul(T.k0[r * 2 + a], cconj(T.k0[c * 2 + e]));
+    }
+  } else {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+      const int ri = i >> 6 & 3, ci = i >> 4 & 3, ai = i >> 2 & 3, ei = i & 3;
+      const double2 kr = cmul(T.k0[(ri >> 1) * 2 + (ai >> 1)], T.k1[(ri & 1) * 2 + (ai & 1)]);
+      const double2 kc = cmul(T.k0[(ci >> 1) * 2 + (ei >> 1)], T.k1[(ci & 1) * 2 + (ei & 1)]);
+      coef[T.coef_off + i] = cmul(kr, cconj(kc));
+    }
+  }
+}
 
 // out = p rho + sum_t w_t K_t rho K_t^dagger, one thread per output element.
 __global__ __launch_bounds__(256) void channel_kernel(const double2 *__restrict__ rho,
                                                       double2 *__restrict__ out, int nq,
                                                       double p_keep,
                                                       const DevTerm *__restrict__ terms,
-                                                      int nterms) {
+                                                      int nterms,
+                                                      const double2 *__restrict__ coef) {
   const uint64_t NN = 1ull << (2 * nq);
   const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= NN) return;
@@ -54,36 +80,32 @@ __global__ __launch_bounds__(256) void channel_kernel(const double2 *__restrict_
       const int b = T.bit0;
       const int rb = (int)((n >> b) & 1), cb = (int)((m >> b) & 1);
       const uint64_t n0 = n & ~(1ull << b), m0 = m & ~(1ull << b);
+      const double2 *C = coef + T.coef_off + (rb * 2 + cb) * 4;
+#pragma unroll
       for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c) {
-          const double2 coef = cmul(T.k0[rb * 2 + a], cconj(T.k0[cb * 2 + c]));
-          const double2 v = rho[((n0 | ((uint64_t)a << b)) << nq) | (m0 | ((uint64_t)c << b))];
-          const double2 p = cmul(coef, v);
-          acc.x += p.x;
-          acc.y += p.y;
-        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          acc = cmad(acc, C[a * 2 + e],
+                     rho[((n0 | ((uint64_t)a << b)) << nq) | (m0 | ((uint64_t)e << b))]);
     } else {
       const int b0 = T.bit0, b1 = T.bit1;
-      const int r0 = (int)((n >> b0) & 1), r1 = (int)((n >> b1) & 1);
-      const int c0 = (int)((m >> b0) & 1), c1 = (int)((m >> b1) & 1);
+      const int ri = (int)((n >> b0) & 1) * 2 + (int)((n >> b1) & 1);
+      const int ci = (int)((m >> b0) & 1) * 2 + (int)((m >> b1) & 1);
       const uint64_t clr = ~((1ull << b0) | (1ull << b1));
       const uint64_t n0 = n & clr, m0 = m & clr;
-      for (int a0 = 0; a0 < 2; ++a0)
-        for (int a1 = 0; a1 < 2; ++a1) {
-          const double2 kr = cmul(T.k0[r0 * 2 + a0], T.k1[r1 * 2 + a1]);
-          const uint64_t nn = n0 | ((uint64_t)a0 << b0) | ((uint64_t)a1 << b1);
-          for (int e0 = 0; e0 < 2; ++e0)
-            for (int e1 = 0; e1 < 2; ++e1) {
-              const double2 kc = cconj(cmul(T.k0[c0 * 2 + e0], T.k1[c1 * 2 + e1]));
-              const uint64_t mm = m0 | ((uint64_t)e0 << b0) | ((uint64_t)e1 << b1);
-              const double2 p = cmul(cmul(kr, kc), rho[(nn << nq) | mm]);
-              acc.x += p.x;
-              acc.y += p.y;
-            }
+      const double2 *C = coef + T.coef_off + (ri * 4 + ci) * 16;
+#pragma unroll
+      for (int ai = 0; ai < 4; ++ai) {
+        const uint64_t nn = n0 | ((uint64_t)(ai >> 1) << b0) | ((uint64_t)(ai & 1) << b1);
+#pragma unroll
+        for (int ei = 0; ei < 4; ++ei) {
+          const uint64_t mm = m0 | ((uint64_t)(ei >> 1) << b0) | ((uint64_t)(ei & 1) << b1);
+          acc = cmad(acc, C[ai * 4 + ei], rho[(nn << nq) | mm]);
         }
+      }
     }
-    acc_all.x += T.weight * acc.x;
-    acc_all.y += T.weight * acc.y;
+    acc_all.x = __fma_rn(T.weight, acc.x, acc_all.x);
+    acc_all.y = __fma_rn(T.weight, acc.y, acc_all.y);
   }
   out[x] = acc_all;
 }
@@ -180,6 +202,8 @@ struct qcw_channel {
   double p_keep = 0;
   int nterms = 0;
   DevTerm *terms_d = nullptr;
+  double2 *coef_d = nullptr;
+  int64_t flops_per_element = 0;  // complex multiply-adds * 8 + the weighted sums
 };
 
 extern "C" {
@@ -231,18 +255,35 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
     dt[i].bit0 = nq - t.q[0];
     dt[i].bit1 = t.nops == 2 ? nq - t.q[1] : 0;
   }
+  int64_t ncoef = 0, flops = 2;
+  for (int i = 0; i < nterms; ++i) {
+    dt[i].coef_off = (int32_t)ncoef;
+    ncoef += dt[i].nops == 1 ? 16 : 256;
+    flops += (dt[i].nops == 1 ? 4 : 16) * 8 + 4;
+  }
   qcw_channel *c = new qcw_channel();
   c->nq = nq;
   c->p_keep = p_keep;
   c->nterms = nterms;
+  c->flops_per_element = flops;
   if (nterms) {
     if (hipMalloc(&c->terms_d, sizeof(DevTerm) * nterms) != hipSuccess ||
+        hipMalloc(&c->coef_d, sizeof(double2) * ncoef) != hipSuccess ||
         hipMemcpy(c->terms_d, dt.data(), sizeof(DevTerm) * nterms, hipMemcpyHostToDevice) !=
             hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(c->terms_d);
+      (void)hipFree(c->coef_d);
       delete c;
       return fail(QCW_ENOMEM, "channel terms upload failed");
+    }
+    hipLaunchKernelGGL(channel_coef_kernel, dim3(nterms), dim3(256), 0, nullptr, c->terms_d,
+                       nterms, c->coef_d);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      (void)hipFree(c->terms_d);
+      (void)hipFree(c->coef_d);
+      delete c;
+      return fail(QCW_EHIP, "channel coefficient kernel failed");
     }
   }
   *out = c;
@@ -263,7 +304,7 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
   hipLaunchKernelGGL(channel_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                      reinterpret_cast<const double2 *>(rho_in), reinterpret_cast<double2 *>(rho_out),
-                     c->nq, c->p_keep, c->terms_d, c->nterms);
+                     c->nq, c->p_keep, c->terms_d, c->nterms, c->coef_d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(e));
   return QCW_OK;
@@ -273,10 +314,13 @@ int qcw_channel_destroy(qcw_channel *c) {
   clear_error();
   if (c) {
     (void)hipFree(c->terms_d);
+    (void)hipFree(c->coef_d);
     delete c;
   }
   return QCW_OK;
 }
+
+int64_t qcw_channel_flops_per_element(const qcw_channel *c) { return c ? c->flops_per_element : -1; }
 
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host, double *out_host,
                         void *stream) {
