@@ -129,8 +129,8 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
 
 /*
  * The same circuit with the same result, bit for bit, in fewer passes over
- * HBM: consecutive gates whose targets fit, together with the lowest 5 label
- * bits, in `tile_bits` bits (8..13; 0 = the tuned default, 12) form one pass.  A pass loads each
+ * HBM: consecutive gates whose targets fit, together with the lowest label
+ * bits (3 by default: one 128-byte line per chunk), in `tile_bits` bits (8..13; 0 = the tuned default, 12) form one pass.  A pass loads each
  * tile of 2^tile_bits amplitudes (fixed values of the other bits) into LDS,
  * applies every gate of the run there with the one-gate sweep's arithmetic,
  * and stores it back, so a run of gates costs one read and one write of the
@@ -139,8 +139,16 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
  */
 int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                       const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream);
-/* Number of passes qcw_circuit_fused makes for this gate list (host only). */
-int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits);
+/* The same with the number of contiguous low label bits every tile keeps
+ * (low_bits, 3..5; 0 = the tuned default): tiles are made of 2^low_bits-
+ * amplitude contiguous chunks, and tile_bits - low_bits <= 10 bits are left for
+ * the gates' targets. */
+int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                         const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
+                         void *stream);
+/* Number of passes qcw_circuit_fused_ex makes for this gate list (host only). */
+int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits,
+                         int low_bits);
 
 /*
  * Pick_k as computed by the device (§4a-§4c): writes (2^nq / m) * m labels to

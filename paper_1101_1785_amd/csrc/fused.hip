@@ -22,8 +22,9 @@
 
 namespace qcw {
 
-constexpr int kFusedMaxFree = 8;  // tile bits above the contiguous low bits
+constexpr int kFusedMaxFree = 10;  // tile bits above the contiguous low bits
 constexpr int kFusedDefaultTile = 12;
+constexpr int kFusedDefaultLow = 3;
 
 // Threads per block for a tile of 2^T amplitudes: eight amplitudes per thread
 // from T = 11 up, so larger tiles also get more waves for their gates.
@@ -324,8 +325,18 @@ static int launch_passes_t(qcw_c64 *psi, int nq, const FusedPass *dp, const Fuse
   return QCW_OK;
 }
 
+template <int T>
+static int launch_passes_l(int L, qcw_c64 *psi, int nq, const FusedPass *dp, const FusedGate *dg,
+                           int np, hipStream_t s) {
+  switch (L) {
+    case 3: return launch_passes_t<T, 3>(psi, nq, dp, dg, np, s);
+    case 4: return launch_passes_t<T, 4>(psi, nq, dp, dg, np, s);
+    default: return launch_passes_t<T, 5>(psi, nq, dp, dg, np, s);
+  }
+}
+
 int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, hipStream_t s) {
+              int tile_bits, int low_bits, hipStream_t s) {
   std::vector<Geom> geo(ngates);
   for (int i = 0; i < ngates; ++i) {
     int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
@@ -335,7 +346,7 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
   // Small states: the whole state is one tile; use the one-gate sweep when a
   // tile would not reach a full block of work.
   const int T = std::min(tile_bits, nq);
-  const int L = 5;
+  const int L = low_bits;
   if (T < 8 || nq < 9) {
     for (int i = 0; i < ngates; ++i) {
       int rc = launch_sweep(geo[i], mats + gates[i].mat, psi, psi, s);
@@ -383,16 +394,16 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
   const FusedGate *dg = (const FusedGate *)((char *)dev + pbytes);
   const int np = (int)passes.size();
   switch (T) {
-    case 8: return launch_passes_t<8, 5>(psi, nq, dp, dg, np, s);
-    case 9: return launch_passes_t<9, 5>(psi, nq, dp, dg, np, s);
-    case 10: return launch_passes_t<10, 5>(psi, nq, dp, dg, np, s);
-    case 11: return launch_passes_t<11, 5>(psi, nq, dp, dg, np, s);
-    case 12: return launch_passes_t<12, 5>(psi, nq, dp, dg, np, s);
-    default: return launch_passes_t<13, 5>(psi, nq, dp, dg, np, s);
+    case 8: return launch_passes_l<8>(L, psi, nq, dp, dg, np, s);
+    case 9: return launch_passes_l<9>(L, psi, nq, dp, dg, np, s);
+    case 10: return launch_passes_l<10>(L, psi, nq, dp, dg, np, s);
+    case 11: return launch_passes_l<11>(L, psi, nq, dp, dg, np, s);
+    case 12: return launch_passes_l<12>(L, psi, nq, dp, dg, np, s);
+    default: return launch_passes_l<13>(L, psi, nq, dp, dg, np, s);
   }
 }
 
-int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits) {
+int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits) {
   std::vector<Geom> geo(ngates);
   for (int i = 0; i < ngates; ++i)
     if (make_geom(nq, gates[i].k, gates[i].q, &geo[i])) return -1;
@@ -403,7 +414,7 @@ int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits) {
   std::vector<qcw_c64> zero(64);
   std::vector<qcw_gate> g0(gates, gates + ngates);
   for (auto &g : g0) g.mat = 0;
-  if (plan_passes(nq, geo, g0.data(), zero.data(), FusedShape{T, 5}, passes, fg)) return -1;
+  if (plan_passes(nq, geo, g0.data(), zero.data(), FusedShape{T, low_bits}, passes, fg)) return -1;
   return (int)passes.size();
 }
 
@@ -413,14 +424,18 @@ using namespace qcw;
 
 extern "C" {
 
-int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
-                      const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream) {
+int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                         const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
+                         void *stream) {
   clear_error();
   if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
   if (ngates < 0) return fail(QCW_EINVAL, "ngates < 0");
   if (ngates > 0 && (!gates || !mats)) return fail(QCW_EINVAL, "gates or mats is NULL");
   if (tile_bits == 0) tile_bits = kFusedDefaultTile;
+  if (low_bits == 0) low_bits = kFusedDefaultLow;
   if (tile_bits < 8 || tile_bits > 13) return fail(QCW_EINVAL, "tile_bits=%d outside [8, 13]", tile_bits);
+  if (low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree)
+    return fail(QCW_EINVAL, "low_bits=%d outside [3, 5] or too few for tile_bits=%d", low_bits, tile_bits);
   for (int i = 0; i < ngates; ++i) {
     Geom g;
     int rc = make_geom(nq, gates[i].k, gates[i].q, &g);
@@ -435,16 +450,22 @@ int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
   }
   int rc = check_device_range(psi, ((uint64_t)1 << nq) * sizeof(qcw_c64), "psi");
   if (rc) return rc;
-  return run_fused(psi, nq, gates, ngates, mats, tile_bits, (hipStream_t)stream);
+  return run_fused(psi, nq, gates, ngates, mats, tile_bits, low_bits, (hipStream_t)stream);
 }
 
-int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits) {
+int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                      const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream) {
+  return qcw_circuit_fused_ex(psi, nq, gates, ngates, mats, nmats, tile_bits, 0, stream);
+}
+
+int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits) {
   clear_error();
   if (tile_bits == 0) tile_bits = kFusedDefaultTile;
+  if (low_bits == 0) low_bits = kFusedDefaultLow;
   if (nq < 1 || nq > kMaxQubits || ngates < 0 || (ngates > 0 && !gates) || tile_bits < 8 ||
-      tile_bits > 13)
+      tile_bits > 13 || low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree)
     return fail(QCW_EINVAL, "invalid arguments");
-  int n = fused_pass_count(nq, gates, ngates, tile_bits);
+  int n = fused_pass_count(nq, gates, ngates, tile_bits, low_bits);
   return n < 0 ? fail(QCW_EINVAL, "invalid gate") : n;
 }
 

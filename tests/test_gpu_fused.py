@@ -25,10 +25,10 @@ def L():
     return _lib
 
 
-def _run(L, psi0, c, fused, tile_bits=0):
+def _run(L, psi0, c, fused, tile_bits=0, low_bits=0):
     psi = torch.from_numpy(psi0).to("cuda")
     if fused:
-        L.circuit_fused(psi, c, tile_bits)
+        L.circuit_fused(psi, c, tile_bits, low_bits=low_bits)
     else:
         L.circuit(psi, c)
     torch.cuda.synchronize()
@@ -36,12 +36,13 @@ def _run(L, psi0, c, fused, tile_bits=0):
 
 
 @pytest.mark.parametrize("nq", [9, 10, 12, 14, 18, 22])
-@pytest.mark.parametrize("tile_bits", [8, 10, 12])
-def test_fused_equals_plain_bitwise(L, nq, tile_bits):
-    print(f"[gpu] fused nq={nq} tile_bits={tile_bits}", flush=True)
+@pytest.mark.parametrize("tile_bits,low_bits", [(8, 5), (10, 5), (12, 5), (11, 3), (12, 3),
+                                                (13, 3), (13, 4), (12, 4)])
+def test_fused_equals_plain_bitwise(L, nq, tile_bits, low_bits):
+    print(f"[gpu] fused nq={nq} tile_bits={tile_bits} low_bits={low_bits}", flush=True)
     psi0 = qi.state(11, nq, tag=tile_bits)
     c = qi.circuit(11, nq, 4 * nq, tag=tile_bits)
-    a = _run(L, psi0, c, True, tile_bits)
+    a = _run(L, psi0, c, True, tile_bits, low_bits)
     b = _run(L, psi0, c, False)
     assert np.array_equal(a, b)
     if nq <= 18:
