@@ -142,10 +142,11 @@ int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
 /* The same with the number of contiguous low label bits every tile keeps
  * (low_bits, 3..5; 0 = the tuned default): tiles are made of 2^low_bits-
  * amplitude contiguous chunks, and tile_bits - low_bits <= 10 bits are left for
- * the gates' targets. */
+ * the gates' targets; and the threads per tile (256, 512 or 1024 for
+ * tile_bits >= 12; 0 = the tuned default). */
 int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
-                         void *stream);
+                         int threads, void *stream);
 /* Number of passes qcw_circuit_fused_ex makes for this gate list (host only). */
 int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits,
                          int low_bits);

@@ -65,7 +65,7 @@ _SIGS = {
     "qcw_omega_all": ([_P, _P, _i32, _P], _i32),
     "qcw_circuit": ([_P, _i32, _P, _i32, _P, _i64, _P], _i32),
     "qcw_circuit_fused": ([_P, _i32, _P, _i32, _P, _i64, _i32, _P], _i32),
-    "qcw_circuit_fused_ex": ([_P, _i32, _P, _i32, _P, _i64, _i32, _i32, _P], _i32),
+    "qcw_circuit_fused_ex": ([_P, _i32, _P, _i32, _P, _i64, _i32, _i32, _i32, _P], _i32),
     "qcw_fused_pass_count": ([_i32, _P, _i32, _i32, _i32], _i32),
     "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),
     "qcw_batch_create": ([_P, _P, _i32, _P, _i64, _P, _i64, _P, _i64, ctypes.c_char_p, _P], _i32),
@@ -229,17 +229,17 @@ def qcw_circuit_fused(psi, nq, gates, ngates, mats, nmats, tile_bits=0, stream=N
 
 
 def qcw_circuit_fused_ex(psi, nq, gates, ngates, mats, nmats, tile_bits=0, low_bits=0,
-                         stream=None):
+                         threads=0, stream=None):
     _check(_L.qcw_circuit_fused_ex(_dptr(psi), int(nq), _hptr(gates), int(ngates), _hptr(mats),
-                                   int(nmats), int(tile_bits), int(low_bits), _stream(stream)),
-           "qcw_circuit_fused_ex")
+                                   int(nmats), int(tile_bits), int(low_bits), int(threads),
+                                   _stream(stream)), "qcw_circuit_fused_ex")
 
 
-def circuit_fused(psi, circ, tile_bits=0, stream=None, low_bits=0):
+def circuit_fused(psi, circ, tile_bits=0, stream=None, low_bits=0, threads=0):
     """Apply a qcw_inputs.Circuit in place with qcw_circuit_fused_ex."""
     gates, mats = pack_circuit(circ)
     qcw_circuit_fused_ex(psi, circ.nq, gates, len(circ), mats, mats.size, tile_bits, low_bits,
-                         stream)
+                         threads, stream)
 
 
 def qcw_fused_pass_count(nq, gates, ngates, tile_bits=0, low_bits=0):

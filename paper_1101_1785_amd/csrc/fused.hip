@@ -281,18 +281,17 @@ std::mutex g_plan_mu;
 std::unordered_map<hipStream_t, PlanBuf> g_plan_bufs;
 }  // namespace
 
-template <int T, int L>
+template <int T, int L, int NT>
 static int launch_passes_t(qcw_c64 *psi, int nq, const FusedPass *dp, const FusedGate *dg,
                            int npass, hipStream_t s) {
   const size_t lds = sizeof(double2) << T;
   const uint64_t ntiles = 1ull << (nq - T);
-  constexpr int NT = fused_block(T);
   // 2^13-amplitude tiles fill a CU's LDS with one block, so they run as
   // persistent pipelined blocks; smaller tiles rely on several resident blocks
   // per CU to overlap loads, LDS work and stores (measured faster for them).
   constexpr bool persistent = T >= 13;
-  const void *fn = persistent ? (const void *)fused_persistent_kernel<T, L>
-                              : (const void *)fused_pass_kernel<T, L>;
+  const void *fn = persistent ? (const void *)fused_persistent_kernel<T, L, NT>
+                              : (const void *)fused_pass_kernel<T, L, NT>;
   static unsigned grid = 0;  // once per process and template instance
   if (!grid) {
     if (lds > 64 * 1024) {
@@ -313,10 +312,10 @@ static int launch_passes_t(qcw_c64 *psi, int nq, const FusedPass *dp, const Fuse
     TimedLaunch t(QCW_KERNEL_FUSED, s);
     if (persistent) {
       const unsigned blocks = (unsigned)std::min<uint64_t>(grid, ntiles);
-      hipLaunchKernelGGL((fused_persistent_kernel<T, L>), dim3(blocks), dim3(NT), lds, s,
+      hipLaunchKernelGGL((fused_persistent_kernel<T, L, NT>), dim3(blocks), dim3(NT), lds, s,
                          reinterpret_cast<double2 *>(psi), dp, dg, p, ntiles);
     } else {
-      hipLaunchKernelGGL((fused_pass_kernel<T, L>), dim3((unsigned)ntiles), dim3(NT), lds, s,
+      hipLaunchKernelGGL((fused_pass_kernel<T, L, NT>), dim3((unsigned)ntiles), dim3(NT), lds, s,
                          reinterpret_cast<double2 *>(psi), dp, dg, p);
     }
     hipError_t e = hipGetLastError();
@@ -325,18 +324,31 @@ static int launch_passes_t(qcw_c64 *psi, int nq, const FusedPass *dp, const Fuse
   return QCW_OK;
 }
 
-template <int T>
+template <int T, int NT>
 static int launch_passes_l(int L, qcw_c64 *psi, int nq, const FusedPass *dp, const FusedGate *dg,
                            int np, hipStream_t s) {
   switch (L) {
-    case 3: return launch_passes_t<T, 3>(psi, nq, dp, dg, np, s);
-    case 4: return launch_passes_t<T, 4>(psi, nq, dp, dg, np, s);
-    default: return launch_passes_t<T, 5>(psi, nq, dp, dg, np, s);
+    case 3: return launch_passes_t<T, 3, NT>(psi, nq, dp, dg, np, s);
+    case 4: return launch_passes_t<T, 4, NT>(psi, nq, dp, dg, np, s);
+    default: return launch_passes_t<T, 5, NT>(psi, nq, dp, dg, np, s);
+  }
+}
+
+// Block size per tile size: 256 threads below 2^12 amplitudes; for 2^12 and
+// 2^13, 256 / 512 / 1024 threads (threads = 0 picks the tuned default).
+template <int T>
+static int launch_passes_n(int threads, int L, qcw_c64 *psi, int nq, const FusedPass *dp,
+                           const FusedGate *dg, int np, hipStream_t s) {
+  if (threads == 0) threads = fused_block(T);
+  switch (threads) {
+    case 1024: return launch_passes_l<T, 1024>(L, psi, nq, dp, dg, np, s);
+    case 512: return launch_passes_l<T, 512>(L, psi, nq, dp, dg, np, s);
+    default: return launch_passes_l<T, 256>(L, psi, nq, dp, dg, np, s);
   }
 }
 
 int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, int low_bits, hipStream_t s) {
+              int tile_bits, int low_bits, int threads, hipStream_t s) {
   std::vector<Geom> geo(ngates);
   for (int i = 0; i < ngates; ++i) {
     int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
@@ -394,12 +406,12 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
   const FusedGate *dg = (const FusedGate *)((char *)dev + pbytes);
   const int np = (int)passes.size();
   switch (T) {
-    case 8: return launch_passes_l<8>(L, psi, nq, dp, dg, np, s);
-    case 9: return launch_passes_l<9>(L, psi, nq, dp, dg, np, s);
-    case 10: return launch_passes_l<10>(L, psi, nq, dp, dg, np, s);
-    case 11: return launch_passes_l<11>(L, psi, nq, dp, dg, np, s);
-    case 12: return launch_passes_l<12>(L, psi, nq, dp, dg, np, s);
-    default: return launch_passes_l<13>(L, psi, nq, dp, dg, np, s);
+    case 8: return launch_passes_l<8, 256>(L, psi, nq, dp, dg, np, s);
+    case 9: return launch_passes_l<9, 256>(L, psi, nq, dp, dg, np, s);
+    case 10: return launch_passes_l<10, 256>(L, psi, nq, dp, dg, np, s);
+    case 11: return launch_passes_l<11, 256>(L, psi, nq, dp, dg, np, s);
+    case 12: return launch_passes_n<12>(threads, L, psi, nq, dp, dg, np, s);
+    default: return launch_passes_n<13>(threads, L, psi, nq, dp, dg, np, s);
   }
 }
 
@@ -426,7 +438,7 @@ extern "C" {
 
 int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
-                         void *stream) {
+                         int threads, void *stream) {
   clear_error();
   if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
   if (ngates < 0) return fail(QCW_EINVAL, "ngates < 0");
@@ -436,6 +448,8 @@ int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates
   if (tile_bits < 8 || tile_bits > 13) return fail(QCW_EINVAL, "tile_bits=%d outside [8, 13]", tile_bits);
   if (low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree)
     return fail(QCW_EINVAL, "low_bits=%d outside [3, 5] or too few for tile_bits=%d", low_bits, tile_bits);
+  if (threads != 0 && !((threads == 256 || threads == 512 || threads == 1024) && tile_bits >= 12))
+    return fail(QCW_EINVAL, "threads=%d: 256, 512 or 1024 with tile_bits >= 12, or 0", threads);
   for (int i = 0; i < ngates; ++i) {
     Geom g;
     int rc = make_geom(nq, gates[i].k, gates[i].q, &g);
@@ -450,12 +464,12 @@ int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates
   }
   int rc = check_device_range(psi, ((uint64_t)1 << nq) * sizeof(qcw_c64), "psi");
   if (rc) return rc;
-  return run_fused(psi, nq, gates, ngates, mats, tile_bits, low_bits, (hipStream_t)stream);
+  return run_fused(psi, nq, gates, ngates, mats, tile_bits, low_bits, threads, (hipStream_t)stream);
 }
 
 int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                       const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream) {
-  return qcw_circuit_fused_ex(psi, nq, gates, ngates, mats, nmats, tile_bits, 0, stream);
+  return qcw_circuit_fused_ex(psi, nq, gates, ngates, mats, nmats, tile_bits, 0, 0, stream);
 }
 
 int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits) {

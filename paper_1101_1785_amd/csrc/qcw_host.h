@@ -31,7 +31,7 @@ int launch_sweep(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *ou
 int launch_pick(const Geom &g, uint64_t *labels_dev, hipStream_t s);
 // Fused passes (fused.hip).
 int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, int low_bits, hipStream_t s);
+              int tile_bits, int low_bits, int threads, hipStream_t s);
 int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits);
 
 }  // namespace qcw

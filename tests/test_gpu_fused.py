@@ -50,6 +50,18 @@ def test_fused_equals_plain_bitwise(L, nq, tile_bits, low_bits):
         assert np.linalg.norm(a - r) <= TOL * max(1, len(c) / 64) * np.linalg.norm(r)
 
 
+@pytest.mark.parametrize("tile_bits,low_bits,threads", [(12, 3, 256), (12, 3, 1024), (13, 3, 512),
+                                                        (13, 5, 1024)])
+def test_fused_threads_per_tile(L, tile_bits, low_bits, threads):
+    nq = 17
+    psi0 = qi.state(12, nq)
+    c = qi.circuit(12, nq, 4 * nq)
+    psi = torch.from_numpy(psi0).to("cuda")
+    L.circuit_fused(psi, c, tile_bits, low_bits=low_bits, threads=threads)
+    torch.cuda.synchronize()
+    assert np.array_equal(psi.cpu().numpy(), _run(L, psi0, c, False))
+
+
 def test_fused_fewer_passes(L):
     c = qi.circuit(1, 31, 124)
     g, m = L.pack_circuit(c)
@@ -91,6 +103,8 @@ def test_fused_validation(L):
     bad[1]["q"][0] = 11
     with pytest.raises(L.QcwError, match="gate 1"):
         L.qcw_circuit_fused(psi, 10, bad, len(c), m, m.size)
+    with pytest.raises(L.QcwError, match="threads"):
+        L.qcw_circuit_fused_ex(psi, 10, g, len(c), m, m.size, 11, 3, 1024)
     L.qcw_circuit_fused(psi, 10, g, 0, m, m.size)          # empty circuit is a no-op
 
 
