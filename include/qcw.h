@@ -130,7 +130,7 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
 /*
  * The same circuit with the same result, bit for bit, in fewer passes over
  * HBM: consecutive gates whose targets fit, together with the lowest label
- * bits (3 by default: one 128-byte line per chunk), in `tile_bits` bits (8..13; 0 = the tuned default, 12) form one pass.  A pass loads each
+ * bits (4 by default: 256-byte chunks), in `tile_bits` bits (8..13; 0 = the tuned default, 12) form one pass.  A pass loads each
  * tile of 2^tile_bits amplitudes (fixed values of the other bits) into LDS,
  * applies every gate of the run there with the one-gate sweep's arithmetic,
  * and stores it back, so a run of gates costs one read and one write of the
@@ -142,8 +142,9 @@ int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
 /* The same with the number of contiguous low label bits every tile keeps
  * (low_bits, 3..5; 0 = the tuned default): tiles are made of 2^low_bits-
  * amplitude contiguous chunks, and tile_bits - low_bits <= 10 bits are left for
- * the gates' targets; and the threads per tile (256, 512 or 1024 for
- * tile_bits >= 12; 0 = the tuned default). */
+ * the gates' targets; and the threads per tile (256 or 512 for tile_bits 11;
+ * 256, 512 or 1024 for 12 and 13, where 12 with 1024 is a warp-specialised
+ * pipelined kernel; 0 = the tuned default). */
 int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
                          int threads, void *stream);

@@ -24,7 +24,7 @@ namespace qcw {
 
 constexpr int kFusedMaxFree = 10;  // tile bits above the contiguous low bits
 constexpr int kFusedDefaultTile = 12;
-constexpr int kFusedDefaultLow = 3;
+constexpr int kFusedDefaultLow = 4;
 
 // Threads per block for a tile of 2^T amplitudes: eight amplitudes per thread
 // from T = 11 up, so larger tiles also get more waves for their gates.
@@ -49,17 +49,34 @@ struct alignas(16) FusedPass {
 
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-template <int K, int NT>
-__device__ __forceinline__ void tile_gate(double2 *S, int T, const FusedGate &g) {
+// One gate on a tile of 2^T amplitudes in LDS, NT threads.  Each thread owns
+// 2^(T-K) / NT groups (fixed at compile time) and issues the LDS reads of all
+// of them before any arithmetic, so several reads are in flight per lane.
+template <int K, int NT, int T>
+__device__ __forceinline__ void tile_gate(double2 *S, const FusedGate &g) {
   constexpr int M = 1 << K;
-  const uint32_t ngroups = 1u << (T - K);
-  for (uint32_t j = threadIdx.x; j < ngroups; j += NT) {
-    const uint32_t base = insert_zeros<K, uint32_t>(j, g.sb0, g.sb1, g.sb2);
-    double2 x[M];
+  constexpr uint32_t NG = 1u << (T - K);
+  constexpr int G = NG >= NT ? (int)(NG / NT) : 1;
+  const uint32_t tid = threadIdx.x % NT;
+  double2 x[G][M];
+  uint32_t base[G];
 #pragma unroll
-    for (int r = 0; r < M; ++r) x[r] = S[base + g.off[r]];
-    group_matvec_put<M>(x, [&](int r, int c) { return g.u[r * M + c]; },
-                        [&](int r, double2 y) { S[base + g.off[r]] = y; });
+  for (int i = 0; i < G; ++i) {
+    const uint32_t j = i * NT + tid;
+    base[i] = insert_zeros<K, uint32_t>(j, g.sb0, g.sb1, g.sb2);
+    if (NG >= NT || j < NG) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) x[i][r] = S[base[i] + g.off[r]];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    const uint32_t j = i * NT + tid;
+    if (NG >= NT || j < NG) {
+      const uint32_t b = base[i];
+      group_matvec_put<M>(x[i], [&](int r, int c) { return g.u[r * M + c]; },
+                          [&](int r, double2 y) { S[b + g.off[r]] = y; });
+    }
   }
 }
 
@@ -96,9 +113,9 @@ __global__ __launch_bounds__(NT) void fused_pass_kernel(double2 *psi,
   for (int gi = 0; gi < P.ngates; ++gi) {
     const FusedGate &g = gates[P.gate_off + gi];
     switch (g.k) {
-      case 1: tile_gate<1, NT>(S, T, g); break;
-      case 2: tile_gate<2, NT>(S, T, g); break;
-      default: tile_gate<3, NT>(S, T, g); break;
+      case 1: tile_gate<1, NT, T>(S, g); break;
+      case 2: tile_gate<2, NT, T>(S, g); break;
+      default: tile_gate<3, NT, T>(S, g); break;
     }
     __syncthreads();
   }
@@ -157,9 +174,9 @@ __global__ __launch_bounds__(NT) void fused_persistent_kernel(double2 *psi,
     for (int gi = 0; gi < P.ngates; ++gi) {
       const FusedGate &g = gates[P.gate_off + gi];
       switch (g.k) {
-        case 1: tile_gate<1, NT>(S, T, g); break;
-        case 2: tile_gate<2, NT>(S, T, g); break;
-        default: tile_gate<3, NT>(S, T, g); break;
+        case 1: tile_gate<1, NT, T>(S, g); break;
+        case 2: tile_gate<2, NT, T>(S, g); break;
+        default: tile_gate<3, NT, T>(S, g); break;
       }
       __syncthreads();
     }
@@ -173,6 +190,111 @@ __global__ __launch_bounds__(NT) void fused_persistent_kernel(double2 *psi,
     __syncthreads();  // every thread has read its part of S before it is refilled
     t = tn;
     base = base_n;
+  }
+}
+
+// LDS-only block barrier: waits for this wave's LDS operations, then the
+// workgroup barrier.  Outstanding global loads stay in flight across it (a
+// full __syncthreads would also wait for them).  The memory clobber keeps the
+// compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Warp-specialised persistent pass for 2^12-amplitude tiles: 1024 threads per
+// block, one block per CU, two LDS tile buffers.  Threads 0..511 apply the
+// run of gates to the tile in one buffer; threads 512..1023 meanwhile store
+// the previous tile from the other buffer and load the next tile into it.
+// Both halves pass the same barriers (one per gate); the loading half writes
+// its registers into LDS only in the last gate interval, so its loads are in
+// flight during the whole compute phase.
+template <int L>
+__global__ __launch_bounds__(1024) void fused_ws_kernel(double2 *psi,
+                                                        const FusedPass *__restrict__ passes,
+                                                        const FusedGate *__restrict__ gates,
+                                                        int p, uint64_t ntiles) {
+  constexpr int T = 12;
+  constexpr int NC = 512;                 // compute threads
+  constexpr int PER = (1 << T) / 512;     // amplitudes per memory thread
+  extern __shared__ double2 S2[];
+  const FusedPass &P = passes[p];
+  const bool mem = threadIdx.x >= NC;
+  const int tm = threadIdx.x - NC;        // memory-thread index (valid when mem)
+  // tiles of this block: blockIdx.x, blockIdx.x + gridDim.x, ...
+  if ((uint64_t)blockIdx.x >= ntiles) return;
+  const uint64_t n_it = (ntiles - 1 - blockIdx.x) / gridDim.x + 1;
+  auto base_of = [&](uint64_t t) {
+    uint64_t b = 0;
+    for (int j = 0; j < P.n_outer; ++j) b |= ((t >> j) & 1ull) << P.outer_pos[j];
+    return b;
+  };
+  uint64_t lab[PER];
+  if (mem) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = q * 512 + tm;
+      lab[q] = P.chunk_off[i >> L] + (uint32_t)(i & ((1 << L) - 1));
+    }
+  }
+  const int ng = P.ngates;
+  v2d w[PER];
+  uint64_t base_next = 0;
+  if (mem) {
+    const uint64_t b0 = base_of(blockIdx.x);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      w[q] = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(psi + b0 + lab[q]));
+      S2[q * 512 + tm] = make_double2(w[q].x, w[q].y);
+    }
+  }
+  lds_barrier();
+  uint64_t base_prev = 0, base_cur = base_of(blockIdx.x);
+  for (uint64_t it = 0; it < n_it; ++it) {
+    double2 *X = S2 + ((it & 1) << T);
+    double2 *Y = S2 + (((it + 1) & 1) << T);
+    const bool has_next = it + 1 < n_it;
+    if (mem) {
+      if (it > 0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const double2 a = Y[q * 512 + tm];
+          v2d o = {a.x, a.y};
+          __builtin_nontemporal_store(o, reinterpret_cast<v2d *>(psi + base_prev + lab[q]));
+        }
+      }
+      if (has_next) {
+        base_next = base_of(blockIdx.x + (it + 1) * gridDim.x);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+          w[q] = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(psi + base_next + lab[q]));
+      }
+    }
+    for (int gi = 0; gi < ng; ++gi) {
+      if (!mem) {
+        const FusedGate &g = gates[P.gate_off + gi];
+        switch (g.k) {
+          case 1: tile_gate<1, NC, T>(X, g); break;
+          case 2: tile_gate<2, NC, T>(X, g); break;
+          default: tile_gate<3, NC, T>(X, g); break;
+        }
+      } else if (gi == ng - 1 && has_next) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) Y[q * 512 + tm] = make_double2(w[q].x, w[q].y);
+      }
+      lds_barrier();
+    }
+    base_prev = base_cur;
+    base_cur = base_next;
+  }
+  // the last tile, finished in buffer (n_it - 1) & 1
+  if (mem) {
+    const double2 *Z = S2 + (((n_it - 1) & 1) << T);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const double2 a = Z[q * 512 + tm];
+      v2d o = {a.x, a.y};
+      __builtin_nontemporal_store(o, reinterpret_cast<v2d *>(psi + base_prev + lab[q]));
+    }
   }
 }
 
@@ -334,12 +456,52 @@ static int launch_passes_l(int L, qcw_c64 *psi, int nq, const FusedPass *dp, con
   }
 }
 
+template <int L>
+static int launch_ws(qcw_c64 *psi, int nq, const FusedPass *dp, const FusedGate *dg, int npass,
+                     hipStream_t s) {
+  constexpr int T = 12;
+  const size_t lds = 2 * (sizeof(double2) << T);
+  const uint64_t ntiles = 1ull << (nq - T);
+  static unsigned grid = 0;
+  if (!grid) {
+    const void *fn = (const void *)fused_ws_kernel<L>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return fail(QCW_EHIP, "LDS of %zu B per block: %s", lds, hipGetErrorString(e));
+    int bpc = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, fn, 1024, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(QCW_EHIP, "fused occupancy query failed");
+    }
+    if (bpc < 1) return fail(QCW_EHIP, "warp-specialised fused kernel does not fit a CU");
+    grid = (unsigned)(bpc * ncu);
+  }
+  const unsigned blocks = (unsigned)std::min<uint64_t>(grid, ntiles);
+  for (int p = 0; p < npass; ++p) {
+    TimedLaunch t(QCW_KERNEL_FUSED, s);
+    hipLaunchKernelGGL((fused_ws_kernel<L>), dim3(blocks), dim3(1024), lds, s,
+                       reinterpret_cast<double2 *>(psi), dp, dg, p, ntiles);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(QCW_EHIP, "fused launch: %s", hipGetErrorString(e));
+  }
+  return QCW_OK;
+}
+
 // Block size per tile size: 256 threads below 2^12 amplitudes; for 2^12 and
-// 2^13, 256 / 512 / 1024 threads (threads = 0 picks the tuned default).
+// 2^13, 256 / 512 / 1024 threads (threads = 0 picks the tuned default); for
+// 2^12, threads = 1024 is the warp-specialised pipelined kernel.
 template <int T>
 static int launch_passes_n(int threads, int L, qcw_c64 *psi, int nq, const FusedPass *dp,
                            const FusedGate *dg, int np, hipStream_t s) {
   if (threads == 0) threads = fused_block(T);
+  if (T == 12 && threads == 1024) {
+    switch (L) {
+      case 3: return launch_ws<3>(psi, nq, dp, dg, np, s);
+      case 4: return launch_ws<4>(psi, nq, dp, dg, np, s);
+      default: return launch_ws<5>(psi, nq, dp, dg, np, s);
+    }
+  }
   switch (threads) {
     case 1024: return launch_passes_l<T, 1024>(L, psi, nq, dp, dg, np, s);
     case 512: return launch_passes_l<T, 512>(L, psi, nq, dp, dg, np, s);
@@ -409,7 +571,9 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
     case 8: return launch_passes_l<8, 256>(L, psi, nq, dp, dg, np, s);
     case 9: return launch_passes_l<9, 256>(L, psi, nq, dp, dg, np, s);
     case 10: return launch_passes_l<10, 256>(L, psi, nq, dp, dg, np, s);
-    case 11: return launch_passes_l<11, 256>(L, psi, nq, dp, dg, np, s);
+    case 11:
+      if (threads == 512) return launch_passes_l<11, 512>(L, psi, nq, dp, dg, np, s);
+      return launch_passes_l<11, 256>(L, psi, nq, dp, dg, np, s);
     case 12: return launch_passes_n<12>(threads, L, psi, nq, dp, dg, np, s);
     default: return launch_passes_n<13>(threads, L, psi, nq, dp, dg, np, s);
   }
@@ -448,8 +612,9 @@ int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates
   if (tile_bits < 8 || tile_bits > 13) return fail(QCW_EINVAL, "tile_bits=%d outside [8, 13]", tile_bits);
   if (low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree)
     return fail(QCW_EINVAL, "low_bits=%d outside [3, 5] or too few for tile_bits=%d", low_bits, tile_bits);
-  if (threads != 0 && !((threads == 256 || threads == 512 || threads == 1024) && tile_bits >= 12))
-    return fail(QCW_EINVAL, "threads=%d: 256, 512 or 1024 with tile_bits >= 12, or 0", threads);
+  if (threads != 0 && !((threads == 256 || threads == 512 || threads == 1024) && tile_bits >= 12) &&
+      !((threads == 256 || threads == 512) && tile_bits == 11))
+    return fail(QCW_EINVAL, "threads=%d: 256/512 (tile_bits 11), 256/512/1024 (12, 13), or 0", threads);
   for (int i = 0; i < ngates; ++i) {
     Geom g;
     int rc = make_geom(nq, gates[i].k, gates[i].q, &g);

@@ -50,10 +50,12 @@ def test_fused_equals_plain_bitwise(L, nq, tile_bits, low_bits):
         assert np.linalg.norm(a - r) <= TOL * max(1, len(c) / 64) * np.linalg.norm(r)
 
 
-@pytest.mark.parametrize("tile_bits,low_bits,threads", [(12, 3, 256), (12, 3, 1024), (13, 3, 512),
-                                                        (13, 5, 1024)])
-def test_fused_threads_per_tile(L, tile_bits, low_bits, threads):
-    nq = 17
+@pytest.mark.parametrize("tile_bits,low_bits,threads", [(12, 3, 256), (12, 3, 1024), (12, 5, 1024),
+                                                        (12, 4, 1024), (13, 3, 512), (13, 5, 1024)])
+@pytest.mark.parametrize("nq", [12, 13, 17, 21])
+def test_fused_threads_per_tile(L, tile_bits, low_bits, threads, nq):
+    """Every block shape, including the warp-specialised pipelined kernel
+    (tile_bits = 12, threads = 1024): one tile, a few tiles per block, and many."""
     psi0 = qi.state(12, nq)
     c = qi.circuit(12, nq, 4 * nq)
     psi = torch.from_numpy(psi0).to("cuda")
