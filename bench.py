@@ -279,6 +279,15 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
     ms = e0.elapsed_time(e1) / steps
     n, cms = L.qcw_timing_read(L.QCW_KERNEL_CHANNEL)
     ob = L.qcw_rho_observables(x, psi0=psi0)
+    spectral = {}
+    if nq <= 6:
+        ev, S = L.qcw_rho_eigvals(x)
+        rho0 = torch.from_numpy(np.outer(psi0, psi0.conj()).reshape(-1)).to("cuda")
+        t0 = time.perf_counter()
+        F = L.qcw_rho_fidelity(x, rho0)
+        spectral = {"entropy_bits_after": S, "max_eigenvalue_after": float(ev[-1]),
+                    "general_fidelity_after": F,
+                    "fidelity_call_ms": (time.perf_counter() - t0) * 1e3}
     NN = 1 << (2 * nq)
     fl = ch.flops_per_element() * NN
     cavg = cms / max(n, 1)
@@ -288,7 +297,7 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
             "channel_fp64_frac": fl / (cavg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
             "channel_flops_per_element": ch_flops if (ch_flops := fl // NN) else None,
             "trace_after": ob["trace"].real, "purity_after": ob["purity"],
-            "fidelity_after": ob["fidelity"]}
+            "fidelity_after": ob["fidelity"], **spectral}
 
 
 def bench_plain_small(torch, L, qi, nq, seed, reps=2000):

@@ -271,6 +271,28 @@ int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
 
 /*
+ * Eigenvalue-based observables (§5, classical-limit discussion), for
+ * nq <= 6 (a 64 x 64 rho, the paper's examples use 1, 2 and 5 qubits), by a
+ * parallel cyclic Jacobi eigensolver in one workgroup.  Both calls are
+ * synchronous and take the Hermitian part (rho + rho^dagger) / 2.
+ *
+ * qcw_rho_eigvals writes 2^nq + 1 doubles to out_host: the eigenvalues in
+ * ascending order, then the von Neumann entropy -sum lambda log2 lambda in
+ * bits (over lambda > 0; in the classical limit it tends to nq).
+ * qcw_rho_fidelity writes F = Tr sqrt(sqrt(rho0) rho sqrt(rho0)) (the root
+ * fidelity, 1/sqrt2 after one Hadamard on |0>) for a general rho0.
+ * qcw_rho_partial_trace (asynchronous) writes the reduced density matrix of
+ * the nkeep qubits keep[] (1-based, distinct) to the device array out
+ * (2^nkeep x 2^nkeep, the lowest-numbered kept qubit most significant), for
+ * subsystem entropies and eigenvalues.
+ */
+int qcw_rho_eigvals(const qcw_c64 *rho, int nq, double *out_host, void *stream);
+int qcw_rho_fidelity(const qcw_c64 *rho, const qcw_c64 *rho0, int nq, double *out_host,
+                     void *stream);
+int qcw_rho_partial_trace(const qcw_c64 *rho, int nq, const int *keep, int nkeep, qcw_c64 *out,
+                          void *stream);
+
+/*
  * Serving: a continuous-batching request loop on one GPU.  Requests (one
  * instance each: a state of nq <= cfg.max_nq <= 11 qubits and its circuit)
  * are submitted from any thread; a scheduler thread admits them in arrival

@@ -110,3 +110,17 @@ def fidelity_general(rho, rho0) -> float:
     m = s @ rho @ s
     ev = np.linalg.eigvalsh((m + m.conj().T) / 2)
     return float(np.sum(np.sqrt(np.clip(ev, 0, None))))
+
+
+def partial_trace(rho, keep) -> np.ndarray:
+    """Reduced density matrix of the qubits `keep` (1-based), kept in qubit order:
+    the traced qubits' row and column indices are summed together."""
+    nq = _nq(rho)
+    keep = sorted(keep)
+    letters = "abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ"
+    rows = [letters[q - 1] for q in range(1, nq + 1)]
+    cols = [letters[nq + q - 1] if q in keep else letters[q - 1] for q in range(1, nq + 1)]
+    out = [letters[q - 1] for q in keep] + [letters[nq + q - 1] for q in keep]
+    T = np.einsum("".join(rows + cols) + "->" + "".join(out), rho.reshape((2,) * (2 * nq)))
+    nk = len(keep)
+    return T.reshape(1 << nk, 1 << nk)

@@ -81,6 +81,9 @@ _SIGS = {
     "qcw_channel_destroy": ([_P], _i32),
     "qcw_channel_flops_per_element": ([_P], _i64),
     "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
+    "qcw_rho_eigvals": ([_P, _i32, _P, _P], _i32),
+    "qcw_rho_fidelity": ([_P, _P, _i32, _P, _P], _i32),
+    "qcw_rho_partial_trace": ([_P, _i32, _P, _i32, _P, _P], _i32),
     "qcw_server_create": ([_P, _P], _i32),
     "qcw_server_submit": ([_P, _P, _P], _i32),
     "qcw_server_poll": ([_P, ctypes.c_uint64, _P, _P], _i32),
@@ -556,3 +559,29 @@ def qcw_rho_observables(rho, nq=None, psi0=None, stream=None):
                                   _hptr(out), _stream(stream)), "qcw_rho_observables")
     return {"trace": complex(out[0], out[1]), "purity": float(out[2]),
             "fidelity": float(out[3]), "polarization": out[4:].reshape(nq, 3)}
+
+
+def qcw_rho_eigvals(rho, nq=None, stream=None):
+    """(eigenvalues ascending, entropy in bits)."""
+    nq = _rho_nq(rho, nq)
+    out = np.empty((1 << nq) + 1, dtype=np.float64)
+    _check(_L.qcw_rho_eigvals(_dptr(rho), nq, _hptr(out), _stream(stream)), "qcw_rho_eigvals")
+    return out[:-1], float(out[-1])
+
+
+def qcw_rho_fidelity(rho, rho0, nq=None, stream=None):
+    nq = _rho_nq(rho, nq)
+    out = np.empty(1, dtype=np.float64)
+    _check(_L.qcw_rho_fidelity(_dptr(rho), _dptr(rho0), nq, _hptr(out), _stream(stream)),
+           "qcw_rho_fidelity")
+    return float(out[0])
+
+
+def qcw_rho_partial_trace(rho, keep, nq=None, stream=None):
+    import torch
+    nq = _rho_nq(rho, nq)
+    k = np.ascontiguousarray(keep, dtype=np.int32)
+    out = torch.empty(1 << (2 * len(keep)), dtype=torch.complex128, device=rho.device)
+    _check(_L.qcw_rho_partial_trace(_dptr(rho), nq, _hptr(k), len(keep), _dptr(out),
+                                    _stream(stream)), "qcw_rho_partial_trace")
+    return out

@@ -144,3 +144,35 @@ def test_planted_transpose_mistake_caught():
     Py = lambda r: np.real(np.trace(D.SY @ r))
     assert abs(Py(good) - 0.4) <= 8 * EPS            # Y hits keep P_y
     assert abs(Py(bad) - 0.4) > 0.1
+
+
+def test_partial_trace_pins():
+    """Tracing out one qubit of a product state leaves the other factor; of a
+    Bell state, the maximally mixed 1/2 (entropy 1 bit)."""
+    rng = np.random.default_rng(8)
+    a, b = _rand_rho(rng, 1, 2), _rand_rho(rng, 2, 2)
+    prod = np.kron(a, b)                                  # qubit 1 x qubits 2, 3
+    assert np.max(np.abs(D.partial_trace(prod, [1]) - a)) <= 1e-15
+    assert np.max(np.abs(D.partial_trace(prod, [2, 3]) - b)) <= 1e-15
+    rho = D.conjugate(D.conjugate(D.pure(qi.basis_state(2, 0)), qi.H, (1,)), qi.CNOT, (1, 2))
+    r1 = D.partial_trace(rho, [2])
+    assert np.max(np.abs(r1 - np.eye(2) / 2)) <= 1e-15
+    assert abs(D.eigen_observables(r1)["entropy_bits"] - 1.0) <= 1e-14
+    assert abs(np.trace(D.partial_trace(_rand_rho(rng, 4), [1, 3])) - 1) <= 1e-14
+
+
+def test_eigen_pins():
+    """Pure state: eigenvalues {0, ..., 0, 1}, entropy 0; maximally mixed: all
+    1/2^nq, entropy nq; eigenvalues sum to the trace; fidelity of a state with
+    itself is 1 and with an orthogonal pure state 0."""
+    rng = np.random.default_rng(9)
+    psi = qi.state(4, 3)
+    ev = D.eigen_observables(D.pure(psi))
+    assert np.max(np.abs(ev["eigenvalues"] - np.r_[np.zeros(7), 1.0])) <= 1e-14
+    assert abs(ev["entropy_bits"]) <= 1e-12
+    ev = D.eigen_observables(np.eye(8) / 8)
+    assert abs(ev["entropy_bits"] - 3) <= 1e-14
+    r = _rand_rho(rng, 3)
+    assert abs(np.sum(D.eigen_observables(r)["eigenvalues"]) - 1) <= 1e-14
+    assert abs(D.fidelity_general(r, r) - 1) <= 1e-7
+    assert abs(D.fidelity_general(D.pure(qi.basis_state(2, 0)), D.pure(qi.basis_state(2, 3)))) <= 1e-7

@@ -187,3 +187,69 @@ def test_channel_validation(L):
     with pytest.raises(L.QcwError, match="overlap"):
         ch.apply(a, a)
     ch.close()
+
+
+# ------------------------------------------------------------------ eigen observables
+@pytest.mark.parametrize("nq", [1, 2, 3, 5, 6])
+def test_eigvals_and_entropy(L, nq):
+    rng = np.random.default_rng(40 + nq)
+    for rank in (1, 3, 1 << nq):
+        rho = _rand_rho(rng, nq, rank)
+        ev, S = L.qcw_rho_eigvals(dev(rho))
+        ref = D.eigen_observables(rho)
+        assert np.max(np.abs(ev - ref["eigenvalues"])) <= 1e-13
+        assert abs(S - ref["entropy_bits"]) <= 1e-11
+
+
+def test_classical_limit_on_gpu(L):
+    """Repeated X and Z noise on every qubit drives the eigenvalues to 1/2^nq and
+    the entropy to nq bits (§5, classical limit)."""
+    nq = 3
+    rng = np.random.default_rng(50)
+    a = dev(_rand_rho(rng, nq))
+    b = torch.empty_like(a)
+    xz = [(0.3 / (2 * nq), {q: s}) for q in range(1, nq + 1) for s in (D.SX, D.SZ)]
+    ch = L.Channel(nq, 0.7, xz)
+    for _ in range(300):
+        ch.apply(a, b)
+        a, b = b, a
+    ev, S = L.qcw_rho_eigvals(a)
+    assert np.max(np.abs(ev - 1 / 8)) <= 1e-12 and abs(S - nq) <= 1e-10
+    ch.close()
+
+
+@pytest.mark.parametrize("nq", [1, 2, 4, 6])
+def test_general_fidelity(L, nq):
+    rng = np.random.default_rng(60 + nq)
+    full = 1 << nq
+    r, r0 = _rand_rho(rng, nq, full), _rand_rho(rng, nq, full)
+    assert abs(L.qcw_rho_fidelity(dev(r), dev(r0)) - D.fidelity_general(r, r0)) <= 1e-12
+    # pure reference: the closed form sqrt(<psi0|rho|psi0>) (tiny eigenvalues of
+    # sqrt(rho0) rho sqrt(rho0) lose digits under the square root: 1e-6)
+    psi0 = qi.state(3, nq)
+    f = L.qcw_rho_fidelity(dev(r), dev(D.pure(psi0)))
+    assert abs(f - D.observables(r, psi0)["fidelity"]) <= 1e-6
+    assert abs(L.qcw_rho_fidelity(dev(r), dev(r)) - 1.0) <= 1e-6
+
+
+def test_fidelity_after_one_hadamard_general(L):
+    psi0 = qi.basis_state(1, 0)
+    rho = D.conjugate(D.pure(psi0), qi.H, (1,))
+    assert abs(L.qcw_rho_fidelity(dev(rho), dev(D.pure(psi0))) - 2 ** -0.5) <= 1e-7
+
+
+@pytest.mark.parametrize("nq,keep", [(2, [1]), (2, [2]), (3, [1, 3]), (5, [2, 3, 5]), (8, [4]),
+                                     (8, [1, 2, 7, 8])])
+def test_partial_trace(L, nq, keep):
+    rng = np.random.default_rng(70 + nq)
+    rho = _rand_rho(rng, nq)
+    got = L.qcw_rho_partial_trace(dev(rho), keep)
+    ref = D.partial_trace(rho, keep)
+    assert np.max(np.abs(host(got, len(keep)) - ref)) <= 1e-14
+
+
+def test_bell_subsystem_entropy(L):
+    rho = D.conjugate(D.conjugate(D.pure(qi.basis_state(2, 0)), qi.H, (1,)), qi.CNOT, (1, 2))
+    red = L.qcw_rho_partial_trace(dev(rho), [2])
+    ev, S = L.qcw_rho_eigvals(red)
+    assert np.max(np.abs(ev - 0.5)) <= 1e-15 and abs(S - 1.0) <= 1e-14
