@@ -295,6 +295,7 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
     return {"nq": nq, "paths": 2 * n_p, "steps_per_s": 1e3 / ms, "ms_per_step": ms,
             "channel_ms": cavg, "channel_fp64_tflops": fl / (cavg * 1e-3) / 1e12,
             "channel_fp64_frac": fl / (cavg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "channel_gbs_read_write_once": 32 * NN / (cavg * 1e-3) / 1e9,
             "channel_flops_per_element": ch_flops if (ch_flops := fl // NN) else None,
             "trace_after": ob["trace"].real, "purity_after": ob["purity"],
             "fidelity_after": ob["fidelity"], **spectral}

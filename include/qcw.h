@@ -263,9 +263,14 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
 int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out,
                       void *stream);
 int qcw_channel_destroy(qcw_channel *c);
-/* Real FP64 operations per output element of one application: 8 per complex
- * multiply-add (4 per single-hit term, 16 per double-hit term), 4 for each
- * weighted sum, 2 for p_keep * rho.  For roofline accounting. */
+/* Real FP64 operations per output element of one application, as evaluated.
+ * Terms whose operators are all diagonal or anti-diagonal (Pauli operators,
+ * phases, the identity) read rho at n^x, m^x for a flip mask x; terms with
+ * equal masks share that read: 8 per mask group (one complex multiply-add),
+ * plus 2 per one-operator term and 8 per two-operator term for its
+ * coefficient.  Any other term costs 8 per complex multiply-add (4 for one
+ * operator, 16 for two) plus 4 for its weighted sum.  Plus 2 for p_keep * rho.
+ * For roofline accounting. */
 int64_t qcw_channel_flops_per_element(const qcw_channel *c);
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);

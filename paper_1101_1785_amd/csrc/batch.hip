@@ -32,6 +32,15 @@ __device__ __forceinline__ void lds_gate(double2 *S, int nq, const BGate &g, con
                                          const double2 *Ul, int lane) {
   constexpr int M = 1 << K;
   constexpr int ILP = AMP > M ? AMP / M : 1;
+  // With the matrix staged in LDS, one-qubit gates copy it into registers once
+  // (four broadcast reads) and reuse it for every group of the lane; larger
+  // matrices are read from LDS per use (caching them costs occupancy).
+  constexpr bool UREG = MAT_LDS && K == 1;
+  double2 ureg[UREG ? M * M : 1];
+  if (UREG) {
+#pragma unroll
+    for (int e = 0; e < M * M; ++e) ureg[UREG ? e : 0] = Ul[e];
+  }
   const uint32_t ngroups = 1u << (nq - K);
   for (uint32_t j0 = lane; j0 < ngroups; j0 += 64 * ILP) {
     double2 x[ILP][M];
@@ -51,7 +60,9 @@ __device__ __forceinline__ void lds_gate(double2 *S, int nq, const BGate &g, con
       if (j < ngroups) {
         const uint32_t b = base[i];
         auto put = [&](int r, double2 y) { S[b + g.off[r]] = y; };
-        if (MAT_LDS)
+        if (UREG)
+          group_matvec_put<M>(x[i], [&](int r, int c) { return ureg[UREG ? r * M + c : 0]; }, put);
+        else if (MAT_LDS)
           group_matvec_put<M>(x[i], [&](int r, int c) { return Ul[r * M + c]; }, put);
         else
           group_matvec_put<M>(x[i], [&](int r, int c) { return U[r * M + c]; }, put);

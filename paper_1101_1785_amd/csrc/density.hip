@@ -11,6 +11,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "qcw_device.h"
@@ -32,6 +34,25 @@ struct DevTerm {
   double weight;
   double pad;
   double2 k0[4], k1[4];  // 2x2 operators, row-major
+};
+
+// A term whose operators each have one nonzero entry per row, in distinct
+// columns (Pauli operators, phases, the identity): row r of K reads column
+// r ^ s with s = 0 or 1, so (K rho K^dagger)_{nm} = c(n, m) rho_{n^x, m^x}
+// with x the term's flip mask (the bits of its swapping operators) and
+// c = K[r][r^s] conj(K[c][c^s]) depending only on the bits at the term's qubits.
+struct PermTerm {
+  int32_t nops;
+  int32_t bit0, bit1;
+  int32_t pad;
+  double2 c0[4];  // w K0[r][r^s0] conj(K0[c][c^s0]) at r*2 + c (weight folded in)
+  double2 c1[4];  // K1[r][r^s1] conj(K1[c][c^s1]) at r*2 + c
+};
+
+// Terms sharing a flip mask read the same element of rho: one gather per group.
+struct PermGroup {
+  uint64_t flip;
+  int32_t first, count;
 };
 
 // Coefficient tables, built once on the device when a channel is created.
@@ -59,13 +80,19 @@ __global__ void channel_coef_kernel(const DevTerm *__restrict__ terms, int nterm
   }
 }
 
+__device__ __forceinline__ double2 pick4(const double2 (&c)[4], int r, int cc) {
+  const double2 lo = cc ? c[1] : c[0];
+  const double2 hi = cc ? c[3] : c[2];
+  return r ? hi : lo;
+}
+
 // out = p rho + sum_t w_t K_t rho K_t^dagger, one thread per output element.
-__global__ __launch_bounds__(256) void channel_kernel(const double2 *__restrict__ rho,
-                                                      double2 *__restrict__ out, int nq,
-                                                      double p_keep,
-                                                      const DevTerm *__restrict__ terms,
-                                                      int nterms,
-                                                      const double2 *__restrict__ coef) {
+// Permutation-type terms first, one gather per flip-mask group; then the
+// dense terms from their coefficient tables.
+__global__ __launch_bounds__(256) void channel_kernel(
+    const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
+    const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm,
+    const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef) {
   const uint64_t NN = 1ull << (2 * nq);
   const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= NN) return;
@@ -73,6 +100,20 @@ __global__ __launch_bounds__(256) void channel_kernel(const double2 *__restrict_
   const uint64_t n = x >> nq, m = x & (N - 1);
   const double2 r = rho[x];
   double2 acc_all = make_double2(p_keep * r.x, p_keep * r.y);
+  for (int g = 0; g < ngroups; ++g) {
+    const uint64_t flip = groups[g].flip;
+    const int first = groups[g].first, count = groups[g].count;
+    const double2 v = flip ? rho[((n ^ flip) << nq) | (m ^ flip)] : r;
+    double2 cs = make_double2(0.0, 0.0);
+    for (int t = first; t < first + count; ++t) {
+      const PermTerm &T = perm[t];
+      double2 c = pick4(T.c0, (int)((n >> T.bit0) & 1), (int)((m >> T.bit0) & 1));
+      if (T.nops == 2) c = cmul(c, pick4(T.c1, (int)((n >> T.bit1) & 1), (int)((m >> T.bit1) & 1)));
+      cs.x += c.x;
+      cs.y += c.y;
+    }
+    acc_all = cmad(acc_all, cs, v);
+  }
   for (int t = 0; t < nterms; ++t) {
     const DevTerm &T = terms[t];
     double2 acc = make_double2(0.0, 0.0);
@@ -201,10 +242,23 @@ struct qcw_channel {
   int nq = 0;
   double p_keep = 0;
   int nterms = 0;
-  DevTerm *terms_d = nullptr;
+  int ngroups = 0;
+  DevTerm *terms_d = nullptr;  // dense terms
   double2 *coef_d = nullptr;
-  int64_t flops_per_element = 0;  // complex multiply-adds * 8 + the weighted sums
+  PermGroup *groups_d = nullptr;
+  PermTerm *perm_d = nullptr;
+  int64_t flops_per_element = 0;  // real FP64 operations per output element, as evaluated
 };
+
+namespace {
+void channel_free(qcw_channel *c) {
+  (void)hipFree(c->terms_d);
+  (void)hipFree(c->coef_d);
+  (void)hipFree(c->groups_d);
+  (void)hipFree(c->perm_d);
+  delete c;
+}
+}  // namespace
 
 extern "C" {
 
@@ -238,51 +292,116 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
   *out = nullptr;
   if (nq < 1 || nq > kRhoMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kRhoMaxQubits);
   if (nterms < 0 || (nterms > 0 && (!terms || !mats))) return fail(QCW_EINVAL, "bad term list");
-  std::vector<DevTerm> dt(nterms);
+  std::vector<DevTerm> dt;
+  std::vector<std::pair<uint64_t, PermTerm>> pt;  // (flip mask, term)
   for (int i = 0; i < nterms; ++i) {
     const qcw_kraus_term &t = terms[i];
     if (t.nops < 1 || t.nops > 2) return fail(QCW_EINVAL, "term %d: nops=%d outside {1, 2}", i, t.nops);
-    memset(&dt[i], 0, sizeof(DevTerm));
-    dt[i].nops = t.nops;
-    dt[i].weight = t.weight;
+    double2 k[2][4];
     for (int j = 0; j < t.nops; ++j) {
       if (t.q[j] < 1 || t.q[j] > nq) return fail(QCW_EINVAL, "term %d: qubit %d outside [1, %d]", i, t.q[j], nq);
       if (t.mat[j] < 0 || t.mat[j] + 4 > nmats) return fail(QCW_EINVAL, "term %d: matrix outside mats", i);
-      double2 *k = j == 0 ? dt[i].k0 : dt[i].k1;
-      for (int e = 0; e < 4; ++e) k[e] = make_double2(mats[t.mat[j] + e].re, mats[t.mat[j] + e].im);
+      for (int e = 0; e < 4; ++e) k[j][e] = make_double2(mats[t.mat[j] + e].re, mats[t.mat[j] + e].im);
     }
     if (t.nops == 2 && t.q[0] == t.q[1]) return fail(QCW_EINVAL, "term %d: repeated qubit", i);
-    dt[i].bit0 = nq - t.q[0];
-    dt[i].bit1 = t.nops == 2 ? nq - t.q[1] : 0;
+    const int bit0 = nq - t.q[0], bit1 = t.nops == 2 ? nq - t.q[1] : 0;
+    // Permutation type: per operator, exactly one nonzero per row, in different
+    // columns (s = 0: diagonal, s = 1: anti-diagonal).
+    auto nz = [](double2 a) { return a.x != 0.0 || a.y != 0.0; };
+    int swaps[2] = {0, 0};
+    bool perm_type = true;
+    for (int j = 0; j < t.nops; ++j) {
+      const bool diag = nz(k[j][0]) && nz(k[j][3]) && !nz(k[j][1]) && !nz(k[j][2]);
+      const bool anti = nz(k[j][1]) && nz(k[j][2]) && !nz(k[j][0]) && !nz(k[j][3]);
+      perm_type = perm_type && (diag || anti);
+      swaps[j] = anti;
+    }
+    if (perm_type) {
+      PermTerm p;
+      memset(&p, 0, sizeof(p));
+      p.nops = t.nops;
+      p.bit0 = bit0;
+      p.bit1 = bit1;
+      for (int j = 0; j < t.nops; ++j) {
+        double2 *cj = j == 0 ? p.c0 : p.c1;
+        for (int r = 0; r < 2; ++r)
+          for (int c = 0; c < 2; ++c) {
+            const double2 a = k[j][r * 2 + (r ^ swaps[j])], b = k[j][c * 2 + (c ^ swaps[j])];
+            double2 v = make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+            if (j == 0) v = make_double2(t.weight * v.x, t.weight * v.y);
+            cj[r * 2 + c] = v;
+          }
+      }
+      const uint64_t flip = ((uint64_t)swaps[0] << bit0) | (t.nops == 2 ? (uint64_t)swaps[1] << bit1 : 0);
+      pt.emplace_back(flip, p);
+    } else {
+      DevTerm d;
+      memset(&d, 0, sizeof(d));
+      d.nops = t.nops;
+      d.weight = t.weight;
+      d.bit0 = bit0;
+      d.bit1 = bit1;
+      for (int e = 0; e < 4; ++e) {
+        d.k0[e] = k[0][e];
+        if (t.nops == 2) d.k1[e] = k[1][e];
+      }
+      dt.push_back(d);
+    }
   }
-  int64_t ncoef = 0, flops = 2;
-  for (int i = 0; i < nterms; ++i) {
-    dt[i].coef_off = (int32_t)ncoef;
-    ncoef += dt[i].nops == 1 ? 16 : 256;
-    flops += (dt[i].nops == 1 ? 4 : 16) * 8 + 4;
+  // Group the permutation terms by flip mask (stable: equal masks keep input order).
+  std::stable_sort(pt.begin(), pt.end(),
+                   [](const std::pair<uint64_t, PermTerm> &a, const std::pair<uint64_t, PermTerm> &b) {
+                     return a.first < b.first;
+                   });
+  std::vector<PermGroup> groups;
+  std::vector<PermTerm> perm;
+  int64_t flops = 2;  // p_keep * rho
+  for (size_t i = 0; i < pt.size(); ++i) {
+    if (groups.empty() || groups.back().flip != pt[i].first) {
+      groups.push_back(PermGroup{pt[i].first, (int32_t)i, 0});
+      flops += 8;  // one complex multiply-add per group
+    }
+    ++groups.back().count;
+    perm.push_back(pt[i].second);
+    flops += pt[i].second.nops == 1 ? 2 : 8;  // sum of the coefficient (and its product)
+  }
+  int64_t ncoef = 0;
+  for (DevTerm &d : dt) {
+    d.coef_off = (int32_t)ncoef;
+    ncoef += d.nops == 1 ? 16 : 256;
+    flops += (d.nops == 1 ? 4 : 16) * 8 + 4;
   }
   qcw_channel *c = new qcw_channel();
   c->nq = nq;
   c->p_keep = p_keep;
-  c->nterms = nterms;
+  c->nterms = (int)dt.size();
+  c->ngroups = (int)groups.size();
   c->flops_per_element = flops;
-  if (nterms) {
-    if (hipMalloc(&c->terms_d, sizeof(DevTerm) * nterms) != hipSuccess ||
-        hipMalloc(&c->coef_d, sizeof(double2) * ncoef) != hipSuccess ||
-        hipMemcpy(c->terms_d, dt.data(), sizeof(DevTerm) * nterms, hipMemcpyHostToDevice) !=
+  if (!groups.empty()) {
+    if (hipMalloc(&c->groups_d, sizeof(PermGroup) * groups.size()) != hipSuccess ||
+        hipMalloc(&c->perm_d, sizeof(PermTerm) * perm.size()) != hipSuccess ||
+        hipMemcpy(c->groups_d, groups.data(), sizeof(PermGroup) * groups.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->perm_d, perm.data(), sizeof(PermTerm) * perm.size(), hipMemcpyHostToDevice) !=
             hipSuccess) {
       (void)hipGetLastError();
-      (void)hipFree(c->terms_d);
-      (void)hipFree(c->coef_d);
-      delete c;
+      channel_free(c);
       return fail(QCW_ENOMEM, "channel terms upload failed");
     }
-    hipLaunchKernelGGL(channel_coef_kernel, dim3(nterms), dim3(256), 0, nullptr, c->terms_d,
-                       nterms, c->coef_d);
+  }
+  if (!dt.empty()) {
+    if (hipMalloc(&c->terms_d, sizeof(DevTerm) * dt.size()) != hipSuccess ||
+        hipMalloc(&c->coef_d, sizeof(double2) * ncoef) != hipSuccess ||
+        hipMemcpy(c->terms_d, dt.data(), sizeof(DevTerm) * dt.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      channel_free(c);
+      return fail(QCW_ENOMEM, "channel terms upload failed");
+    }
+    hipLaunchKernelGGL(channel_coef_kernel, dim3((unsigned)dt.size()), dim3(256), 0, nullptr,
+                       c->terms_d, (int)dt.size(), c->coef_d);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-      (void)hipFree(c->terms_d);
-      (void)hipFree(c->coef_d);
-      delete c;
+      channel_free(c);
       return fail(QCW_EHIP, "channel coefficient kernel failed");
     }
   }
@@ -304,7 +423,8 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
   hipLaunchKernelGGL(channel_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                      reinterpret_cast<const double2 *>(rho_in), reinterpret_cast<double2 *>(rho_out),
-                     c->nq, c->p_keep, c->terms_d, c->nterms, c->coef_d);
+                     c->nq, c->p_keep, c->groups_d, c->ngroups, c->perm_d, c->terms_d, c->nterms,
+                     c->coef_d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(e));
   return QCW_OK;
@@ -312,11 +432,7 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
 
 int qcw_channel_destroy(qcw_channel *c) {
   clear_error();
-  if (c) {
-    (void)hipFree(c->terms_d);
-    (void)hipFree(c->coef_d);
-    delete c;
-  }
+  if (c) channel_free(c);
   return QCW_OK;
 }
 

@@ -253,3 +253,26 @@ def test_bell_subsystem_entropy(L):
     red = L.qcw_rho_partial_trace(dev(rho), [2])
     ev, S = L.qcw_rho_eigvals(red)
     assert np.max(np.abs(ev - 0.5)) <= 1e-15 and abs(S - 1.0) <= 1e-14
+
+
+@pytest.mark.parametrize("nq", [1, 3, 7])
+def test_channel_mixed_monomial_and_dense_terms(L, nq):
+    """Diagonal/anti-diagonal terms take the flip-mask path (grouped by mask),
+    all others (random unitaries, one-column and rank-one operators) the table
+    path; both together must match the oracle."""
+    rng = np.random.default_rng(80 + nq)
+    rho0 = _rand_rho(rng, nq)
+    P = [D.SX, D.SY, D.SZ, np.eye(2, dtype=complex), np.array([[0, 1j], [0.5, 0]]),
+         np.array([[0.3, 0], [0.7j, 0]]), np.array([[0, 0.4], [0, 0]]),
+         np.diag([1.0, 0.6])]
+    terms = []
+    for i in range(12):
+        qs = [int(x) + 1 for x in rng.choice(nq, min(nq, 1 + i % 2), replace=False)]
+        ops = {q: (P[int(rng.integers(len(P)))] if i % 3 else qi.random_unitary(rng, 2))
+               for q in qs}
+        terms.append((0.2 / 12, ops))
+    ch = L.Channel(nq, 0.8, terms)
+    a, b = dev(rho0), torch.empty(1 << (2 * nq), dtype=torch.complex128, device="cuda")
+    ch.apply(a, b)
+    assert np.max(np.abs(host(b, nq) - D.channel(rho0, 0.8, terms))) <= TOL
+    ch.close()
