@@ -180,8 +180,12 @@ int qcw_debug_pick_device(int nq, int k, const int *targets, uint64_t *out_host)
  * `stream` (NULL: a private stream).  qcw_batch_run replays the graph on
  * `stream`: every instance's state advances by its whole circuit, in place.
  * The handle owns its device copies and the graph; qcw_batch_destroy frees
- * them (never the caller's states).  Results equal, bit for bit, those of
- * qcw_circuit applied to each instance alone.
+ * them (never the caller's states).  With the exact tile shapes (every shape
+ * but "amp4_mfma") results equal, bit for bit, those of qcw_circuit applied
+ * to each instance alone.  "amp4_mfma" fuses each circuit (qcw_fuse_circuit,
+ * at most three qubits per gate) and applies two- and three-qubit gates with
+ * FP64 matrix-core instructions: results then agree with qcw_circuit to FP64
+ * rounding, and still do not depend on the other instances of the launch.
  */
 typedef struct {
   int32_t nq;
@@ -205,6 +209,25 @@ int qcw_batch_info(const qcw_batch *b, int nq, int *variant, int *blocks, int *l
 int qcw_batch_destroy(qcw_batch *b);
 /* Name of a tile-shape variant ("amp8_sgpr", ...), as used in tune tables. */
 const char *qcw_batch_variant_name(int variant);
+
+/*
+ * Gate fusion (§2c, tensor-product structure; gates compose in list order):
+ * every run of consecutive gates whose targets together span at most
+ * max_qubits (1..3) qubits becomes one gate on that union, its matrix the
+ * product of the run's gates, each extended by the identity (the first gate
+ * rightmost).  Gates are never reordered.  The union's qubits are listed in
+ * order of first appearance (first = most significant local bit).  A run of
+ * one gate is copied unchanged; a fused matrix carries the rounding of its
+ * products, so the fused circuit equals the original to FP64 rounding.
+ * All arrays are host memory: gates (ngates) and mats (nmats) as for
+ * qcw_circuit; out_gates must hold ngates entries, out_mats out_mats_cap
+ * (64 * ngates always suffices).  Writes the fused gate count and matrix
+ * entries to *out_ngates and *out_nmats.  QCW_EINVAL for an invalid gate or
+ * too small an out_mats.
+ */
+int qcw_fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
+                     int64_t nmats, int max_qubits, qcw_gate *out_gates, int *out_ngates,
+                     qcw_c64 *out_mats, int64_t out_mats_cap, int64_t *out_nmats);
 
 /*
  * Autotuner: for every qubit count in [nq_lo, nq_hi] (1 <= nq_lo <= nq_hi <=
@@ -308,7 +331,9 @@ int qcw_rho_partial_trace(const qcw_c64 *rho, int nq, const int *keep, int nkeep
  * Requests that arrive while a tick runs join the next tick.  A request
  * never leaves the queue except by completing or failing, and the queue head
  * is never overtaken (no starvation).  Results equal, bit for bit, those of
- * qcw_circuit run on the request alone.
+ * qcw_circuit run on the request alone, unless the tune table puts the
+ * request's size on "amp4_mfma" (see qcw_batch_create): then the request's
+ * circuit is fused at submit and results agree to FP64 rounding.
  *
  * All request arrays are HOST pointers copied by qcw_server_submit, which
  * does not block on the GPU.  A request that can never run (invalid gates,

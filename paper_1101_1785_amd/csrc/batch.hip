@@ -12,6 +12,9 @@
 //           with a staged matrix), i.e. max(1, amp / 2^k) groups per lane
 //   mat     where the wave reads the gate matrix: the scalar cache (wave-
 //           uniform loads) or a copy staged in the wave's LDS.
+//   mfma    two- and three-qubit gates on the FP64 matrix cores (below); the
+//           summation order differs from the plain path, so results agree with
+//           it to rounding rather than bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "qcw_batch.h"
@@ -71,6 +74,110 @@ __device__ __forceinline__ void lds_gate(double2 *S, int nq, const BGate &g, con
   }
 }
 
+// ---- FP64 matrix-core gates ------------------------------------------------
+// The complex m x m product is the real 2m x 2m product
+//   [Re y; Im y] = [[Re U, -Im U], [Im U, Re U]] [Re x; Im x]
+// over many groups at once (one group per column).  Lane layouts of the two
+// instructions used (l = lane):
+//   v_mfma_f64_4x4x4f64, four independent 4x4x4 blocks, block (l >> 2) & 3:
+//     A[l & 3][l >> 4], B[l >> 4][l & 3], D[l >> 4][l & 3]
+//   v_mfma_f64_16x16x4f64:
+//     A[l & 15][l >> 4], B[l >> 4][l & 15], D[4v + (l >> 4)][l & 15], v = 0..3
+// The matrix is spread over the lanes (each lane holds one or two entries), so
+// no lane needs the whole matrix; every lane reads and writes back exactly the
+// amplitudes it owns, so a gate needs no exchange between lanes.
+typedef double qcw_d4 __attribute__((ext_vector_type(4)));
+
+// Offset of local index r from its group's base: the first target is the most
+// significant bit of r, and off[1 << j] is the stride of local bit j.
+template <int K>
+__device__ __forceinline__ uint32_t member_off(const BGate &g, int r) {
+  uint32_t o = (r & 1) ? g.off[1] : 0u;
+  if (K >= 2 && (r & 2)) o += g.off[2];
+  if (K >= 3 && (r & 4)) o += g.off[4];
+  return o;
+}
+
+// Two-qubit gate, 16 groups per step: columns are groups t0 + (l & 15); the
+// real 8 x 8 matrix splits into four 4 x 4 blocks acting on (Re x, Im x):
+//   Re y = ReU Re x - ImU Im x,  Im y = ImU Re x + ReU Im x.
+// Lane l holds U[l & 3][l >> 4] and owns amplitude l >> 4 of its group.
+__device__ __forceinline__ void mfma_gate2(double2 *S, int nq, const BGate &g, const double2 *Ul,
+                                           int lane) {
+  const uint32_t ngroups = 1u << (nq - 2);
+  const int r = lane >> 4;
+  const double2 u = Ul[(lane & 3) * 4 + r];
+  const uint32_t moff = member_off<2>(g, r);
+  for (uint32_t t0 = 0; t0 < ngroups; t0 += 32) {
+    const uint32_t ja = t0 + (lane & 15), jb = ja + 16;
+    const bool oka = ja < ngroups, okb = jb < ngroups;
+    const uint32_t pa = insert_zeros<2, uint32_t>(ja, g.sb0, g.sb1, g.sb2) + moff;
+    const uint32_t pb = insert_zeros<2, uint32_t>(jb, g.sb0, g.sb1, g.sb2) + moff;
+    double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
+    if (oka) xa = S[pa];
+    if (okb) xb = S[pb];
+    double ra = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, xa.x, 0.0, 0, 0, 0);
+    double ia = __builtin_amdgcn_mfma_f64_4x4x4f64(u.y, xa.x, 0.0, 0, 0, 0);
+    double rb = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, xb.x, 0.0, 0, 0, 0);
+    double ib = __builtin_amdgcn_mfma_f64_4x4x4f64(u.y, xb.x, 0.0, 0, 0, 0);
+    ra = __builtin_amdgcn_mfma_f64_4x4x4f64(-u.y, xa.y, ra, 0, 0, 0);
+    ia = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, xa.y, ia, 0, 0, 0);
+    rb = __builtin_amdgcn_mfma_f64_4x4x4f64(-u.y, xb.y, rb, 0, 0, 0);
+    ib = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, xb.y, ib, 0, 0, 0);
+    if (oka) S[pa] = make_double2(ra, ia);
+    if (okb) S[pb] = make_double2(rb, ib);
+  }
+}
+
+// Three-qubit gate, 16 groups per step.  Real index of (amplitude c, part p)
+// is 8 (c >> 2) + 4 p + (c & 3), so a lane's four output rows (4v + (l >> 4))
+// are Re, Im of amplitude s = l >> 4 and Re, Im of amplitude 4 + s -- the two
+// amplitudes it also supplies as B.  Lane l holds the A entries of row
+// l & 15: U[r][s] and U[r][4 + s] with r = 4 ((l & 15) >> 3) + (l & 3).
+__device__ __forceinline__ void mfma_gate3(double2 *S, int nq, const BGate &g, const double2 *Ul,
+                                           int lane) {
+  const uint32_t ngroups = 1u << (nq - 3);
+  const int s = lane >> 4, row = lane & 15;
+  const int r = 4 * (row >> 3) + (row & 3);
+  const bool im_row = (row >> 2) & 1;
+  const double2 u0 = Ul[r * 8 + s], u1 = Ul[r * 8 + 4 + s];
+  const double a0 = im_row ? u0.y : u0.x, a1 = im_row ? u0.x : -u0.y;
+  const double a2 = im_row ? u1.y : u1.x, a3 = im_row ? u1.x : -u1.y;
+  const uint32_t m0 = member_off<3>(g, s), m1 = member_off<3>(g, 4 + s);
+  for (uint32_t t0 = 0; t0 < ngroups; t0 += 32) {
+    const uint32_t ja = t0 + (lane & 15), jb = ja + 16;
+    const bool oka = ja < ngroups, okb = jb < ngroups;
+    const uint32_t ba = insert_zeros<3, uint32_t>(ja, g.sb0, g.sb1, g.sb2);
+    const uint32_t bb = insert_zeros<3, uint32_t>(jb, g.sb0, g.sb1, g.sb2);
+    double2 xa0 = make_double2(0.0, 0.0), xa1 = xa0, xb0 = xa0, xb1 = xa0;
+    if (oka) {
+      xa0 = S[ba + m0];
+      xa1 = S[ba + m1];
+    }
+    if (okb) {
+      xb0 = S[bb + m0];
+      xb1 = S[bb + m1];
+    }
+    qcw_d4 da = {0.0, 0.0, 0.0, 0.0}, db = {0.0, 0.0, 0.0, 0.0};
+    da = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, xa0.x, da, 0, 0, 0);
+    db = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, xb0.x, db, 0, 0, 0);
+    da = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, xa0.y, da, 0, 0, 0);
+    db = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, xb0.y, db, 0, 0, 0);
+    da = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, xa1.x, da, 0, 0, 0);
+    db = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, xb1.x, db, 0, 0, 0);
+    da = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, xa1.y, da, 0, 0, 0);
+    db = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, xb1.y, db, 0, 0, 0);
+    if (oka) {
+      S[ba + m0] = make_double2(da[0], da[1]);
+      S[ba + m1] = make_double2(da[2], da[3]);
+    }
+    if (okb) {
+      S[bb + m0] = make_double2(db[0], db[1]);
+      S[bb + m1] = make_double2(db[2], db[3]);
+    }
+  }
+}
+
 // Copies an instance's 2^nq amplitudes from HBM into the wave's LDS region,
 // eight loads in flight per lane before any LDS store when 2^nq >= 512.
 __device__ __forceinline__ void load_state(double2 *S, const double2 *st, uint32_t N, int lane) {
@@ -91,7 +198,7 @@ __device__ __forceinline__ void load_state(double2 *S, const double2 *st, uint32
   for (uint32_t n = n0 + lane; n < N; n += 64) S[n] = st[n];
 }
 
-template <int AMP, bool MAT_LDS>
+template <int AMP, bool MAT_LDS, bool MFMA = false>
 __device__ void run_instance(const BInst &in, const BGate *__restrict__ gates,
                              const double2 *__restrict__ mats, double2 *__restrict__ states,
                              double2 *S, double2 *Ul, int lane, int g_begin, int g_end) {
@@ -123,8 +230,14 @@ __device__ void run_instance(const BInst &in, const BGate *__restrict__ gates,
     }
     switch (g.k) {
       case 1: lds_gate<1, AMP, MAT_LDS>(S, nq, g, U, Ub, lane); break;
-      case 2: lds_gate<2, AMP, MAT_LDS>(S, nq, g, U, Ub, lane); break;
-      default: lds_gate<3, AMP, MAT_LDS>(S, nq, g, U, Ub, lane); break;
+      case 2:
+        if (MFMA) mfma_gate2(S, nq, g, Ub, lane);
+        else lds_gate<2, AMP, MAT_LDS>(S, nq, g, U, Ub, lane);
+        break;
+      default:
+        if (MFMA) mfma_gate3(S, nq, g, Ub, lane);
+        else lds_gate<3, AMP, MAT_LDS>(S, nq, g, U, Ub, lane);
+        break;
     }
   }
   wave_lds_sync();
@@ -159,6 +272,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(
       case kVarAmp8Sgpr: run_instance<8, false>(in, gates, mats, states, S, Ul, lane, g0, g1); break;
       case kVarAmp16Sgpr: run_instance<16, false>(in, gates, mats, states, S, Ul, lane, g0, g1); break;
       case kVarAmp4Lds: run_instance<4, true>(in, gates, mats, states, S, Ul, lane, g0, g1); break;
+      case kVarAmp4Mfma: run_instance<4, true, true>(in, gates, mats, states, S, Ul, lane, g0, g1); break;
       default: run_instance<8, true>(in, gates, mats, states, S, Ul, lane, g0, g1); break;
     }
     // The LDS region is reused by the next item only after this wave's
@@ -176,10 +290,14 @@ __global__ void reset_counter_kernel(int *counter) {
 }
 
 int launch_batch(const BatchLaunch &L, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, L.counter);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(QCW_EHIP, "counter reset launch: %s", hipGetErrorString(e));
   if (L.nitems == 0) return QCW_OK;
+  hipError_t e;
+  // The work counter is read only when items outnumber the grid's waves.
+  if ((int64_t)L.nitems > (int64_t)L.blocks * (L.threads / 64)) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, L.counter);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(QCW_EHIP, "counter reset launch: %s", hipGetErrorString(e));
+  }
   TimedLaunch t(kKernelBatch, s);
   hipLaunchKernelGGL(batch_kernel, dim3(L.blocks), dim3(L.threads), L.lds_bytes, s, L.items,
                      L.nitems, L.inst, L.gates, L.mats, L.states, L.counter, L.wave_amps);

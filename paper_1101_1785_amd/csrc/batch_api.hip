@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -17,7 +18,7 @@
 namespace qcw {
 
 static const char *kVarNames[kVarCount] = {"amp4_sgpr", "amp8_sgpr", "amp16_sgpr",
-                                           "amp4_lds", "amp8_lds"};
+                                           "amp4_lds", "amp8_lds", "amp4_mfma"};
 
 const char *variant_name(int v) { return (v >= 0 && v < kVarCount) ? kVarNames[v] : "?"; }
 
@@ -245,6 +246,37 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
     int v = variant_override ? variant_override[in.nq] : b->tune.variant[in.nq];
     items.push_back({i, v, 0, in.ngates});
   }
+  // Instances on the matrix-core variant (already exact only to rounding) run
+  // their circuits fused into gates of at most three qubits.  Instances that
+  // share a gate range share its fused copy.
+  std::vector<double2> m2((size_t)nmats);
+  for (int64_t i = 0; i < nmats; ++i) m2[i] = make_double2(mats[i].re, mats[i].im);
+  std::map<std::pair<int64_t, int>, std::pair<int64_t, int>> fused_at;
+  for (BItem &it : items) {
+    if (it.variant != kVarAmp4Mfma) continue;
+    BInst &in = b->inst_h[it.inst];
+    auto key = std::make_pair(in.gate_off, in.ngates);
+    auto f = fused_at.find(key);
+    if (f == fused_at.end()) {
+      std::vector<qcw_gate> fg;
+      std::vector<qcw_c64> fm;
+      int rc = fuse_circuit(in.nq, gates + in.gate_off, in.ngates, mats, nmats,
+                            std::min(3, in.nq), &fg, &fm);
+      if (rc) return rc;
+      const int64_t goff = (int64_t)bg.size(), moff = (int64_t)m2.size();
+      for (const qcw_c64 &z : fm) m2.push_back(make_double2(z.re, z.im));
+      for (qcw_gate g : fg) {
+        BGate t;
+        g.mat += moff;
+        if ((rc = make_bgate(in.nq, g, (int64_t)m2.size(), &t))) return rc;
+        bg.push_back(t);
+      }
+      f = fused_at.emplace(key, std::make_pair(goff, (int)fg.size())).first;
+    }
+    in.gate_off = f->second.first;
+    in.ngates = f->second.second;
+    it.g_end = in.ngates;
+  }
   std::stable_sort(items.begin(), items.end(), [&](const BItem &x, const BItem &y) {
     const BInst &a = b->inst_h[x.inst], &c = b->inst_h[y.inst];
     return ((int64_t)a.ngates << a.nq) > ((int64_t)c.ngates << c.nq);
@@ -254,8 +286,6 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
   int rc;
   if ((rc = upload(&b->inst_d, b->inst_h.data(), b->inst_h.size(), "instances"))) return rc;
   if ((rc = upload(&b->gates_d, bg.data(), bg.size(), "gates"))) return rc;
-  std::vector<double2> m2((size_t)nmats);
-  for (int64_t i = 0; i < nmats; ++i) m2[i] = make_double2(mats[i].re, mats[i].im);
   if ((rc = upload(&b->mats_d, m2.data(), m2.size(), "matrices"))) return rc;
   if ((rc = upload(&b->items_d, items.data(), items.size(), "work items"))) return rc;
   int zero = 0;

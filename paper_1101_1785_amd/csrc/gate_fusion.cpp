@@ -1,0 +1,158 @@
+// Gate fusion: runs of consecutive gates whose targets together span at most
+// max_qubits qubits become one gate on that union.
+//
+// Gates compose in list order (the operator of a circuit is the product of
+// its gates, the first gate rightmost), so a run g_1 .. g_r acting inside a
+// qubit set Q is the single operator E(g_r) ... E(g_1) on Q, where E(g)
+// extends g to Q by the identity on Q's other qubits (the tensor structure of
+// §2c).  Only consecutive gates are merged; nothing is reordered.  The fused
+// matrix carries the rounding of its products, so a fused circuit equals the
+// original to rounding, not bit for bit.
+#include <string.h>
+
+#include <complex>
+#include <vector>
+
+#include "qcw_host.h"
+
+namespace qcw {
+
+namespace {
+
+using cd = std::complex<double>;
+
+struct Block {
+  int u = 0;           // qubits in the union
+  int q[3] = {0, 0, 0};  // union qubits, first = most significant local bit
+  std::vector<cd> M;   // 2^u x 2^u, row-major
+};
+
+int local_bit(const Block &b, int qubit) {
+  for (int j = 0; j < b.u; ++j)
+    if (b.q[j] == qubit) return b.u - 1 - j;
+  return -1;
+}
+
+// Adds qubit `qubit` as the new least significant local bit: M <- M (x) I_2.
+void grow(Block &b, int qubit) {
+  const int m = 1 << b.u;
+  std::vector<cd> M2((size_t)4 * m * m, cd(0.0, 0.0));
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c)
+      for (int a = 0; a < 2; ++a) M2[(size_t)(2 * r + a) * (2 * m) + (2 * c + a)] = b.M[(size_t)r * m + c];
+  b.q[b.u++] = qubit;
+  b.M.swap(M2);
+}
+
+// M <- E(g) M, with E(g) the gate extended to the block's qubits.
+void apply_gate(Block &b, const qcw_gate &g, const qcw_c64 *U) {
+  const int m = 1 << b.u, mg = 1 << g.k;
+  int bits[3];
+  int mask = 0;
+  for (int j = 0; j < g.k; ++j) {
+    bits[j] = local_bit(b, g.q[j]);
+    mask |= 1 << bits[j];
+  }
+  auto gidx = [&](int R) {  // local index of the gate's targets inside R
+    int r = 0;
+    for (int j = 0; j < g.k; ++j) r = (r << 1) | ((R >> bits[j]) & 1);
+    return r;
+  };
+  auto place = [&](int rest, int r) {  // block index with the gate's bits set from r
+    int R = rest;
+    for (int j = 0; j < g.k; ++j)
+      if ((r >> (g.k - 1 - j)) & 1) R |= 1 << bits[j];
+    return R;
+  };
+  std::vector<cd> out((size_t)m * m, cd(0.0, 0.0));
+  for (int R = 0; R < m; ++R) {
+    const int rest = R & ~mask, rg = gidx(R);
+    for (int C = 0; C < m; ++C) {
+      cd acc(0.0, 0.0);
+      for (int c = 0; c < mg; ++c) {
+        const qcw_c64 u = U[rg * mg + c];
+        acc += cd(u.re, u.im) * b.M[(size_t)place(rest, c) * m + C];
+      }
+      out[(size_t)R * m + C] = acc;
+    }
+  }
+  b.M.swap(out);
+}
+
+}  // namespace
+
+int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats, int64_t nmats,
+                 int max_qubits, std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats) {
+  if (max_qubits < 1 || max_qubits > 3) return fail(QCW_EINVAL, "max_qubits=%d outside [1, 3]", max_qubits);
+  out_gates->clear();
+  out_mats->clear();
+  Block cur;
+  int run = 0;               // gates in the current block
+  const qcw_gate *first = nullptr;
+  auto flush = [&]() {
+    if (!run) return;
+    qcw_gate g;
+    memset(&g, 0, sizeof g);
+    g.mat = (int64_t)out_mats->size();
+    if (run == 1) {  // a lone gate is kept as given (same bits as unfused)
+      g.k = first->k;
+      for (int j = 0; j < first->k; ++j) g.q[j] = first->q[j];
+      out_mats->insert(out_mats->end(), mats + first->mat, mats + first->mat + (1 << (2 * first->k)));
+    } else {
+      g.k = cur.u;
+      for (int j = 0; j < cur.u; ++j) g.q[j] = cur.q[j];
+      for (const cd &z : cur.M) out_mats->push_back({z.real(), z.imag()});
+    }
+    out_gates->push_back(g);
+    run = 0;
+  };
+  for (int i = 0; i < ngates; ++i) {
+    const qcw_gate &g = gates[i];
+    Geom geo;
+    int rc = make_geom(nq, g.k, g.q, &geo);
+    if (rc) return rc;
+    if (g.mat < 0 || g.mat + ((int64_t)1 << (2 * g.k)) > nmats)
+      return fail(QCW_EINVAL, "gate %d: matrix offset outside mats", i);
+    int fresh = 0;
+    for (int j = 0; j < g.k; ++j) fresh += local_bit(cur, g.q[j]) < 0;
+    if (run && cur.u + fresh > max_qubits) flush();
+    if (!run) {
+      cur = Block();
+      cur.M.assign(1, cd(1.0, 0.0));
+      first = &g;
+    }
+    for (int j = 0; j < g.k; ++j)
+      if (local_bit(cur, g.q[j]) < 0) grow(cur, g.q[j]);
+    apply_gate(cur, g, mats + g.mat);
+    ++run;
+  }
+  flush();
+  return QCW_OK;
+}
+
+}  // namespace qcw
+
+using namespace qcw;
+
+extern "C" int qcw_fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
+                                int64_t nmats, int max_qubits, qcw_gate *out_gates,
+                                int *out_ngates, qcw_c64 *out_mats, int64_t out_mats_cap,
+                                int64_t *out_nmats) {
+  clear_error();
+  if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
+  if (ngates < 0 || (ngates > 0 && (!gates || !mats)) || !out_ngates || !out_nmats ||
+      (ngates > 0 && !out_gates))
+    return fail(QCW_EINVAL, "NULL argument");
+  std::vector<qcw_gate> g;
+  std::vector<qcw_c64> m;
+  int rc = fuse_circuit(nq, gates, ngates, mats, nmats, max_qubits, &g, &m);
+  if (rc) return rc;
+  if ((int64_t)m.size() > out_mats_cap || (!m.empty() && !out_mats))
+    return fail(QCW_EINVAL, "out_mats holds %lld entries, %zu needed", (long long)out_mats_cap,
+                m.size());
+  if (!g.empty()) memcpy(out_gates, g.data(), g.size() * sizeof(qcw_gate));
+  if (!m.empty()) memcpy(out_mats, m.data(), m.size() * sizeof(qcw_c64));
+  *out_ngates = (int)g.size();
+  *out_nmats = (int64_t)m.size();
+  return QCW_OK;
+}

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "qcw_host.h"
 
 namespace qcw {
@@ -19,7 +21,8 @@ enum BatchVariant : int32_t {
   kVarAmp16Sgpr = 2,
   kVarAmp4Lds = 3,
   kVarAmp8Lds = 4,
-  kVarCount = 5
+  kVarAmp4Mfma = 5,  // k = 2, 3 on FP64 matrix cores: equal to the plain path to rounding only
+  kVarCount = 6
 };
 const char *variant_name(int v);
 int variant_from_name(const char *s);
@@ -74,6 +77,11 @@ int tune_load(const char *path, TuneTable *t);
 
 // Geometry of a gate for the batch kernel; validates like make_geom.
 int make_bgate(int nq, const qcw_gate &g, int64_t nmats, BGate *out);
+
+// Fuses runs of consecutive gates spanning at most max_qubits qubits into one
+// gate each (gate_fusion.cpp); output matrix offsets index *out_mats.
+int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats, int64_t nmats,
+                 int max_qubits, std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats);
 
 // Sizes one persistent launch for instances of at most max_nq qubits.
 int plan_batch_launch(int max_nq, int nitems, BatchLaunch *L);

@@ -128,6 +128,15 @@ int ServerCore::submit(const qcw_request &r, uint64_t *ticket) {
   q->mats.assign(r.mats, r.mats + r.nmats);
   q->psi0.assign(r.psi0, r.psi0 + ((size_t)1 << r.nq));
   q->t_submit = now_ns();
+  rc = ex_->prepare(q.get());
+  if (!rc && request_device_bytes(q->nq, q->ngates, (int64_t)q->mats.size()) >
+                 (cfg_.hbm_budget_bytes & ~uint64_t(255)))
+    rc = fail(QCW_EINVAL, "request needs more than the whole budget");
+  if (rc) {
+    std::lock_guard<std::mutex> lk(mu_);
+    ctr_.rejected++;
+    return rc;
+  }
   {
     std::lock_guard<std::mutex> lk(mu_);
     if (stop_) return fail(QCW_EINVAL, "server is stopping");

@@ -46,6 +46,12 @@ struct TickItem {
 class Executor {
  public:
   virtual ~Executor() {}
+  // May rewrite a submitted request's circuit into an equivalent one before it
+  // is sized and queued (called from the submitting thread).
+  virtual int prepare(ServeRequest *r) {
+    (void)r;
+    return QCW_OK;
+  }
   // Copies an admitted request into the arena at `off` (its own region).
   virtual int load(int slot, uint64_t off, const ServeRequest &r) = 0;
   // Runs one tick: every listed slot advances over its gate range; the states

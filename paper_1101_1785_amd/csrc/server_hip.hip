@@ -63,6 +63,21 @@ class HipExecutor : public Executor {
     return QCW_OK;
   }
 
+  // Requests whose size runs on the matrix-core variant are fused into gates
+  // of at most three qubits, as in the batched form.
+  int prepare(ServeRequest *r) override {
+    if (r->ngates == 0 || tune_.variant[r->nq] != kVarAmp4Mfma) return QCW_OK;
+    std::vector<qcw_gate> fg;
+    std::vector<qcw_c64> fm;
+    int rc = fuse_circuit(r->nq, r->gates.data(), r->ngates, r->mats.data(),
+                          (int64_t)r->mats.size(), std::min(3, r->nq), &fg, &fm);
+    if (rc) return rc;
+    r->gates.swap(fg);
+    r->mats.swap(fm);
+    r->ngates = (int)r->gates.size();
+    return QCW_OK;
+  }
+
   int load(int slot, uint64_t off, const ServeRequest &r) override {
     (void)hipSetDevice(dev_);
     SlotInfo &s = slots_[slot];

@@ -1,0 +1,110 @@
+"""Gate fusion (qcw_fuse_circuit, host code) against the oracle.
+
+Fusion merges runs of consecutive gates spanning at most three qubits into one
+gate (§2c tensor structure; gates compose in list order).  Pins: the fused
+circuit moves every state as the original does (oracle on both, FP64
+tolerance); two one-qubit gates on different qubits fuse to their Kronecker
+product (first listed qubit most significant); a circuit followed by its
+inverse fuses to the identity map; runs of one gate are copied bit for bit;
+no run spans more than max_qubits qubits and no gate is reordered.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import qcw_inputs as qi
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1101_1785_amd import _lib
+    return _lib
+
+
+def _unpack(nq, gates, mats):
+    c = qi.Circuit(nq)
+    for g in gates:
+        k = int(g["k"])
+        m = 1 << k
+        U = mats[int(g["mat"]):int(g["mat"]) + m * m].reshape(m, m)
+        c.add(U, *[int(x) for x in g["q"][:k]])
+    return c
+
+
+@pytest.mark.parametrize("nq,G,seed", [(1, 6, 1), (2, 10, 2), (3, 12, 3), (5, 30, 4), (9, 36, 5)])
+def test_fused_circuit_matches_original(L, nq, G, seed):
+    c = qi.circuit(seed, nq, G, 0)
+    fg, fm = L.fuse_circuit(nq, c)
+    f = _unpack(nq, fg, fm)
+    assert 1 <= len(f) <= len(c)
+    assert all(1 <= k <= min(3, nq) for k in f.ks)
+    for t in f.targets:
+        assert len(set(t)) == len(t) and all(1 <= q <= nq for q in t)
+    psi = qi.state(seed, nq, 1)
+    a, b = oracle.circuit(c, psi), oracle.circuit(f, psi)
+    assert np.linalg.norm(a - b) <= TOL * np.linalg.norm(a)
+
+
+def test_runs_respect_order_and_span(L):
+    """Greedy runs: the fused gate count equals an independent recount of the
+    maximal runs whose union of targets stays within the limit."""
+    for seed in range(6):
+        nq = 7
+        c = qi.circuit(40 + seed, nq, 40, 0)
+        for mq in (1, 2, 3):
+            fg, _ = L.fuse_circuit(nq, c, max_qubits=mq)
+            runs, cur = 0, set()
+            for t in c.targets:
+                if cur and len(cur | set(t)) <= mq:
+                    cur |= set(t)
+                else:
+                    runs += 1
+                    cur = set(t)
+            assert len(fg) == runs, (seed, mq)
+
+
+def test_two_one_qubit_gates_fuse_to_kron(L):
+    rng = np.random.default_rng(7)
+    A, B = qi.random_unitary(rng, 2), qi.random_unitary(rng, 2)
+    c = qi.Circuit(4).add(A, 3).add(B, 1)
+    fg, fm = L.fuse_circuit(4, c, max_qubits=2)
+    assert len(fg) == 1 and int(fg[0]["k"]) == 2 and list(fg[0]["q"][:2]) == [3, 1]
+    # union order (3, 1): qubit 3 is the most significant local bit
+    np.testing.assert_allclose(fm.reshape(4, 4), np.kron(A, B), rtol=0, atol=1e-15)
+
+
+def test_circuit_then_inverse_fuses_to_identity_map(L):
+    nq = 3
+    c = qi.circuit(11, nq, 8, 0)
+    inv = c.inverse()
+    both = qi.Circuit(nq)
+    for k, t, U in list(zip(c.ks, c.targets, c.mats)) + list(zip(inv.ks, inv.targets, inv.mats)):
+        both.add(U, *t)
+    fg, fm = L.fuse_circuit(nq, both)
+    f = _unpack(nq, fg, fm)
+    psi = qi.state(11, nq, 2)
+    np.testing.assert_allclose(oracle.circuit(f, psi), psi, rtol=0, atol=1e-13)
+
+
+def test_lone_gates_copied_bit_for_bit(L):
+    rng = np.random.default_rng(9)
+    c = qi.Circuit(6)
+    for i in range(6):
+        c.add(qi.random_unitary(rng, 8), *((1, 2, 3) if i % 2 == 0 else (4, 5, 6)))
+    fg, fm = L.fuse_circuit(6, c)
+    assert len(fg) == 6
+    g, m = L.pack_circuit(c)
+    assert np.array_equal(fg["k"], g["k"]) and np.array_equal(fg["q"], g["q"])
+    assert np.array_equal(fm, m)
+
+
+def test_fusion_validation(L):
+    c = qi.circuit(3, 4, 5, 0)
+    with pytest.raises(L.QcwError):
+        L.fuse_circuit(4, c, max_qubits=4)
+    with pytest.raises(L.QcwError):
+        L.fuse_circuit(3, qi.Circuit(4).add(qi.X, 4))   # qubit outside [1, nq]
+    g, m = L.fuse_circuit(4, qi.Circuit(4))
+    assert g.size == 0 and m.size == 0

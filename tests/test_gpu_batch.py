@@ -79,7 +79,7 @@ def test_every_variant_bit_identical(L, tmp_path):
     inst = qi.batch(5, 80, 2, 9)
     plain = _plain(L, inst)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    for v in range(5):
+    for v in range(5):  # the exact variants; amp4_mfma (5) has its own tests
         name = L.qcw_batch_variant_name(v)
         table = tmp_path / f"t{v}.txt"
         table.write_text(f"arch {arch}\n" + "".join(f"nq {q} variant {name}\n" for q in range(1, 12)))
@@ -91,6 +91,64 @@ def test_every_variant_bit_identical(L, tmp_path):
         for o, p in zip(_split(states.cpu().numpy(), inst), plain):
             assert np.array_equal(o, p), name
         b.close()
+
+
+def _forced_table(L, tmp_path, name):
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    table = tmp_path / f"{name}.txt"
+    table.write_text(f"arch {arch}\n" + "".join(f"nq {q} variant {name}\n" for q in range(1, 12)))
+    return str(table)
+
+
+@pytest.mark.parametrize("lo,hi,count,seed", [(1, 11, 150, 8), (2, 3, 64, 9), (9, 9, 48, 10)])
+def test_mfma_variant_matches_oracle_and_is_mix_independent(L, tmp_path, lo, hi, count, seed):
+    """Two- and three-qubit gates on the matrix cores: a different summation
+    order, so the bar is the oracle tolerance; each instance's bits must not
+    depend on the other instances of the launch."""
+    print(f"[gpu] mfma variant nq {lo}..{hi} x {count}", flush=True)
+    table = _forced_table(L, tmp_path, "amp4_mfma")
+    inst = qi.batch(seed, count, lo, hi)
+    states = torch.from_numpy(_pack_states(inst)).to("cuda")
+    b = L.Batch([(nq, c) for nq, _, c in inst], states, tune_table=table)
+    assert L.qcw_batch_variant_name(b.info(hi)[0]) == "amp4_mfma"
+    b.run()
+    torch.cuda.synchronize()
+    outs = _split(states.cpu().numpy(), inst)
+    b.close()
+    _check_vs_oracle(outs, inst)
+    for i in range(0, count, max(1, count // 8)):
+        nq, p, c = inst[i]
+        one = torch.from_numpy(p.copy()).to("cuda")
+        b1 = L.Batch([(nq, c)], one, tune_table=table)
+        b1.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(one.cpu().numpy(), outs[i]), i
+        b1.close()
+
+
+def test_mfma_variant_named_gates_exact(L, tmp_path):
+    """Permutation gates (CNOT, SWAP, Toffoli, X) have entries 0 and 1: every
+    product is exact, so the matrix-core path must reproduce them exactly."""
+    table = _forced_table(L, tmp_path, "amp4_mfma")
+    rng = np.random.default_rng(12)
+    inst = []
+    for i in range(40):
+        nq = int(rng.integers(3, 10))
+        c = qi.Circuit(nq)
+        for _ in range(3 * nq):
+            k = int(rng.integers(1, 4))
+            t = tuple(int(x) + 1 for x in rng.choice(nq, k, replace=False))
+            c.add({1: qi.X, 2: qi.CNOT, 3: qi.TOFFOLI}[k] if i % 2 else
+                  {1: qi.X, 2: qi.SWAP, 3: qi.TOFFOLI}[k], *t)
+        inst.append((nq, qi.state(12, nq, i), c))
+    states = torch.from_numpy(_pack_states(inst)).to("cuda")
+    b = L.Batch([(nq, c) for nq, _, c in inst], states, tune_table=table)
+    b.run()
+    torch.cuda.synchronize()
+    outs = _split(states.cpu().numpy(), inst)
+    b.close()
+    for o, r in zip(outs, oracle.circuit_batch(inst)):
+        assert np.array_equal(o, r)
 
 
 def test_graph_replays_with_eager_work_between(L):
@@ -185,11 +243,17 @@ def test_autotune_writes_a_loadable_table(L, tmp_path):
     inst = qi.batch(8, 40, 3, 5)
     states = torch.from_numpy(_pack_states(inst)).to("cuda")
     b = L.Batch([(nq, c) for nq, _, c in inst], states, tune_table=str(out))
+    chosen = {nq: L.qcw_batch_variant_name(b.info(nq)[0]) for nq in (3, 4, 5)}
     b.run()
     torch.cuda.synchronize()
-    for o, p in zip(_split(states.cpu().numpy(), inst), _plain(L, inst)):
-        assert np.array_equal(o, p)
+    outs = _split(states.cpu().numpy(), inst)
     b.close()
+    # exact variants reproduce the plain path bit for bit; the matrix-core one
+    # agrees to rounding
+    for o, p, (nq, _, _) in zip(outs, _plain(L, inst), inst):
+        if chosen[nq] != "amp4_mfma":
+            assert np.array_equal(o, p)
+    _check_vs_oracle(outs, inst)
 
 
 def test_committed_tune_table_loads(L):

@@ -95,3 +95,33 @@ def test_invalid_request_rejected_others_fine(L):
     assert np.array_equal(out, _alone(L, nq, p, c))
     assert s.counters()["rejected"] == 2
     s.close()
+
+
+def test_mfma_table_server_equals_batch_alone(L, tmp_path):
+    """With the matrix-core tile shape selected, a request's circuit is fused at
+    submit: its result must equal the batched form run on that request alone
+    with the same table (same fusion, same kernel), bit for bit, and the
+    oracle within tolerance."""
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    table = tmp_path / "mfma.txt"
+    table.write_text(f"arch {arch}\n" + "".join(f"nq {q} variant amp4_mfma\n" for q in range(1, 12)))
+    inst = qi.batch(13, 60, 2, 9)
+    s = L.Server(hbm_budget_bytes=16 << 20, max_slots=32, tune_table=str(table))
+    tickets = [s.submit(nq, c, p) for nq, p, c in inst]
+    outs = []
+    for t, (nq, p, c) in zip(tickets, inst):
+        out, st = s.wait(t, nq)
+        assert out is not None and st.status == 0
+        outs.append(out)
+    s.close()
+    refs = oracle.circuit_batch(inst)
+    for out, r, (nq, p, c) in zip(outs, refs, inst):
+        assert np.linalg.norm(out - r) <= 1e-12 * max(1, len(c) / 64) * np.linalg.norm(r)
+    for i in range(0, len(inst), 7):
+        nq, p, c = inst[i]
+        one = torch.from_numpy(p.copy()).to("cuda")
+        b = L.Batch([(nq, c)], one, tune_table=str(table))
+        b.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(one.cpu().numpy(), outs[i]), i
+        b.close()
