@@ -94,16 +94,16 @@ int make_bgate(int nq, const qcw_gate &g, int64_t nmats, BGate *out) {
   return QCW_OK;
 }
 
-int plan_batch_launch(int max_nq, int nitems, BatchLaunch *L) {
-  const int wave_amps = 1 << std::max(max_nq, 1);
-  const size_t per_wave = (size_t)(wave_amps + 128) * sizeof(double2);
-  // Each wave keeps its own LDS region; a block holds as many waves (up to
-  // four) as fit in 64 KiB of dynamic LDS.
-  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kBatchBlock / 64, (64 * 1024) / per_wave));
+// Grid of one persistent kernel: each wave needs per_wave bytes of LDS; a
+// block holds as many waves (up to four) as fit in 64 KiB of dynamic LDS.
+static int plan_shape(int max_nq, int nitems, size_t per_wave, bool mfma, BatchShape *sh) {
+  *sh = BatchShape{};
+  if (nitems <= 0) return QCW_OK;
   if (per_wave > 64 * 1024) return fail(QCW_EINVAL, "instances of %d qubits exceed LDS", max_nq);
+  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kBatchBlock / 64, (64 * 1024) / per_wave));
   const size_t lds = per_wave * wpb;
   int bpc = 0;
-  int rc = batch_kernel_occupancy(lds, wpb * 64, &bpc);
+  int rc = mfma ? batch_mfma_occupancy(lds, wpb * 64, &bpc) : batch_kernel_occupancy(lds, wpb * 64, &bpc);
   if (rc) return rc;
   if (bpc < 1) return fail(QCW_EINVAL, "batch kernel does not fit a CU with %zu B of LDS", lds);
   int dev = 0, ncu = 0;
@@ -113,11 +113,19 @@ int plan_batch_launch(int max_nq, int nitems, BatchLaunch *L) {
     return fail(QCW_EHIP, "cannot query the device");
   }
   const int blocks_needed = (nitems + wpb - 1) / wpb;
-  L->wave_amps = wave_amps;
-  L->lds_bytes = lds;
-  L->threads = wpb * 64;
-  L->blocks = (unsigned)std::max(1, std::min(ncu * bpc, blocks_needed));
+  sh->wave_amps = 1 << std::max(max_nq, 1);
+  sh->lds_bytes = lds;
+  sh->threads = wpb * 64;
+  sh->blocks = (unsigned)std::max(1, std::min(ncu * bpc, blocks_needed));
   return QCW_OK;
+}
+
+int plan_batch_launch(int max_nq, int n_exact, int n_mfma, BatchLaunch *L) {
+  const size_t amps = (size_t)1 << std::max(max_nq, 1);
+  // exact kernel: state plus two 64-entry matrix slots; matrix-core kernel: state only
+  int rc = plan_shape(max_nq, n_exact, (amps + 128) * sizeof(double2), false, &L->ex);
+  if (rc) return rc;
+  return plan_shape(max_nq, n_mfma, amps * sizeof(double2), true, &L->mf);
 }
 
 // Largest batch-resident instance: each wave needs (2^nq + 128) * 16 bytes of
@@ -277,28 +285,34 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
     in.ngates = f->second.second;
     it.g_end = in.ngates;
   }
+  // Exact-kernel items first, then matrix-core items; most work first in each.
   std::stable_sort(items.begin(), items.end(), [&](const BItem &x, const BItem &y) {
+    const bool mx = x.variant == kVarAmp4Mfma, my = y.variant == kVarAmp4Mfma;
+    if (mx != my) return my;
     const BInst &a = b->inst_h[x.inst], &c = b->inst_h[y.inst];
     return ((int64_t)a.ngates << a.nq) > ((int64_t)c.ngates << c.nq);
   });
   b->nitems = (int)items.size();
+  int n_exact = 0;
+  for (const BItem &it : items) n_exact += it.variant != kVarAmp4Mfma;
 
   int rc;
   if ((rc = upload(&b->inst_d, b->inst_h.data(), b->inst_h.size(), "instances"))) return rc;
   if ((rc = upload(&b->gates_d, bg.data(), bg.size(), "gates"))) return rc;
   if ((rc = upload(&b->mats_d, m2.data(), m2.size(), "matrices"))) return rc;
   if ((rc = upload(&b->items_d, items.data(), items.size(), "work items"))) return rc;
-  int zero = 0;
-  if ((rc = upload(&b->counter_d, &zero, 1, "work counter"))) return rc;
+  const int zeros[2] = {0, 0};
+  if ((rc = upload(&b->counter_d, zeros, 2, "work counters"))) return rc;
 
   b->L.items = b->items_d;
   b->L.nitems = b->nitems;
+  b->L.n_exact = n_exact;
   b->L.inst = b->inst_d;
   b->L.gates = b->gates_d;
   b->L.mats = b->mats_d;
   b->L.states = reinterpret_cast<double2 *>(states);
   b->L.counter = b->counter_d;
-  return plan_batch_launch(max_nq, b->nitems, &b->L);
+  return plan_batch_launch(max_nq, n_exact, b->nitems - n_exact, &b->L);
 }
 
 static int capture(qcw_batch *b, hipStream_t user) {
@@ -379,8 +393,10 @@ int qcw_batch_info(const qcw_batch *b, int nq, int *variant, int *blocks, int *l
   clear_error();
   if (!b) return fail(QCW_EINVAL, "invalid batch handle");
   if (variant) *variant = (nq >= 1 && nq <= kBatchMaxNq) ? b->tune.variant[nq] : -1;
-  if (blocks) *blocks = (int)b->L.blocks;
-  if (lds_bytes) *lds_bytes = (int)b->L.lds_bytes;
+  const int v = (nq >= 1 && nq <= kBatchMaxNq) ? b->tune.variant[nq] : -1;
+  const BatchShape &sh = (v == kVarAmp4Mfma && b->L.mf.blocks) || !b->L.ex.blocks ? b->L.mf : b->L.ex;
+  if (blocks) *blocks = (int)sh.blocks;
+  if (lds_bytes) *lds_bytes = (int)sh.lds_bytes;
   return QCW_OK;
 }
 

@@ -50,22 +50,32 @@ struct BItem {
   int32_t g_end;
 };
 
+// Grid of one of the two persistent kernels.
+struct BatchShape {
+  int wave_amps = 0;     // amplitudes of LDS state per wavefront
+  size_t lds_bytes = 0;  // dynamic LDS per block
+  int threads = 0;
+  unsigned blocks = 0;
+};
+
 struct BatchLaunch {
-  const BItem *items;
-  int nitems;
+  const BItem *items;  // items [0, n_exact) run in the exact kernel, the rest in
+  int nitems;          // the matrix-core kernel (variant kVarAmp4Mfma)
+  int n_exact;
   const BInst *inst;
   const BGate *gates;
   const double2 *mats;
   double2 *states;
-  int *counter;
-  int wave_amps;
-  size_t lds_bytes;
-  int threads;
-  unsigned blocks;
+  int *counter;        // two work counters: exact kernel, matrix-core kernel
+  BatchShape ex, mf;
 };
 
+// Enqueues the reset of the work counters (when needed) and both kernels.
 int launch_batch(const BatchLaunch &L, hipStream_t s);
 int batch_kernel_occupancy(size_t lds_bytes, int threads, int *blocks_per_cu);
+// The matrix-core kernel (batch_mfma.hip).
+int launch_batch_mfma(const BatchLaunch &L, hipStream_t s);
+int batch_mfma_occupancy(size_t lds_bytes, int threads, int *blocks_per_cu);
 
 // Per-qubit-count variant choice, loaded from a tune table or the defaults.
 struct TuneTable {
@@ -83,7 +93,8 @@ int make_bgate(int nq, const qcw_gate &g, int64_t nmats, BGate *out);
 int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats, int64_t nmats,
                  int max_qubits, std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats);
 
-// Sizes one persistent launch for instances of at most max_nq qubits.
-int plan_batch_launch(int max_nq, int nitems, BatchLaunch *L);
+// Sizes both persistent kernels for n_exact and n_mfma items of at most
+// max_nq qubits (a kernel with no items gets no grid).
+int plan_batch_launch(int max_nq, int n_exact, int n_mfma, BatchLaunch *L);
 
 }  // namespace qcw

@@ -53,7 +53,7 @@ class HipExecutor : public Executor {
       return mem_fail("arena", arena_bytes_);
     if (hipMalloc(&inst_d_, sizeof(BInst) * max_slots_) != hipSuccess ||
         hipMalloc(&items_d_, sizeof(BItem) * max_slots_) != hipSuccess ||
-        hipMalloc(&counter_d_, sizeof(int)) != hipSuccess)
+        hipMalloc(&counter_d_, 2 * sizeof(int)) != hipSuccess)
       return mem_fail("tables", 0);
     if (hipHostMalloc(&inst_h_, sizeof(BInst) * max_slots_) != hipSuccess ||
         hipHostMalloc(&items_h_, sizeof(BItem) * max_slots_) != hipSuccess ||
@@ -120,16 +120,22 @@ class HipExecutor : public Executor {
       items_h_[i] = {i, tune_.variant[s.nq], items[i].g_begin, items[i].g_end};
       max_nq = std::max(max_nq, s.nq);
     }
-    // Largest work first, as in the batched form.
+    // As in the batched form: exact-kernel items first, then matrix-core
+    // items; the most work first in each.
     std::stable_sort(items_h_, items_h_ + n, [&](const BItem &a, const BItem &b) {
+      const bool ma = a.variant == kVarAmp4Mfma, mb = b.variant == kVarAmp4Mfma;
+      if (ma != mb) return mb;
       return ((int64_t)(a.g_end - a.g_begin) << inst_h_[a.inst].nq) >
              ((int64_t)(b.g_end - b.g_begin) << inst_h_[b.inst].nq);
     });
+    int n_exact = 0;
+    for (int i = 0; i < n; ++i) n_exact += items_h_[i].variant != kVarAmp4Mfma;
     BatchLaunch L{};
-    int rc = plan(max_nq, n, &L);
+    int rc = plan(max_nq, n_exact, n - n_exact, &L);
     if (rc) return rc;
     L.items = items_d_;
     L.nitems = n;
+    L.n_exact = n_exact;
     L.inst = inst_d_;
     L.gates = (const BGate *)arena_;
     L.mats = (const double2 *)arena_;
@@ -167,17 +173,21 @@ class HipExecutor : public Executor {
     int64_t state_off = 0, gate_off = 0;
   };
 
-  int plan(int max_nq, int n, BatchLaunch *L) {
+  int plan(int max_nq, int n_exact, int n_mfma, BatchLaunch *L) {
     auto &c = plans_[max_nq];
     if (!c.valid) {
-      // Size the grid once per LDS footprint for the largest possible tick.
-      int rc = plan_batch_launch(max_nq, max_slots_, &c.L);
+      // Size both grids once per LDS footprint for the largest possible tick.
+      int rc = plan_batch_launch(max_nq, max_slots_, max_slots_, &c.L);
       if (rc) return rc;
       c.valid = true;
     }
     *L = c.L;
-    const int wpb = L->threads / 64;
-    L->blocks = (unsigned)std::max(1, std::min<int>((int)c.L.blocks, (n + wpb - 1) / wpb));
+    auto clamp = [](BatchShape &sh, int items) {
+      const int wpb = sh.threads / 64;
+      sh.blocks = items > 0 ? (unsigned)std::max(1, std::min<int>((int)sh.blocks, (items + wpb - 1) / wpb)) : 0u;
+    };
+    clamp(L->ex, n_exact);
+    clamp(L->mf, n_mfma);
     return QCW_OK;
   }
 
