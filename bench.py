@@ -53,6 +53,8 @@ def _args():
     p.add_argument("--serve-seconds", type=float, default=10.0,
                    help="length of the open-loop serving run (the full workload is 60 s)")
     p.add_argument("--serve-rate", type=float, default=2000.0)
+    p.add_argument("--serve-sweep-seconds", type=float, default=2.0,
+                   help="seconds per offered rate in the serving rate sweep (0: skip)")
     p.add_argument("--skip-extra", action="store_true",
                    help="only the headline workload (no batched/serving sections)")
     p.add_argument("--counters", action="store_true",
@@ -214,13 +216,17 @@ def bench_serving(L, qi, seed, rate, seconds, lo, hi, tune_table, pool=4096):
     sched = t0 + (arr * 1e9).astype(np.int64)
     ready = threading.Semaphore(0)
 
+    submit_s = [0.0]
+
     def client():
         for i in range(arr.size):
             dt = (sched[i] - time.monotonic_ns()) / 1e9
             if dt > 0:
                 time.sleep(dt)
             nq, p, g, m = reqs[i % pool]
+            c0 = time.perf_counter()
             tickets[i] = s.submit(nq, psi0=p, gates=g, mats=m)
+            submit_s[0] += time.perf_counter() - c0
             ready.release()
 
     def collector():
@@ -245,8 +251,78 @@ def bench_serving(L, qi, seed, rate, seconds, lo, hi, tune_table, pool=4096):
         "max_ms": float(lat.max()), "solves_per_s": float(arr.size / span),
         "failed": int(np.count_nonzero(status)), "ticks": int(cnt["ticks"]),
         "peak_active": int(cnt["peak_active"]), "peak_pending": int(cnt["peak_pending"]),
+        "client_submit_us": submit_s[0] / arr.size * 1e6,
         "latency_from": "scheduled arrival to completion (open loop)",
     }
+
+
+def bench_plain_serving(torch, L, qi, seed, rate, seconds, lo, hi, pool=4096):
+    """The same open-loop arrivals served one request at a time on the plain path:
+    copy the state in, one sweep per gate (qcw_circuit), copy the result out.
+    Device and pinned host buffers are allocated once per qubit count."""
+    arr = qi.poisson_arrivals(seed, rate, seconds)
+    inst = qi.batch(seed, pool, lo, hi)
+    reqs = [(nq, torch.from_numpy(p).pin_memory(), *L.pack_circuit(c), len(c))
+            for nq, p, c in inst]
+    dev = {q: torch.empty(1 << q, dtype=torch.complex128, device="cuda") for q in range(lo, hi + 1)}
+    out = {q: torch.empty(1 << q, dtype=torch.complex128).pin_memory() for q in range(lo, hi + 1)}
+
+    def serve(nq, p, g, m, G):
+        psi = dev[nq]
+        psi.copy_(p, non_blocking=True)
+        L.qcw_circuit(psi, nq, g, G, m, m.size)
+        out[nq].copy_(psi, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+
+    for r in reqs[:64]:                                  # warm
+        serve(*r)
+    done_ns = np.zeros(arr.size, np.int64)
+    t0 = time.monotonic_ns() + 20_000_000
+    sched = t0 + (arr * 1e9).astype(np.int64)
+    for i in range(arr.size):
+        dt = (sched[i] - time.monotonic_ns()) / 1e9
+        if dt > 0:
+            time.sleep(dt)
+        serve(*reqs[i % pool])
+        done_ns[i] = time.monotonic_ns()
+    lat = (done_ns - sched) / 1e6
+    span = (done_ns.max() - sched.min()) / 1e9
+    return {"rate_per_s": rate, "requests": int(arr.size),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "solves_per_s": float(arr.size / span)}
+
+
+def bench_serving_sweep(torch, L, qi, tt, seconds, rates=(2000, 8000, 12000, 16000, 24000),
+                        plain_rates=(1000, 2000, 4000, 6000, 8000)):
+    """Raise the offered rate until p99 diverges, for the continuous-batching server
+    and for the plain one-request-at-a-time path.  A rate counts as sustained when
+    nothing failed, at least 95% of the offered rate completed, and p99 stayed
+    within 20x the p99 at the lowest rate."""
+    def sweep(run, rs):
+        rows, best, base = [], None, None
+        for r in rs:
+            d = run(r)
+            rows.append({k: d[k] for k in ("rate_per_s", "p50_ms", "p99_ms", "solves_per_s")
+                         if k in d} | ({"client_submit_us": d["client_submit_us"]}
+                                       if "client_submit_us" in d else {}))
+            base = base if base is not None else d["p99_ms"]
+            ok = d.get("failed", 0) == 0 and d["solves_per_s"] >= 0.95 * r and \
+                d["p99_ms"] <= 20 * base
+            if not ok:
+                break
+            best = r
+        return rows, best
+    srv, srv_best = sweep(lambda r: bench_serving(L, qi, 3, r, seconds, 3, 9, tt), rates)
+    pln, pln_best = sweep(lambda r: bench_plain_serving(torch, L, qi, 3, r, seconds, 3, 9),
+                          plain_rates)
+    return {"seconds_per_rate": seconds, "nq_range": [3, 9], "seed": 3,
+            "server": srv, "plain": pln,
+            "max_sustained_rate_server": srv_best, "max_sustained_rate_plain": pln_best,
+            "criterion": "no failures, >= 95% of offered rate completed, p99 <= 20x the "
+                         "lowest-rate p99; sweep stops at the first rate that misses",
+            "client": "one Python thread submits (client_submit_us per request, including "
+                      "the host-side fusion of the request's circuit) and one collects; above "
+                      "~1/client_submit_us the client, not the server, sets the rate"}
 
 
 def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
@@ -458,6 +534,9 @@ def main():
         extra["multiverse_nq12"] = bench_multiverse(torch, L, qi, 12, 5)
         extra["multiverse_nq5"] = bench_multiverse(torch, L, qi, 5, 5, steps=200)
         extra["serving_config3"] = bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9, tt)
+        if a.serve_sweep_seconds > 0:
+            extra["serving_rate_sweep"] = bench_serving_sweep(torch, L, qi, tt,
+                                                              a.serve_sweep_seconds)
 
     out = {
         "metric": METRIC,

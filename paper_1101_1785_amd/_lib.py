@@ -125,7 +125,8 @@ def _mat(U, k: int | None = None) -> np.ndarray:
 
 
 def _hptr(a: np.ndarray):
-    return a.ctypes.data_as(_P)
+    """Host address of a numpy array (an int, which ctypes passes as void*)."""
+    return a.ctypes.data
 
 
 def _dptr(t):

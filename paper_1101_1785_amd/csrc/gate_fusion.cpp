@@ -21,10 +21,12 @@ namespace {
 
 using cd = std::complex<double>;
 
+// A run being fused: its union of qubits and the product matrix on them
+// (2^u x 2^u, row-major, u <= 3; fixed storage, no allocation).
 struct Block {
-  int u = 0;           // qubits in the union
+  int u = 0;
   int q[3] = {0, 0, 0};  // union qubits, first = most significant local bit
-  std::vector<cd> M;   // 2^u x 2^u, row-major
+  cd M[64];
 };
 
 int local_bit(const Block &b, int qubit) {
@@ -33,15 +35,24 @@ int local_bit(const Block &b, int qubit) {
   return -1;
 }
 
+// Starts a block with one gate: its qubits in its own order, its matrix.
+void start(Block &b, const qcw_gate &g, const qcw_c64 *U) {
+  b.u = g.k;
+  for (int j = 0; j < g.k; ++j) b.q[j] = g.q[j];
+  const int mm = 1 << (2 * g.k);
+  for (int e = 0; e < mm; ++e) b.M[e] = cd(U[e].re, U[e].im);
+}
+
 // Adds qubit `qubit` as the new least significant local bit: M <- M (x) I_2.
 void grow(Block &b, int qubit) {
-  const int m = 1 << b.u;
-  std::vector<cd> M2((size_t)4 * m * m, cd(0.0, 0.0));
+  const int m = 1 << b.u, m2 = 2 * m;
+  cd M2[64];
+  for (int e = 0; e < m2 * m2; ++e) M2[e] = cd(0.0, 0.0);
   for (int r = 0; r < m; ++r)
     for (int c = 0; c < m; ++c)
-      for (int a = 0; a < 2; ++a) M2[(size_t)(2 * r + a) * (2 * m) + (2 * c + a)] = b.M[(size_t)r * m + c];
+      for (int a = 0; a < 2; ++a) M2[(2 * r + a) * m2 + (2 * c + a)] = b.M[r * m + c];
   b.q[b.u++] = qubit;
-  b.M.swap(M2);
+  for (int e = 0; e < m2 * m2; ++e) b.M[e] = M2[e];
 }
 
 // M <- E(g) M, with E(g) the gate extended to the block's qubits.
@@ -53,30 +64,31 @@ void apply_gate(Block &b, const qcw_gate &g, const qcw_c64 *U) {
     bits[j] = local_bit(b, g.q[j]);
     mask |= 1 << bits[j];
   }
-  auto gidx = [&](int R) {  // local index of the gate's targets inside R
-    int r = 0;
-    for (int j = 0; j < g.k; ++j) r = (r << 1) | ((R >> bits[j]) & 1);
-    return r;
-  };
-  auto place = [&](int rest, int r) {  // block index with the gate's bits set from r
-    int R = rest;
+  int spread[8];  // local index c of the gate -> block index bits
+  for (int c = 0; c < mg; ++c) {
+    int R = 0;
     for (int j = 0; j < g.k; ++j)
-      if ((r >> (g.k - 1 - j)) & 1) R |= 1 << bits[j];
-    return R;
-  };
-  std::vector<cd> out((size_t)m * m, cd(0.0, 0.0));
+      if ((c >> (g.k - 1 - j)) & 1) R |= 1 << bits[j];
+    spread[c] = R;
+  }
+  cd out[64];
   for (int R = 0; R < m; ++R) {
-    const int rest = R & ~mask, rg = gidx(R);
+    const int rest = R & ~mask;
+    int rg = 0;
+    for (int j = 0; j < g.k; ++j) rg = (rg << 1) | ((R >> bits[j]) & 1);
     for (int C = 0; C < m; ++C) {
-      cd acc(0.0, 0.0);
+      // plain complex product (no Annex G special-case handling)
+      double ar = 0.0, ai = 0.0;
       for (int c = 0; c < mg; ++c) {
         const qcw_c64 u = U[rg * mg + c];
-        acc += cd(u.re, u.im) * b.M[(size_t)place(rest, c) * m + C];
+        const cd v = b.M[(rest | spread[c]) * m + C];
+        ar += u.re * v.real() - u.im * v.imag();
+        ai += u.re * v.imag() + u.im * v.real();
       }
-      out[(size_t)R * m + C] = acc;
+      out[R * m + C] = cd(ar, ai);
     }
   }
-  b.M.swap(out);
+  for (int e = 0; e < m * m; ++e) b.M[e] = out[e];
 }
 
 }  // namespace
@@ -86,6 +98,8 @@ int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
   if (max_qubits < 1 || max_qubits > 3) return fail(QCW_EINVAL, "max_qubits=%d outside [1, 3]", max_qubits);
   out_gates->clear();
   out_mats->clear();
+  out_gates->reserve((size_t)ngates);
+  out_mats->reserve((size_t)64 * ngates);
   Block cur;
   int run = 0;               // gates in the current block
   const qcw_gate *first = nullptr;
@@ -101,7 +115,7 @@ int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
     } else {
       g.k = cur.u;
       for (int j = 0; j < cur.u; ++j) g.q[j] = cur.q[j];
-      for (const cd &z : cur.M) out_mats->push_back({z.real(), z.imag()});
+      for (int e = 0; e < (1 << (2 * cur.u)); ++e) out_mats->push_back({cur.M[e].real(), cur.M[e].imag()});
     }
     out_gates->push_back(g);
     run = 0;
@@ -117,13 +131,13 @@ int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
     for (int j = 0; j < g.k; ++j) fresh += local_bit(cur, g.q[j]) < 0;
     if (run && cur.u + fresh > max_qubits) flush();
     if (!run) {
-      cur = Block();
-      cur.M.assign(1, cd(1.0, 0.0));
+      start(cur, g, mats + g.mat);
       first = &g;
+    } else {
+      for (int j = 0; j < g.k; ++j)
+        if (local_bit(cur, g.q[j]) < 0) grow(cur, g.q[j]);
+      apply_gate(cur, g, mats + g.mat);
     }
-    for (int j = 0; j < g.k; ++j)
-      if (local_bit(cur, g.q[j]) < 0) grow(cur, g.q[j]);
-    apply_gate(cur, g, mats + g.mat);
     ++run;
   }
   flush();
