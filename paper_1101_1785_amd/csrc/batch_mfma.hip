@@ -8,217 +8,21 @@
 // The summation order differs from the plain path, so results agree with it
 // to rounding, not bit for bit.
 //
-// The complex m x m product is the real 2m x 2m product
-//   [Re y; Im y] = [[Re U, -Im U], [Im U, Re U]] [Re x; Im x]
-// over many groups at once (one group per column).  Lane layouts of the two
-// instructions used (l = lane):
-//   v_mfma_f64_4x4x4f64, four independent 4x4x4 blocks, block (l >> 2) & 3:
-//     A[l & 3][l >> 4], B[l >> 4][l & 3], D[l >> 4][l & 3]
-//   v_mfma_f64_16x16x4f64:
-//     A[l & 15][l >> 4], B[l >> 4][l & 15], D[4v + (l >> 4)][l & 15], v = 0..3
-// Each lane holds only the one or two matrix entries its A operand needs,
-// prefetched from HBM into registers one gate ahead, so a wave keeps no copy
-// of the matrix in LDS and its LDS holds the state alone.  Every lane reads
-// and writes back exactly the amplitudes it owns, so a gate needs no exchange
-// between lanes.
+// The gate updates themselves (real form of the complex product, lane
+// layouts of the FP64 matrix-core instructions) are in mfma_gates.h.  Each
+// lane's one or two matrix entries are prefetched from HBM into registers one
+// gate ahead, so a wave keeps no copy of the matrix in LDS and its LDS holds
+// the state alone.
 #include <hip/hip_runtime.h>
 
 #include "batch_common.h"
+#include "mfma_gates.h"
 #include "qcw_batch.h"
 #include "qcw_device.h"
 
 namespace qcw {
 
 namespace {
-
-typedef double qcw_d4 __attribute__((ext_vector_type(4)));
-
-// Tiles of 16 groups applied together by one gate step: their LDS latencies
-// and matrix-core chains overlap.
-constexpr int kTiles = 4;
-
-// Wave-uniform fields of a gate descriptor (see load_desc).  off1, off2, off4
-// are the strides of local bits 0, 1, 2 (off[1 << j]).
-struct Fields {
-  int k, sb0, sb1, sb2;
-  uint32_t off1, off2, off4;
-};
-
-__device__ __forceinline__ Fields fields_of(uint32_t d) {
-  Fields f;
-  f.k = (int)desc_field(d, 0);
-  f.sb0 = (int)desc_field(d, 1);
-  f.sb1 = (int)desc_field(d, 2);
-  f.sb2 = (int)desc_field(d, 3);
-  f.off1 = desc_field(d, 5);
-  f.off2 = desc_field(d, 6);
-  f.off4 = desc_field(d, 8);
-  return f;
-}
-
-// Offset of local index r from its group's base (first target = most
-// significant bit of r).
-__device__ __forceinline__ uint32_t member(const Fields &f, int r) {
-  return ((r & 1) ? f.off1 : 0u) + ((r & 2) ? f.off2 : 0u) + ((r & 4) ? f.off4 : 0u);
-}
-
-// The matrix entries lane `lane` needs for a gate of the given descriptor:
-//   k = 3: U[r][s] and U[r][4 + s], r = 4 ((l & 15) >> 3) + (l & 3), s = l >> 4
-//   k = 2: U[l & 3][l >> 4]
-//   k = 1: U[l & 3] (lanes 0..3 hold the whole 2 x 2 matrix, row-major)
-// Both loads are always issued (for k < 3 the second repeats the first), so
-// the operands stay in registers.
-struct Operands {
-  double2 p0, p1;
-};
-__device__ __forceinline__ Operands fetch_operands(uint32_t d, const double2 *__restrict__ mats,
-                                                   int lane) {
-  const int k = (int)desc_field(d, 0);
-  const double2 *U = mats + desc_mat(d);
-  const int row = lane & 15, r = 4 * (row >> 3) + (row & 3), s = lane >> 4;
-  const int i0 = k == 3 ? r * 8 + s : (k == 2 ? (lane & 3) * 4 + s : (lane & 3));
-  const int i1 = k == 3 ? r * 8 + 4 + s : i0;
-  Operands o;
-  o.p0 = U[i0];
-  o.p1 = U[i1];
-  return o;
-}
-
-__device__ __forceinline__ double lane_double(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
-// One-qubit gate on the vector ALU: the 2 x 2 matrix is made wave-uniform
-// (readlane from lanes 0..3); each lane takes four groups per step.
-__device__ __forceinline__ void gate1(double2 *S, int nq, const Fields &f, double2 p0, int lane) {
-  double2 u[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) u[e] = make_double2(lane_double(p0.x, e), lane_double(p0.y, e));
-  const uint32_t ngroups = 1u << (nq - 1);
-  const uint32_t lane_base = insert_zeros<1, uint32_t>((uint32_t)lane, f.sb0, 0, 0);
-  for (uint32_t j0 = 0; j0 < ngroups; j0 += 256) {
-    double2 x0[4], x1[4];
-    uint32_t b[4];
-    bool ok[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      ok[t] = j0 + 64 * t + lane < ngroups;
-      b[t] = lane_base | insert_zeros<1, uint32_t>(j0 + 64 * t, f.sb0, 0, 0);
-      if (ok[t]) {
-        x0[t] = S[b[t]];
-        x1[t] = S[b[t] + f.off1];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (ok[t]) {
-        double2 y0 = make_double2(0.0, 0.0), y1 = y0;
-        y0 = cmad(y0, u[0], x0[t]);
-        y0 = cmad(y0, u[1], x1[t]);
-        y1 = cmad(y1, u[2], x0[t]);
-        y1 = cmad(y1, u[3], x1[t]);
-        S[b[t]] = y0;
-        S[b[t] + f.off1] = y1;
-      }
-  }
-}
-
-// Two-qubit gate, 16 groups per tile: columns are groups t0 + 16 t + (l & 15);
-// the real 8 x 8 matrix splits into four 4 x 4 blocks acting on (Re x, Im x):
-//   Re y = ReU Re x - ImU Im x,  Im y = ImU Re x + ReU Im x.
-// Lane l holds U[l & 3][l >> 4] and owns amplitude l >> 4 of its group.  FULL:
-// every tile of the step is complete (2^(nq-2) >= 16 kTiles), no masking.
-template <bool FULL>
-__device__ __forceinline__ void gate2(double2 *S, int nq, const Fields &f, double2 u, int lane) {
-  const uint32_t ngroups = 1u << (nq - 2);
-  // insert_zeros deposits the bits of the group index into the non-target
-  // positions, so for t0 + 16 t + (l & 15) it is the OR of the deposits of
-  // the wave-uniform part and of l & 15.
-  const uint32_t lane_p =
-      insert_zeros<2, uint32_t>((uint32_t)(lane & 15), f.sb0, f.sb1, 0) + member(f, lane >> 4);
-  const bool lane_ok = FULL || (uint32_t)(lane & 15) < ngroups;
-  for (uint32_t t0 = 0; t0 < ngroups; t0 += 16 * kTiles) {
-    uint32_t p[kTiles];
-    bool ok[kTiles];
-    double2 x[kTiles];
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
-      ok[t] = FULL || (lane_ok && t0 + 16 * t < ngroups);
-      p[t] = lane_p | insert_zeros<2, uint32_t>(t0 + 16 * t, f.sb0, f.sb1, 0);
-      x[t] = make_double2(0.0, 0.0);
-      if (ok[t]) x[t] = S[p[t]];
-    }
-    double re[kTiles], im[kTiles];
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
-      re[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, x[t].x, 0.0, 0, 0, 0);
-      im[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(u.y, x[t].x, 0.0, 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
-      re[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(-u.y, x[t].y, re[t], 0, 0, 0);
-      im[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, x[t].y, im[t], 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t)
-      if (ok[t]) S[p[t]] = make_double2(re[t], im[t]);
-  }
-}
-
-// Three-qubit gate, 16 groups per tile.  Real index of (amplitude c, part p)
-// is 8 (c >> 2) + 4 p + (c & 3), so a lane's four output rows (4v + (l >> 4))
-// are Re, Im of amplitude s = l >> 4 and Re, Im of amplitude 4 + s -- the two
-// amplitudes it also supplies as B.  Lane l holds the A entries of its row
-// l & 15 (fetch_operands): real part for a Re row, and the signs and parts of
-// the real form for an Im row.
-template <bool FULL>
-__device__ __forceinline__ void gate3(double2 *S, int nq, const Fields &f, double2 u0, double2 u1,
-                                      int lane) {
-  const uint32_t ngroups = 1u << (nq - 3);
-  const int s = lane >> 4;
-  const bool im_row = (lane >> 2) & 1;
-  const double a0 = im_row ? u0.y : u0.x, a1 = im_row ? u0.x : -u0.y;
-  const double a2 = im_row ? u1.y : u1.x, a3 = im_row ? u1.x : -u1.y;
-  const uint32_t m0 = member(f, s), m1 = member(f, 4 + s);
-  const uint32_t lane_b = insert_zeros<3, uint32_t>((uint32_t)(lane & 15), f.sb0, f.sb1, f.sb2);
-  const bool lane_ok = FULL || (uint32_t)(lane & 15) < ngroups;
-  for (uint32_t t0 = 0; t0 < ngroups; t0 += 16 * kTiles) {
-    uint32_t b[kTiles];
-    bool ok[kTiles];
-    double2 x0[kTiles], x1[kTiles];
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
-      ok[t] = FULL || (lane_ok && t0 + 16 * t < ngroups);
-      b[t] = lane_b | insert_zeros<3, uint32_t>(t0 + 16 * t, f.sb0, f.sb1, f.sb2);
-      x0[t] = make_double2(0.0, 0.0);
-      x1[t] = x0[t];
-      if (ok[t]) {
-        x0[t] = S[b[t] + m0];
-        x1[t] = S[b[t] + m1];
-      }
-    }
-    qcw_d4 d[kTiles];
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
-      d[t] = qcw_d4{0.0, 0.0, 0.0, 0.0};
-      d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0[t].x, d[t], 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0[t].y, d[t], 0, 0, 0);
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, x1[t].x, d[t], 0, 0, 0);
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, x1[t].y, d[t], 0, 0, 0);
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t)
-      if (ok[t]) {
-        S[b[t] + m0] = make_double2(d[t][0], d[t][1]);
-        S[b[t] + m1] = make_double2(d[t][2], d[t][3]);
-      }
-  }
-}
 
 __device__ void run_mfma_instance(const BInst &in, const BGate *__restrict__ gates,
                                   const double2 *__restrict__ mats, double2 *__restrict__ states,
@@ -230,25 +34,19 @@ __device__ void run_mfma_instance(const BInst &in, const BGate *__restrict__ gat
   if (g_begin < g_end) {
     // Descriptors arrive two gates ahead, matrix operands one gate ahead.
     const uint32_t *gd = reinterpret_cast<const uint32_t *>(gates + in.gate_off);
+    auto operands = [&](uint32_t d) {
+      return mc::fetch_operands((int)desc_field(d, 0), mats + desc_mat(d), lane);
+    };
     uint32_t dcur = load_desc(gd, g_begin, g_end, lane);
     uint32_t dnext = load_desc(gd, g_begin + 1, g_end, lane);
-    Operands nxt = fetch_operands(dcur, mats, lane);
-    const bool full2 = nq - 2 >= 4 + 2, full3 = nq - 3 >= 4 + 2;  // 2^(nq-k) >= 16 kTiles
+    mc::Operands nxt = operands(dcur);
     for (int gi = g_begin; gi < g_end; ++gi) {
-      const Fields f = fields_of(dcur);
+      const mc::Fields f = mc::fields_of(dcur);
       const double2 u0 = nxt.p0, u1 = nxt.p1;
       const uint32_t dnext2 = load_desc(gd, gi + 2, g_end, lane);
-      if (gi + 1 < g_end) nxt = fetch_operands(dnext, mats, lane);
+      if (gi + 1 < g_end) nxt = operands(dnext);
       wave_lds_sync();
-      if (f.k == 3) {
-        if (full3) gate3<true>(S, nq, f, u0, u1, lane);
-        else gate3<false>(S, nq, f, u0, u1, lane);
-      } else if (f.k == 2) {
-        if (full2) gate2<true>(S, nq, f, u0, lane);
-        else gate2<false>(S, nq, f, u0, lane);
-      } else {
-        gate1(S, nq, f, u0, lane);
-      }
+      mc::apply(S, 0, 1u << (nq - f.k), f, u0, u1, lane);
       dcur = dnext;
       dnext = dnext2;
     }

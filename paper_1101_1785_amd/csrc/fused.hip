@@ -509,29 +509,9 @@ static int launch_passes_n(int threads, int L, qcw_c64 *psi, int nq, const Fused
   }
 }
 
-int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, int low_bits, int threads, hipStream_t s) {
-  std::vector<Geom> geo(ngates);
-  for (int i = 0; i < ngates; ++i) {
-    int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
-    if (rc) return rc;
-  }
-  if (ngates == 0) return QCW_OK;
-  // Small states: the whole state is one tile; use the one-gate sweep when a
-  // tile would not reach a full block of work.
-  const int T = std::min(tile_bits, nq);
-  const int L = low_bits;
-  if (T < 8 || nq < 9) {
-    for (int i = 0; i < ngates; ++i) {
-      int rc = launch_sweep(geo[i], mats + gates[i].mat, psi, psi, s);
-      if (rc) return rc;
-    }
-    return QCW_OK;
-  }
-  std::vector<FusedPass> passes;
-  std::vector<FusedGate> fg;
-  int rc = plan_passes(nq, geo, gates, mats, FusedShape{T, L}, passes, fg);
-  if (rc) return rc;
+// Uploads a plan into the stream's plan buffer.
+static int upload_plan(const std::vector<FusedPass> &passes, const std::vector<FusedGate> &fg,
+                       hipStream_t s, const FusedPass **dp, const FusedGate **dg) {
   const size_t pbytes = passes.size() * sizeof(FusedPass);
   const size_t need = pbytes + fg.size() * sizeof(FusedGate);
   void *dev = nullptr;
@@ -564,8 +544,37 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
   }
   // the host blob must outlive the (possibly staged) copy
   if (hipStreamSynchronize(s) != hipSuccess) return fail(QCW_EHIP, "fused plan upload sync");
-  const FusedPass *dp = (const FusedPass *)dev;
-  const FusedGate *dg = (const FusedGate *)((char *)dev + pbytes);
+  *dp = (const FusedPass *)dev;
+  *dg = (const FusedGate *)((char *)dev + pbytes);
+  return QCW_OK;
+}
+
+int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
+              int tile_bits, int low_bits, int threads, hipStream_t s) {
+  std::vector<Geom> geo(ngates);
+  for (int i = 0; i < ngates; ++i) {
+    int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
+    if (rc) return rc;
+  }
+  if (ngates == 0) return QCW_OK;
+  // Small states: the whole state is one tile; use the one-gate sweep when a
+  // tile would not reach a full block of work.
+  const int T = std::min(tile_bits, nq);
+  const int L = low_bits;
+  if (T < 8 || nq < 9) {
+    for (int i = 0; i < ngates; ++i) {
+      int rc = launch_sweep(geo[i], mats + gates[i].mat, psi, psi, s);
+      if (rc) return rc;
+    }
+    return QCW_OK;
+  }
+  std::vector<FusedPass> passes;
+  std::vector<FusedGate> fg;
+  int rc = plan_passes(nq, geo, gates, mats, FusedShape{T, L}, passes, fg);
+  if (rc) return rc;
+  const FusedPass *dp = nullptr;
+  const FusedGate *dg = nullptr;
+  if ((rc = upload_plan(passes, fg, s, &dp, &dg))) return rc;
   const int np = (int)passes.size();
   switch (T) {
     case 8: return launch_passes_l<8, 256>(L, psi, nq, dp, dg, np, s);

@@ -136,3 +136,4 @@ def test_fullsize_fused_equals_plain_and_roundtrips(L):
     assert err <= TOL * max(1.0, 2 * len(c) / 64)
     del a, ref
     torch.cuda.empty_cache()
+
