@@ -325,6 +325,44 @@ def bench_serving_sweep(torch, L, qi, tt, seconds, rates=(2000, 8000, 12000, 160
                       "~1/client_submit_us the client, not the server, sets the rate"}
 
 
+def bench_grover(torch, L, qi, tt, count=1024, n=6, seed=9):
+    """Textbook Grover search (qcw_inputs.workloads) over n data qubits, at the
+    optimal iteration count, for `count` random marked items in one batched
+    launch; every result checked against the closed form."""
+    from qcw_inputs import workloads as W
+    k = W.grover_optimal_iterations(n)
+    rng = np.random.default_rng([seed, 3])
+    marked = rng.integers(0, 1 << n, count)
+    cache = {}
+    circs = []
+    for m in marked:
+        if int(m) not in cache:
+            cache[int(m)] = W.grover(n, int(m), k)
+        circs.append(cache[int(m)])
+    nq = circs[0].nq
+    psi0 = np.zeros(1 << nq, complex)
+    psi0[0] = 1.0
+    states = torch.from_numpy(np.tile(psi0, count)).to("cuda")
+    b = L.Batch([(nq, c) for c in circs], states, tune_table=tt)
+    b.run()
+    torch.cuda.synchronize()
+    flat = states.cpu().numpy().reshape(count, 1 << nq)
+    a, o = W.grover_amplitudes(n, k)
+    err = 0.0
+    for i, m in enumerate(marked):
+        ref = np.zeros(1 << nq, complex)
+        ref[np.arange(1 << n) << (nq - n)] = o
+        ref[int(m) << (nq - n)] = a
+        err = max(err, float(np.max(np.abs(flat[i] - ref))))
+    tm = _time_batch(torch, b, 20)
+    b.close()
+    ms = min(tm.values())
+    return {"data_qubits": n, "qubits": nq, "iterations": k, "gates_per_search": len(circs[0]),
+            "searches": count, "us_per_launch": ms * 1e3, "searches_per_s": count / (ms * 1e-3),
+            "success_probability": a * a, "max_abs_err_vs_closed_form": err,
+            "launch": min(tm, key=tm.get)}
+
+
 def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
     """Multiverse density-matrix steps (Eq. rhoE4): channel of n_p single-hit and
     n_p double-hit Pauli paths (weights eps*p_s/n_p, p1=.95, p2=.05, p_keep=1-eps),
@@ -531,6 +569,7 @@ def main():
         extra["batched_config4"] = bench_batched(torch, L, qi, 4, 4096, 9, 9, tt,
                                                  label="4096 x nq 9")
         extra["plain_nq9"] = bench_plain_small(torch, L, qi, 9, 1)
+        extra["grover_n6"] = bench_grover(torch, L, qi, tt)
         extra["multiverse_nq12"] = bench_multiverse(torch, L, qi, 12, 5)
         extra["multiverse_nq5"] = bench_multiverse(torch, L, qi, 5, 5, steps=200)
         extra["serving_config3"] = bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9, tt)
