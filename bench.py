@@ -363,6 +363,38 @@ def bench_grover(torch, L, qi, tt, count=1024, n=6, seed=9):
             "launch": min(tm, key=tm.get)}
 
 
+def bench_shard(torch, L, qi, nq=32):
+    """One GPU's kernel for gates on the top qubit of a 32-qubit state split over
+    two GPUs (qcw_op_shard): its 2^31-amplitude half updated from itself and the
+    partner's staged half.  Algorithmic traffic 48 B per local amplitude."""
+    h = 1 << (nq - 1)
+    free, _ = torch.cuda.mem_get_info()
+    if free < 2 * 16 * h + (8 << 30):
+        return {"skipped": "not enough device memory"}
+    loc = torch.zeros(h, dtype=torch.complex128, device="cuda")
+    rem = torch.zeros_like(loc)
+    rng = np.random.default_rng(12)
+    out = {"nq_total": nq, "amplitudes_per_gpu": h, "bytes_per_amplitude": 48}
+    for k, t in ((1, (1,)), (2, (1, 17)), (3, (5, 1, 30))):
+        U = qi.random_unitary(rng, 1 << k)
+        L.qcw_op_shard(k, t, U, 0, loc, rem, nq)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            L.qcw_op_shard(k, t, U, 0, loc, rem, nq)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        out[f"k{k}_targets"] = list(t)
+        out[f"k{k}_ms"] = ms
+        out[f"k{k}_gbs"] = 48 * h / (ms * 1e-3) / 1e9
+    del loc, rem
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
     """Multiverse density-matrix steps (Eq. rhoE4): channel of n_p single-hit and
     n_p double-hit Pauli paths (weights eps*p_s/n_p, p1=.95, p2=.05, p_keep=1-eps),
@@ -570,6 +602,7 @@ def main():
                                                  label="4096 x nq 9")
         extra["plain_nq9"] = bench_plain_small(torch, L, qi, 9, 1)
         extra["grover_n6"] = bench_grover(torch, L, qi, tt)
+        extra["shard_nq32"] = bench_shard(torch, L, qi)
         extra["multiverse_nq12"] = bench_multiverse(torch, L, qi, 12, 5)
         extra["multiverse_nq5"] = bench_multiverse(torch, L, qi, 5, 5, steps=200)
         extra["serving_config3"] = bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9, tt)

@@ -153,6 +153,23 @@ int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bit
                          int low_bits);
 
 /*
+ * One GPU's part of a gate on a state split over two GPUs by qubit 1 (the most
+ * significant bit, §2c), the distribution of the paper's MPI predecessor (§5,
+ * general remarks).  The full state has nq qubits (2 <= nq <= 34); this GPU's
+ * share psi_local holds, in label order, the 2^(nq-1) amplitudes whose qubit
+ * 1 equals rank_bit (0 or 1); psi_remote holds the partner's share as received
+ * before this gate (read only; must not overlap psi_local).  Targets are in
+ * the full state's numbering.  If qubit 1 is a target, psi_local becomes this
+ * GPU's half of the gate applied to the whole state; run on both halves (each
+ * with the other's pre-gate share as psi_remote) the result equals qcw_opk on
+ * the whole state, bit for bit.  Otherwise the gate is the one-gate sweep on
+ * the share and psi_remote is not read.  Device buffers, asynchronous on
+ * stream; the exchange itself is the caller's.
+ */
+int qcw_op_shard(int k, const int *targets, const qcw_c64 *U, int rank_bit, qcw_c64 *psi_local,
+                 const qcw_c64 *psi_remote, int nq, void *stream);
+
+/*
  * Pick_k as computed by the device (§4a-§4c): writes (2^nq / m) * m labels to
  * the HOST array out_host, group after group in ascending base label, the
  * members of a group in ascending local index.  nq <= 26.  Synchronous.

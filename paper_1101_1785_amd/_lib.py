@@ -68,6 +68,7 @@ _SIGS = {
     "qcw_circuit_fused_ex": ([_P, _i32, _P, _i32, _P, _i64, _i32, _i32, _i32, _P], _i32),
     "qcw_fused_pass_count": ([_i32, _P, _i32, _i32, _i32], _i32),
     "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),
+    "qcw_op_shard": ([_i32, _P, _P, _i32, _P, _P, _i32, _P], _i32),
     "qcw_batch_create": ([_P, _P, _i32, _P, _i64, _P, _i64, _P, _i64, ctypes.c_char_p, _P], _i32),
     "qcw_batch_run": ([_P, _P], _i32),
     "qcw_batch_run_eager": ([_P, _P], _i32),
@@ -245,6 +246,15 @@ def circuit_fused(psi, circ, tile_bits=0, stream=None, low_bits=0, threads=0):
     gates, mats = pack_circuit(circ)
     qcw_circuit_fused_ex(psi, circ.nq, gates, len(circ), mats, mats.size, tile_bits, low_bits,
                          threads, stream)
+
+
+def qcw_op_shard(k, targets, U, rank_bit, psi_local, psi_remote, nq, stream=None):
+    """One rank's half of a gate on a state split by qubit 1 (see include/qcw.h)."""
+    t = _targets(targets)
+    Uc = np.ascontiguousarray(U, dtype=np.complex128).reshape(-1)
+    rem = _dptr(psi_remote) if psi_remote is not None else None
+    _check(_L.qcw_op_shard(int(k), _hptr(t), _hptr(Uc), int(rank_bit), _dptr(psi_local), rem,
+                           int(nq), _stream(stream)), "qcw_op_shard")
 
 
 def qcw_fused_pass_count(nq, gates, ngates, tile_bits=0, low_bits=0):
