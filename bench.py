@@ -6,7 +6,9 @@ with probabilities .50/.35/.15, random ordered targets, random unitaries)
 applied in place to one nq-qubit complex FP64 state that is already resident
 in HBM.  The default workload is the largest single state the 64 GB device
 budget admits, nq = 31 (2^31 amplitudes, 32 GiB), seed 1, run by the fused
-multi-gate path (qcw_circuit_fused; --path plain for one sweep per gate).
+multi-gate path (qcw_circuit_fused_ex with both plan flags: gates on disjoint
+qubits reordered into fewer passes, gates merged inside a pass; --plan 0 for
+the bit-exact list-order passes, --path plain for one sweep per gate).
 
 Prints ONE JSON line with the throughput (solves/s), the roofline of the
 dominant kernel (algorithmic bytes 32 * 2^nq per launch -- one pass reads and
@@ -47,6 +49,8 @@ def _args():
     p.add_argument("--path", choices=["fused", "plain"], default="fused",
                    help="fused multi-gate passes (default) or one sweep per gate")
     p.add_argument("--tile-bits", type=int, default=0)
+    p.add_argument("--plan", type=int, choices=[0, 1, 2, 3], default=3,
+                   help="fused plan flags: 1 = QCW_PLAN_COMMUTE, 2 = QCW_PLAN_FUSE (default both)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-log2", type=int, default=26,
                    help="contiguous outputs per gate timed on the CPU oracle")
@@ -488,12 +492,12 @@ def counters_run(torch, L, qi):
         L.qcw_opk(k, t, qi.random_unitary(rng, 1 << k), psi)
     c = qi.circuit(1, nq, 4 * nq)
     g, m = L.pack_circuit(c)
-    L.qcw_circuit_fused(psi, nq, g, len(c), m, m.size)
+    L.qcw_circuit_fused_ex(psi, nq, g, len(c), m, m.size, 0, 0, 0, 3)
     torch.cuda.synchronize()
     print(json.dumps({"counters_run": {
         "copy_bytes_read": 16 << 27, "copy_bytes_written": 16 << 27,
         "sweep_launches": 3, "sweep_bytes_per_launch": 32 * N,
-        "fused_passes": L.qcw_fused_pass_count(nq, g, len(c)),
+        "fused_passes": L.qcw_fused_pass_count(nq, g, len(c), 0, 0, 3),
         "fused_bytes_per_pass": 32 * N, "nq": nq}}), flush=True)
 
 
@@ -528,7 +532,8 @@ def main():
 
     def solve():
         if a.path == "fused":
-            L.qcw_circuit_fused(psi, nq, gates, G, mats, mats.size, a.tile_bits, stream)
+            L.qcw_circuit_fused_ex(psi, nq, gates, G, mats, mats.size, a.tile_bits, 0, 0, a.plan,
+                                   stream)
         else:
             L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)
 
@@ -558,7 +563,7 @@ def main():
     per_k = {}
     if a.path == "fused":
         launches, kms = L.qcw_timing_read(L.QCW_KERNEL_FUSED)
-        npass = L.qcw_fused_pass_count(nq, gates, G, a.tile_bits)
+        npass = L.qcw_fused_pass_count(nq, gates, G, a.tile_bits, 0, a.plan)
         kernel = "qcw::fused_pass_kernel (one pass = a run of gates over the state in LDS tiles)"
         unit_note = f"one pass over the state; {npass} passes per {G}-gate solve"
     else:
@@ -575,16 +580,28 @@ def main():
         unit_note = "one gate over the state"
     avg_ms = kms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    # the circuit's algorithmic flops (its gates as listed), spread over the launches
+    flops_per_launch = _flops_per_solve(circ) / max(npass, 1)
+    fp64_tflops = flops_per_launch / (avg_ms * 1e-3) / 1e12
     norm = torch.linalg.vector_norm(psi).item()
 
-    # the other path, for comparison (same state buffer, untimed by the events above)
+    # the other paths, for comparison (same state buffer, untimed by the events above)
     other = {}
     if a.path == "fused":
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)
-        torch.cuda.synchronize()
-        other = {"plain_one_sweep_per_gate_solves_per_s": 1.0 / (time.perf_counter() - t1)}
+        def once(fn):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return 1.0 / (time.perf_counter() - t1)
+        other = {
+            "plain_one_sweep_per_gate_solves_per_s":
+                once(lambda: L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)),
+            "fused_list_order_bit_exact_solves_per_s":
+                once(lambda: L.qcw_circuit_fused_ex(psi, nq, gates, G, mats, mats.size,
+                                                    a.tile_bits, 0, 0, 0, stream)),
+            "fused_list_order_passes": L.qcw_fused_pass_count(nq, gates, G, a.tile_bits, 0, 0),
+        }
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -629,7 +646,9 @@ def main():
                         f"(k=1/2/3 at .50/.35/.15, random ordered targets, random unitaries); "
                         f"seed {a.seed}",
             "nq": nq, "gates": G, "seed": a.seed,
-            "path": "qcw_circuit_fused" if a.path == "fused" else "qcw_circuit",
+            "path": "qcw_circuit_fused_ex" if a.path == "fused" else "qcw_circuit",
+            "plan": ({0: "list order (bit-exact)", 1: "QCW_PLAN_COMMUTE", 2: "QCW_PLAN_FUSE",
+                      3: "QCW_PLAN_COMMUTE|QCW_PLAN_FUSE"}[a.plan] if a.path == "fused" else None),
             "passes_per_solve": npass,
             **other,
         },
@@ -640,6 +659,9 @@ def main():
             "kernel": kernel, "unit_of_work": unit_note, "launches": launches,
             "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
             "per_k": per_k or None,
+            "algorithmic_flops_per_launch": flops_per_launch,
+            "fp64_achieved_tflops": fp64_tflops,
+            "fp64_frac": fp64_tflops / FP64_PEAK_TFLOPS,
         },
         "cpu_baseline": cpu,
         "checks": {"final_norm": norm, "wall_s": wall},

@@ -139,18 +139,45 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
  */
 int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                       const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream);
+/* Plan flags for qcw_circuit_fused_ex (0: passes are runs of consecutive
+ * gates and the result equals qcw_circuit bit for bit).  Each flag leaves the
+ * circuit's operator unchanged and changes only the rounding: results equal
+ * qcw_circuit to FP64 rounding. */
+enum {
+  /* A gate may join an earlier pass ahead of gates that were deferred to a
+   * later one, provided it shares no qubit with any of them: gates on
+   * disjoint qubits commute (the tensor structure of §2c), and gates sharing
+   * a qubit keep their order.  A random 124-gate circuit on 31 qubits takes
+   * 11 passes instead of 17. */
+  QCW_PLAN_COMMUTE = 1,
+  /* Inside each pass, consecutive gates spanning at most three qubits become
+   * one gate (their product, computed on the host), so a tile goes through
+   * LDS fewer times (124 gates become about 70 for the circuit above). */
+  QCW_PLAN_FUSE = 2,
+};
+
 /* The same with the number of contiguous low label bits every tile keeps
  * (low_bits, 3..5; 0 = the tuned default): tiles are made of 2^low_bits-
  * amplitude contiguous chunks, and tile_bits - low_bits <= 10 bits are left for
- * the gates' targets; and the threads per tile (256 or 512 for tile_bits 11;
+ * the gates' targets; the threads per tile (256 or 512 for tile_bits 11;
  * 256, 512 or 1024 for 12 and 13, where 12 with 1024 is a warp-specialised
- * pipelined kernel; 0 = the tuned default). */
+ * pipelined kernel; 0 = the tuned default); and the plan flags
+ * (QCW_PLAN_COMMUTE | QCW_PLAN_FUSE, or 0; other bits are QCW_EINVAL). */
 int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
-                         int threads, void *stream);
-/* Number of passes qcw_circuit_fused_ex makes for this gate list (host only). */
+                         int threads, int plan, void *stream);
+/* Number of passes qcw_circuit_fused_ex makes for this gate list and plan
+ * (host only; QCW_PLAN_FUSE does not change it). */
 int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits,
-                         int low_bits);
+                         int low_bits, int plan);
+/* The same plan in full (host only): pass_of[g] receives the pass of gate g
+ * (0-based), order[0..ngates) the gate indices in the order the passes apply
+ * them (before any QCW_PLAN_FUSE merging).  pass_of and order are caller-owned
+ * host arrays of ngates ints.  Returns the pass count, or a negative code.
+ * States below 9 qubits (or tile_bits < 8) run one sweep per gate: pass_of[g]
+ * = g and the list order. */
+int qcw_fused_plan(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits,
+                   int plan, int *pass_of, int *order);
 
 /*
  * One GPU's part of a gate on a state split over two GPUs by qubit 1 (the most

@@ -33,6 +33,7 @@ _i64 = ctypes.c_int64
 QCW_OK, QCW_EINVAL, QCW_ENOMEM, QCW_EHIP, QCW_EAGAIN = 0, -1, -2, -3, -4
 QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3, QCW_KERNEL_BATCH = 1, 2, 3, 4
 QCW_KERNEL_FUSED = 5
+QCW_PLAN_COMMUTE, QCW_PLAN_FUSE = 1, 2
 QCW_KERNEL_CHANNEL = 6
 
 
@@ -65,8 +66,9 @@ _SIGS = {
     "qcw_omega_all": ([_P, _P, _i32, _P], _i32),
     "qcw_circuit": ([_P, _i32, _P, _i32, _P, _i64, _P], _i32),
     "qcw_circuit_fused": ([_P, _i32, _P, _i32, _P, _i64, _i32, _P], _i32),
-    "qcw_circuit_fused_ex": ([_P, _i32, _P, _i32, _P, _i64, _i32, _i32, _i32, _P], _i32),
-    "qcw_fused_pass_count": ([_i32, _P, _i32, _i32, _i32], _i32),
+    "qcw_circuit_fused_ex": ([_P, _i32, _P, _i32, _P, _i64, _i32, _i32, _i32, _i32, _P], _i32),
+    "qcw_fused_pass_count": ([_i32, _P, _i32, _i32, _i32, _i32], _i32),
+    "qcw_fused_plan": ([_i32, _P, _i32, _i32, _i32, _i32, _P, _P], _i32),
     "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),
     "qcw_op_shard": ([_i32, _P, _P, _i32, _P, _P, _i32, _P], _i32),
     "qcw_batch_create": ([_P, _P, _i32, _P, _i64, _P, _i64, _P, _i64, ctypes.c_char_p, _P], _i32),
@@ -235,17 +237,17 @@ def qcw_circuit_fused(psi, nq, gates, ngates, mats, nmats, tile_bits=0, stream=N
 
 
 def qcw_circuit_fused_ex(psi, nq, gates, ngates, mats, nmats, tile_bits=0, low_bits=0,
-                         threads=0, stream=None):
+                         threads=0, plan=0, stream=None):
     _check(_L.qcw_circuit_fused_ex(_dptr(psi), int(nq), _hptr(gates), int(ngates), _hptr(mats),
                                    int(nmats), int(tile_bits), int(low_bits), int(threads),
-                                   _stream(stream)), "qcw_circuit_fused_ex")
+                                   int(plan), _stream(stream)), "qcw_circuit_fused_ex")
 
 
-def circuit_fused(psi, circ, tile_bits=0, stream=None, low_bits=0, threads=0):
+def circuit_fused(psi, circ, tile_bits=0, stream=None, low_bits=0, threads=0, plan=0):
     """Apply a qcw_inputs.Circuit in place with qcw_circuit_fused_ex."""
     gates, mats = pack_circuit(circ)
     qcw_circuit_fused_ex(psi, circ.nq, gates, len(circ), mats, mats.size, tile_bits, low_bits,
-                         threads, stream)
+                         threads, plan, stream)
 
 
 def qcw_op_shard(k, targets, U, rank_bit, psi_local, psi_remote, nq, stream=None):
@@ -257,11 +259,23 @@ def qcw_op_shard(k, targets, U, rank_bit, psi_local, psi_remote, nq, stream=None
                            int(nq), _stream(stream)), "qcw_op_shard")
 
 
-def qcw_fused_pass_count(nq, gates, ngates, tile_bits=0, low_bits=0):
-    n = _L.qcw_fused_pass_count(int(nq), _hptr(gates), int(ngates), int(tile_bits), int(low_bits))
+def qcw_fused_pass_count(nq, gates, ngates, tile_bits=0, low_bits=0, plan=0):
+    n = _L.qcw_fused_pass_count(int(nq), _hptr(gates), int(ngates), int(tile_bits), int(low_bits),
+                                int(plan))
     if n < 0:
         raise QcwError(n, "qcw_fused_pass_count")
     return n
+
+
+def qcw_fused_plan(nq, gates, ngates, tile_bits=0, low_bits=0, plan=0):
+    """(pass count, pass_of per gate, gate indices in execution order)."""
+    pass_of = np.zeros(max(int(ngates), 1), dtype=np.int32)
+    order = np.zeros(max(int(ngates), 1), dtype=np.int32)
+    n = _L.qcw_fused_plan(int(nq), _hptr(gates), int(ngates), int(tile_bits), int(low_bits),
+                          int(plan), _hptr(pass_of), _hptr(order))
+    if n < 0:
+        raise QcwError(n, "qcw_fused_plan")
+    return n, pass_of[:ngates], order[:ngates]
 
 
 def qcw_debug_pick_device(nq, targets):

@@ -25,6 +25,7 @@ namespace qcw {
 constexpr int kFusedMaxFree = 10;  // tile bits above the contiguous low bits
 constexpr int kFusedDefaultTile = 12;
 constexpr int kFusedDefaultLow = 4;
+constexpr int kFuseExtraFlops = 2;  // see plan_passes
 
 // Threads per block for a tile of 2^T amplitudes: eight amplitudes per thread
 // from T = 11 up, so larger tiles also get more waves for their gates.
@@ -305,40 +306,94 @@ struct FusedShape {
 
 static int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 
-// Greedy: extend the current run while the union of target bits and the low
-// L bits fits in T bits; then widen every pass's tile with the lowest unused
-// bits (larger contiguous chunks).
-static int plan_passes(int nq, const std::vector<Geom> &geo, const qcw_gate *gates,
-                       const qcw_c64 *mats, FusedShape sh, std::vector<FusedPass> &passes,
-                       std::vector<FusedGate> &fg) {
+// Cuts the gate list into passes.  A pass's tile bits are the low L bits and
+// the target bits of its gates (at most T); every pass is then widened with the
+// lowest unused bits (larger contiguous chunks).
+//
+// By default a pass is a run of consecutive gates, extended while its bits
+// fit, and results equal the one-sweep-per-gate path bit for bit.  Two plan
+// flags trade that for less work; both leave the circuit's operator unchanged
+// and change only the rounding:
+// * QCW_PLAN_COMMUTE: each pass scans all gates not yet placed, in list order,
+//   and takes every gate that fits, provided it shares no qubit with a gate
+//   skipped earlier in the scan.  Gates on disjoint qubits commute (the tensor
+//   structure of §2c), so moving it ahead of the skipped gates is exact, and
+//   gates that share a qubit keep their order.
+// * QCW_PLAN_FUSE: inside each pass, consecutive gates spanning at most three
+//   qubits are merged into one gate (their matrix product, the first gate
+//   rightmost), so the tile makes fewer LDS round trips.  A merge may add at
+//   most kFuseExtraFlops flops per amplitude: two one-qubit gates, or two
+//   two-qubit gates sharing a qubit, are merged; a one-qubit gate and a
+//   disjoint two-qubit gate (44 -> 62 flops) are not, since the in-tile work
+//   is bound by FP64 arithmetic about as much as by LDS traffic (measured
+//   slower at nq = 31).
+struct PlanRun {
+  std::vector<int> g;  // gate indices, in execution order
+  uint64_t mask;       // tile bits before widening
+};
+
+static std::vector<PlanRun> plan_runs(int nq, const std::vector<Geom> &geo, FusedShape sh,
+                                      bool commute) {
   const int T = std::min(sh.T, nq);
   const int L = std::min(sh.L, T);
   const uint64_t low = (L >= 64) ? ~0ull : ((1ull << L) - 1);
-  std::vector<std::pair<int, uint64_t>> runs;  // (first gate, tile mask)
-  uint64_t cur = low;
-  int first = 0;
-  for (int g = 0; g < (int)geo.size(); ++g) {
+  const int ng = (int)geo.size();
+  std::vector<uint64_t> gm(ng);
+  for (int g = 0; g < ng; ++g) {
     uint64_t m = 0;
     for (int j = 0; j < geo[g].k; ++j) m |= 1ull << geo[g].bit[j];
-    if (popcount64(cur | m) > T) {
-      runs.push_back({first, cur});
-      first = g;
-      cur = low | m;
-    } else {
-      cur |= m;
+    gm[g] = m;
+  }
+  std::vector<PlanRun> runs;
+  if (!commute) {
+    PlanRun cur{{}, low};
+    for (int g = 0; g < ng; ++g) {
+      if (popcount64(cur.mask | gm[g]) > T) {
+        runs.push_back(std::move(cur));
+        cur = PlanRun{{}, low};
+      }
+      cur.mask |= gm[g];
+      cur.g.push_back(g);
+    }
+    if (!cur.g.empty()) runs.push_back(std::move(cur));
+  } else {
+    std::vector<int> rem(ng), left;
+    for (int g = 0; g < ng; ++g) rem[g] = g;
+    while (!rem.empty()) {
+      // the first remaining gate always fits (k + L <= T), so every scan places one
+      PlanRun cur{{}, low};
+      uint64_t blocked = 0;
+      left.clear();
+      for (int g : rem) {
+        if (!(gm[g] & blocked) && popcount64(cur.mask | gm[g]) <= T) {
+          cur.mask |= gm[g];
+          cur.g.push_back(g);
+        } else {
+          blocked |= gm[g];
+          left.push_back(g);
+        }
+      }
+      runs.push_back(std::move(cur));
+      rem.swap(left);
     }
   }
-  if (!geo.empty()) runs.push_back({first, cur});
+  return runs;
+}
+
+static int plan_passes(int nq, const std::vector<Geom> &geo, const qcw_gate *gates,
+                       const qcw_c64 *mats, FusedShape sh, int plan,
+                       std::vector<FusedPass> &passes, std::vector<FusedGate> &fg) {
+  const bool fuse = (plan & QCW_PLAN_FUSE) != 0;
+  const int T = std::min(sh.T, nq);
+  const int L = std::min(sh.L, T);
+  const std::vector<PlanRun> runs = plan_runs(nq, geo, sh, (plan & QCW_PLAN_COMMUTE) != 0);
   passes.clear();
   fg.clear();
   for (size_t r = 0; r < runs.size(); ++r) {
-    const int g0 = runs[r].first;
-    const int g1 = (r + 1 < runs.size()) ? runs[r + 1].first : (int)geo.size();
-    uint64_t mask = runs[r].second;
+    uint64_t mask = runs[r].mask;
     for (int b = 0; b < nq && popcount64(mask) < T; ++b) mask |= 1ull << b;
     FusedPass P;
     memset(&P, 0, sizeof P);
-    P.ngates = g1 - g0;
     P.gate_off = (int)fg.size();
     P.T = T;
     P.L = L;
@@ -366,12 +421,34 @@ static int plan_passes(int nq, const std::vector<Geom> &geo, const qcw_gate *gat
         if ((c >> j) & 1) o |= 1ull << free_pos[j];
       P.chunk_off[c] = o;
     }
-    for (int g = g0; g < g1; ++g) {
+    // the pass's gates as (geometry, matrix): as listed, or fused
+    std::vector<Geom> pg;
+    std::vector<const qcw_c64 *> pu;
+    std::vector<qcw_gate> fgates;
+    std::vector<qcw_c64> fmats;
+    if (fuse) {
+      int rc = fuse_gate_list(gates, runs[r].g.data(), (int)runs[r].g.size(), mats, 3,
+                              kFuseExtraFlops, &fgates, &fmats);
+      if (rc) return rc;
+      pg.resize(fgates.size());
+      for (size_t i = 0; i < fgates.size(); ++i) {
+        if ((rc = make_geom(nq, fgates[i].k, fgates[i].q, &pg[i]))) return rc;
+        pu.push_back(fmats.data() + fgates[i].mat);
+      }
+    } else {
+      for (int g : runs[r].g) {
+        pg.push_back(geo[g]);
+        pu.push_back(mats + gates[g].mat);
+      }
+    }
+    P.ngates = (int)pg.size();
+    for (size_t i = 0; i < pg.size(); ++i) {
+      const Geom &gg = pg[i];
       FusedGate G;
       memset(&G, 0, sizeof G);
-      G.k = geo[g].k;
+      G.k = gg.k;
       int lb[3] = {0, 0, 0};
-      for (int j = 0; j < G.k; ++j) lb[j] = local_of[geo[g].bit[j]];
+      for (int j = 0; j < G.k; ++j) lb[j] = local_of[gg.bit[j]];
       int sl[3] = {lb[0], lb[1], lb[2]};
       std::sort(sl, sl + G.k);
       G.sb0 = sl[0];
@@ -383,7 +460,7 @@ static int plan_passes(int nq, const std::vector<Geom> &geo, const qcw_gate *gat
           if ((rr >> (G.k - 1 - j)) & 1) o |= 1u << lb[j];
         G.off[rr] = o;
       }
-      const qcw_c64 *U = mats + gates[g].mat;
+      const qcw_c64 *U = pu[i];
       for (int e = 0; e < (1 << (2 * G.k)); ++e) G.u[e] = make_double2(U[e].re, U[e].im);
       fg.push_back(G);
     }
@@ -550,7 +627,7 @@ static int upload_plan(const std::vector<FusedPass> &passes, const std::vector<F
 }
 
 int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, int low_bits, int threads, hipStream_t s) {
+              int tile_bits, int low_bits, int threads, int plan, hipStream_t s) {
   std::vector<Geom> geo(ngates);
   for (int i = 0; i < ngates; ++i) {
     int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
@@ -570,7 +647,7 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
   }
   std::vector<FusedPass> passes;
   std::vector<FusedGate> fg;
-  int rc = plan_passes(nq, geo, gates, mats, FusedShape{T, L}, passes, fg);
+  int rc = plan_passes(nq, geo, gates, mats, FusedShape{T, L}, plan, passes, fg);
   if (rc) return rc;
   const FusedPass *dp = nullptr;
   const FusedGate *dg = nullptr;
@@ -588,19 +665,29 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
   }
 }
 
-int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits) {
+int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits,
+                     int plan, int *pass_of, int *order) {
   std::vector<Geom> geo(ngates);
   for (int i = 0; i < ngates; ++i)
     if (make_geom(nq, gates[i].k, gates[i].q, &geo[i])) return -1;
   const int T = std::min(tile_bits, nq);
-  if (T < 8 || nq < 9) return ngates;
-  std::vector<FusedPass> passes;
-  std::vector<FusedGate> fg;
-  std::vector<qcw_c64> zero(64);
-  std::vector<qcw_gate> g0(gates, gates + ngates);
-  for (auto &g : g0) g.mat = 0;
-  if (plan_passes(nq, geo, g0.data(), zero.data(), FusedShape{T, low_bits}, passes, fg)) return -1;
-  return (int)passes.size();
+  if (T < 8 || nq < 9) {  // one sweep per gate, in list order
+    for (int i = 0; i < ngates; ++i) {
+      if (pass_of) pass_of[i] = i;
+      if (order) order[i] = i;
+    }
+    return ngates;
+  }
+  const std::vector<PlanRun> runs =
+      plan_runs(nq, geo, FusedShape{T, low_bits}, (plan & QCW_PLAN_COMMUTE) != 0);
+  int pos = 0;
+  for (size_t r = 0; r < runs.size(); ++r)
+    for (int g : runs[r].g) {
+      if (pass_of) pass_of[g] = (int)r;
+      if (order) order[pos] = g;
+      ++pos;
+    }
+  return (int)runs.size();
 }
 
 }  // namespace qcw
@@ -611,8 +698,10 @@ extern "C" {
 
 int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
-                         int threads, void *stream) {
+                         int threads, int plan, void *stream) {
   clear_error();
+  if (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE))
+    return fail(QCW_EINVAL, "plan=%d has bits other than QCW_PLAN_COMMUTE and QCW_PLAN_FUSE", plan);
   if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
   if (ngates < 0) return fail(QCW_EINVAL, "ngates < 0");
   if (ngates > 0 && (!gates || !mats)) return fail(QCW_EINVAL, "gates or mats is NULL");
@@ -638,22 +727,38 @@ int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates
   }
   int rc = check_device_range(psi, ((uint64_t)1 << nq) * sizeof(qcw_c64), "psi");
   if (rc) return rc;
-  return run_fused(psi, nq, gates, ngates, mats, tile_bits, low_bits, threads, (hipStream_t)stream);
+  return run_fused(psi, nq, gates, ngates, mats, tile_bits, low_bits, threads, plan,
+                   (hipStream_t)stream);
 }
 
 int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                       const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream) {
-  return qcw_circuit_fused_ex(psi, nq, gates, ngates, mats, nmats, tile_bits, 0, 0, stream);
+  return qcw_circuit_fused_ex(psi, nq, gates, ngates, mats, nmats, tile_bits, 0, 0, 0, stream);
 }
 
-int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits) {
+int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits,
+                         int plan) {
   clear_error();
   if (tile_bits == 0) tile_bits = kFusedDefaultTile;
   if (low_bits == 0) low_bits = kFusedDefaultLow;
   if (nq < 1 || nq > kMaxQubits || ngates < 0 || (ngates > 0 && !gates) || tile_bits < 8 ||
-      tile_bits > 13 || low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree)
+      tile_bits > 13 || low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree ||
+      (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE)))
     return fail(QCW_EINVAL, "invalid arguments");
-  int n = fused_pass_count(nq, gates, ngates, tile_bits, low_bits);
+  int n = fused_pass_count(nq, gates, ngates, tile_bits, low_bits, plan, nullptr, nullptr);
+  return n < 0 ? fail(QCW_EINVAL, "invalid gate") : n;
+}
+
+int qcw_fused_plan(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits,
+                   int plan, int *pass_of, int *order) {
+  clear_error();
+  if (tile_bits == 0) tile_bits = kFusedDefaultTile;
+  if (low_bits == 0) low_bits = kFusedDefaultLow;
+  if (nq < 1 || nq > kMaxQubits || ngates < 0 || (ngates > 0 && (!gates || !pass_of || !order)) ||
+      tile_bits < 8 || tile_bits > 13 || low_bits < 3 || low_bits > 5 ||
+      tile_bits - low_bits > kFusedMaxFree || (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE)))
+    return fail(QCW_EINVAL, "invalid arguments");
+  int n = fused_pass_count(nq, gates, ngates, tile_bits, low_bits, plan, pass_of, order);
   return n < 0 ? fail(QCW_EINVAL, "invalid gate") : n;
 }
 

@@ -8,6 +8,7 @@
 // §2c).  Only consecutive gates are merged; nothing is reordered.  The fused
 // matrix carries the rounding of its products, so a fused circuit equals the
 // original to rounding, not bit for bit.
+#include <limits.h>
 #include <string.h>
 
 #include <complex>
@@ -93,13 +94,18 @@ void apply_gate(Block &b, const qcw_gate &g, const qcw_c64 *U) {
 
 }  // namespace
 
-int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats, int64_t nmats,
-                 int max_qubits, std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats) {
+// Flops per amplitude of one k-qubit gate: m = 2^k outputs per group, each m
+// complex products and m - 1 additions, per group of m amplitudes.
+static int gate_flops(int k) { return 8 * (1 << k) - 2; }
+
+int fuse_gate_list(const qcw_gate *gates, const int *idx, int n, const qcw_c64 *mats,
+                   int max_qubits, int max_extra_flops, std::vector<qcw_gate> *out_gates,
+                   std::vector<qcw_c64> *out_mats) {
   if (max_qubits < 1 || max_qubits > 3) return fail(QCW_EINVAL, "max_qubits=%d outside [1, 3]", max_qubits);
   out_gates->clear();
   out_mats->clear();
-  out_gates->reserve((size_t)ngates);
-  out_mats->reserve((size_t)64 * ngates);
+  out_gates->reserve((size_t)n);
+  out_mats->reserve((size_t)64 * n);
   Block cur;
   int run = 0;               // gates in the current block
   const qcw_gate *first = nullptr;
@@ -120,16 +126,13 @@ int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
     out_gates->push_back(g);
     run = 0;
   };
-  for (int i = 0; i < ngates; ++i) {
-    const qcw_gate &g = gates[i];
-    Geom geo;
-    int rc = make_geom(nq, g.k, g.q, &geo);
-    if (rc) return rc;
-    if (g.mat < 0 || g.mat + ((int64_t)1 << (2 * g.k)) > nmats)
-      return fail(QCW_EINVAL, "gate %d: matrix offset outside mats", i);
+  for (int i = 0; i < n; ++i) {
+    const qcw_gate &g = gates[idx ? idx[i] : i];
     int fresh = 0;
     for (int j = 0; j < g.k; ++j) fresh += local_bit(cur, g.q[j]) < 0;
-    if (run && cur.u + fresh > max_qubits) flush();
+    if (run && (cur.u + fresh > max_qubits ||
+                gate_flops(cur.u + fresh) - gate_flops(cur.u) - gate_flops(g.k) > max_extra_flops))
+      flush();
     if (!run) {
       start(cur, g, mats + g.mat);
       first = &g;
@@ -142,6 +145,19 @@ int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
   }
   flush();
   return QCW_OK;
+}
+
+int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats, int64_t nmats,
+                 int max_qubits, std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats) {
+  for (int i = 0; i < ngates; ++i) {
+    const qcw_gate &g = gates[i];
+    Geom geo;
+    int rc = make_geom(nq, g.k, g.q, &geo);
+    if (rc) return rc;
+    if (g.mat < 0 || g.mat + ((int64_t)1 << (2 * g.k)) > nmats)
+      return fail(QCW_EINVAL, "gate %d: matrix offset outside mats", i);
+  }
+  return fuse_gate_list(gates, nullptr, ngates, mats, max_qubits, INT_MAX, out_gates, out_mats);
 }
 
 }  // namespace qcw

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "qcw.h"
 #include "qcw_common.h"
@@ -31,7 +32,19 @@ int launch_sweep(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *ou
 int launch_pick(const Geom &g, uint64_t *labels_dev, hipStream_t s);
 // Fused passes (fused.hip).
 int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, int low_bits, int threads, hipStream_t s);
-int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits);
+              int tile_bits, int low_bits, int threads, int plan, hipStream_t s);
+// Pass count of a plan; when non-NULL, pass_of[g] receives gate g's pass and
+// order[] the gate indices in execution order.
+int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits,
+                     int plan, int *pass_of, int *order);
+// Gate fusion (gate_fusion.cpp): gates idx[0..n) (all n gates when idx is
+// NULL), in that order, merged greedily into runs spanning at most max_qubits
+// qubits, one gate per run; a gate joins the current run only if the merged
+// gate costs at most max_extra_flops more flops per amplitude than the run and
+// the gate apart (8 * 2^k - 2 for k qubits).  Output matrix offsets index
+// *out_mats.  The gates must already be valid.
+int fuse_gate_list(const qcw_gate *gates, const int *idx, int n, const qcw_c64 *mats,
+                   int max_qubits, int max_extra_flops, std::vector<qcw_gate> *out_gates,
+                   std::vector<qcw_c64> *out_mats);
 
 }  // namespace qcw

@@ -1,8 +1,11 @@
 """GPU parity of the fused multi-gate passes (qcw_circuit_fused).
 
 A fused pass runs each gate's group update with the same arithmetic as the
-one-gate sweep, so the result must equal the plain path bit for bit, and the
-oracle within the FP64 circuit tolerance.
+one-gate sweep, so with no plan flags the result must equal the plain path bit
+for bit, and the oracle within the FP64 circuit tolerance.  The plan flags
+(QCW_PLAN_COMMUTE: gates on disjoint qubits reordered; QCW_PLAN_FUSE: gates
+merged inside a pass) keep the operator and change only the rounding: their
+results must equal the plain path and the oracle within that tolerance.
 """
 import numpy as np
 import pytest
@@ -25,10 +28,13 @@ def L():
     return _lib
 
 
-def _run(L, psi0, c, fused, tile_bits=0, low_bits=0):
+COMMUTE, FUSE = 1, 2
+
+
+def _run(L, psi0, c, fused, tile_bits=0, low_bits=0, plan=0):
     psi = torch.from_numpy(psi0).to("cuda")
     if fused:
-        L.circuit_fused(psi, c, tile_bits, low_bits=low_bits)
+        L.circuit_fused(psi, c, tile_bits, low_bits=low_bits, plan=plan)
     else:
         L.circuit(psi, c)
     torch.cuda.synchronize()
@@ -62,6 +68,57 @@ def test_fused_threads_per_tile(L, tile_bits, low_bits, threads, nq):
     L.circuit_fused(psi, c, tile_bits, low_bits=low_bits, threads=threads)
     torch.cuda.synchronize()
     assert np.array_equal(psi.cpu().numpy(), _run(L, psi0, c, False))
+
+
+def _close(a, b, G):
+    return np.linalg.norm(a - b) <= TOL * max(1, G / 64) * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("plan", [COMMUTE, FUSE, COMMUTE | FUSE])
+@pytest.mark.parametrize("nq", [9, 12, 14, 18, 22])
+@pytest.mark.parametrize("tile_bits,low_bits", [(8, 5), (11, 3), (12, 4), (13, 4)])
+def test_fused_plan_equals_plain_to_rounding(L, nq, tile_bits, low_bits, plan):
+    print(f"[gpu] fused plan={plan} nq={nq} tile_bits={tile_bits} low_bits={low_bits}", flush=True)
+    psi0 = qi.state(13, nq, tag=tile_bits)
+    c = qi.circuit(13, nq, 4 * nq, tag=tile_bits + 100 * plan)
+    a = _run(L, psi0, c, True, tile_bits, low_bits, plan)
+    b = _run(L, psi0, c, False)
+    assert _close(a, b, len(c))
+    if nq <= 18:
+        assert _close(a, oracle.circuit(c, psi0), len(c))
+
+
+@pytest.mark.parametrize("tile_bits,low_bits,threads", [(12, 3, 256), (12, 4, 1024), (13, 5, 1024),
+                                                        (13, 3, 512), (11, 4, 512)])
+@pytest.mark.parametrize("nq", [13, 21])
+def test_fused_plan_threads_per_tile(L, tile_bits, low_bits, threads, nq):
+    psi0 = qi.state(14, nq)
+    c = qi.circuit(14, nq, 6 * nq)
+    psi = torch.from_numpy(psi0).to("cuda")
+    L.circuit_fused(psi, c, tile_bits, low_bits=low_bits, threads=threads, plan=COMMUTE | FUSE)
+    torch.cuda.synchronize()
+    assert _close(psi.cpu().numpy(), _run(L, psi0, c, False), len(c))
+
+
+def test_fused_plan_ghz_and_inverse(L):
+    """GHZ chain on 16 qubits under both flags: (|0..0> + |1..1>)/sqrt2 to a
+    few ulp, zeros elsewhere to a few ulp; then the inverse circuit restores
+    |0..0>."""
+    nq = 16
+    c = qi.Circuit(nq).add(qi.H, 1)
+    for t in range(2, nq + 1):
+        c.add(qi.CNOT, 1, t)
+    psi = torch.from_numpy(qi.basis_state(nq, 0)).to("cuda")
+    L.circuit_fused(psi, c, plan=COMMUTE | FUSE)
+    torch.cuda.synchronize()
+    out = psi.cpu().numpy()
+    ref = np.zeros(1 << nq, complex)
+    ref[0] = ref[-1] = qi.S2
+    assert np.abs(out - ref).max() <= 8 * 2.0 ** -53
+    L.circuit_fused(psi, c.inverse(), plan=COMMUTE | FUSE)
+    torch.cuda.synchronize()
+    back = psi.cpu().numpy()
+    assert np.abs(back - qi.basis_state(nq, 0)).max() <= 16 * 2.0 ** -53
 
 
 def test_fused_fewer_passes(L):
@@ -107,6 +164,8 @@ def test_fused_validation(L):
         L.qcw_circuit_fused(psi, 10, bad, len(c), m, m.size)
     with pytest.raises(L.QcwError, match="threads"):
         L.qcw_circuit_fused_ex(psi, 10, g, len(c), m, m.size, 11, 3, 1024)
+    with pytest.raises(L.QcwError, match="plan"):
+        L.qcw_circuit_fused_ex(psi, 10, g, len(c), m, m.size, 12, 4, 0, 4)
     L.qcw_circuit_fused(psi, 10, g, 0, m, m.size)          # empty circuit is a no-op
 
 
@@ -137,3 +196,29 @@ def test_fullsize_fused_equals_plain_and_roundtrips(L):
     del a, ref
     torch.cuda.empty_cache()
 
+
+def test_fullsize_fused_plan_matches_plain(L):
+    """nq = 31, the 124-gate benchmark circuit with both plan flags (the
+    benchmark's launch configuration): equal to one sweep per gate (whose
+    single-gate outputs are checked against the oracle at this size) within
+    the circuit tolerance, as a relative 2-norm and amplitude by amplitude."""
+    free, _ = torch.cuda.mem_get_info()
+    if free < (3 * (16 << FULL_NQ) + (4 << 30)):
+        pytest.skip("not enough device memory")
+    print("[gpu] full size fused plan", flush=True)
+    psi0 = qi.state(1, FULL_NQ)
+    c = qi.circuit(1, FULL_NQ, 4 * FULL_NQ)
+    a = torch.from_numpy(psi0).to("cuda")
+    b = a.clone()
+    L.circuit_fused(a, c, plan=COMMUTE | FUSE)
+    L.circuit(b, c)
+    torch.cuda.synchronize()
+    tol = TOL * max(1.0, len(c) / 64)
+    err = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+    assert err <= tol
+    # every amplitude of this state has modulus about 2^-15.5; allow the same
+    # relative error on each
+    worst = (a - b).abs().max().item()
+    assert worst <= tol * 2.0 ** -15.5 * 64
+    del a, b
+    torch.cuda.empty_cache()
