@@ -59,6 +59,9 @@ def _args():
     p.add_argument("--serve-rate", type=float, default=2000.0)
     p.add_argument("--serve-sweep-seconds", type=float, default=2.0,
                    help="seconds per offered rate in the serving rate sweep (0: skip)")
+    p.add_argument("--no-compare", action="store_true",
+                   help="skip the untimed comparison solves (plain path, list-order plan), so a "
+                        "kernel trace holds only the timed launches")
     p.add_argument("--skip-extra", action="store_true",
                    help="only the headline workload (no batched/serving sections)")
     p.add_argument("--counters", action="store_true",
@@ -587,7 +590,7 @@ def main():
 
     # the other paths, for comparison (same state buffer, untimed by the events above)
     other = {}
-    if a.path == "fused":
+    if a.path == "fused" and not a.no_compare:
         def once(fn):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
