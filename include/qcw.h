@@ -256,13 +256,18 @@ const char *qcw_batch_variant_name(int variant);
 
 /*
  * Gate fusion (§2c, tensor-product structure; gates compose in list order):
- * every run of consecutive gates whose targets together span at most
- * max_qubits (1..3) qubits becomes one gate on that union, its matrix the
- * product of the run's gates, each extended by the identity (the first gate
- * rightmost).  Gates are never reordered.  The union's qubits are listed in
- * order of first appearance (first = most significant local bit).  A run of
- * one gate is copied unchanged; a fused matrix carries the rounding of its
- * products, so the fused circuit equals the original to FP64 rounding.
+ * gates whose targets together span at most max_qubits (1..3) qubits become
+ * one gate on that union, its matrix the product of the block's gates, each
+ * extended by the identity (the first gate rightmost).  A block starts at
+ * the first gate not yet placed and scans onward.  regroup = 0: the block is
+ * a run of consecutive gates (gates are never reordered).  regroup = 1: a
+ * gate may also join the block ahead of gates the scan passed over, provided
+ * it shares no qubit with any of them (they commute, so the circuit's
+ * operator is unchanged); random 36-gate circuits on 9 qubits fuse to ~13
+ * gates instead of ~19.  The union's qubits are listed in order of first
+ * appearance (first = most significant local bit).  A block of one gate is
+ * copied unchanged; a fused matrix carries the rounding of its products, so
+ * the fused circuit equals the original to FP64 rounding.
  * All arrays are host memory: gates (ngates) and mats (nmats) as for
  * qcw_circuit; out_gates must hold ngates entries, out_mats out_mats_cap
  * (64 * ngates always suffices).  Writes the fused gate count and matrix
@@ -270,8 +275,9 @@ const char *qcw_batch_variant_name(int variant);
  * too small an out_mats.
  */
 int qcw_fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-                     int64_t nmats, int max_qubits, qcw_gate *out_gates, int *out_ngates,
-                     qcw_c64 *out_mats, int64_t out_mats_cap, int64_t *out_nmats);
+                     int64_t nmats, int max_qubits, int regroup, qcw_gate *out_gates,
+                     int *out_ngates, qcw_c64 *out_mats, int64_t out_mats_cap,
+                     int64_t *out_nmats);
 
 /*
  * Autotuner: for every qubit count in [nq_lo, nq_hi] (1 <= nq_lo <= nq_hi <=

@@ -78,7 +78,7 @@ _SIGS = {
     "qcw_batch_destroy": ([_P], _i32),
     "qcw_batch_variant_name": ([_i32], ctypes.c_char_p),
     "qcw_batch_autotune": ([ctypes.c_char_p, _i32, _i32, _i32, _i32, _P], _i32),
-    "qcw_fuse_circuit": ([_i32, _P, _i32, _P, _i64, _i32, _P, _P, _P, _i64, _P], _i32),
+    "qcw_fuse_circuit": ([_i32, _P, _i32, _P, _i64, _i32, _i32, _P, _P, _P, _i64, _P], _i32),
     "qcw_rho_conjugate": ([_i32, _P, _P, _P, _i32, _P], _i32),
     "qcw_channel_create": ([_P, _i32, ctypes.c_double, _P, _i32, _P, _i64], _i32),
     "qcw_channel_apply": ([_P, _P, _P, _P], _i32),
@@ -355,10 +355,11 @@ def qcw_batch_destroy(h):
     _check(_L.qcw_batch_destroy(h), "qcw_batch_destroy")
 
 
-def fuse_circuit(nq, circ, max_qubits=3):
+def fuse_circuit(nq, circ, max_qubits=3, regroup=False):
     """Gate fusion (host only): returns (gates, mats) in the packed layout of
-    pack_circuit, the runs of consecutive gates spanning at most max_qubits
-    qubits merged into one gate each."""
+    pack_circuit, blocks of gates spanning at most max_qubits qubits merged
+    into one gate each (runs of consecutive gates, or with regroup also gates
+    that commute past the gates between them)."""
     g, m = pack_circuit(circ)
     n = g.size
     og = np.zeros(max(n, 1), dtype=GATE_DTYPE)
@@ -366,7 +367,7 @@ def fuse_circuit(nq, circ, max_qubits=3):
     ng = ctypes.c_int(0)
     nm = ctypes.c_int64(0)
     _check(_L.qcw_fuse_circuit(int(nq), _hptr(g), int(n), _hptr(m), int(m.size), int(max_qubits),
-                               _hptr(og), ctypes.byref(ng), _hptr(om), int(om.size),
+                               int(bool(regroup)), _hptr(og), ctypes.byref(ng), _hptr(om), int(om.size),
                                ctypes.byref(nm)), "qcw_fuse_circuit")
     return og[:ng.value].copy(), om[:nm.value].copy()
 

@@ -269,7 +269,7 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
       std::vector<qcw_gate> fg;
       std::vector<qcw_c64> fm;
       int rc = fuse_circuit(in.nq, gates + in.gate_off, in.ngates, mats, nmats,
-                            std::min(3, in.nq), &fg, &fm);
+                            std::min(3, in.nq), true, &fg, &fm);
       if (rc) return rc;
       const int64_t goff = (int64_t)bg.size(), moff = (int64_t)m2.size();
       for (const qcw_c64 &z : fm) m2.push_back(make_double2(z.re, z.im));

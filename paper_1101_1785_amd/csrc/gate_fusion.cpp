@@ -99,56 +99,85 @@ void apply_gate(Block &b, const qcw_gate &g, const qcw_c64 *U) {
 static int gate_flops(int k) { return 8 * (1 << k) - 2; }
 
 int fuse_gate_list(const qcw_gate *gates, const int *idx, int n, const qcw_c64 *mats,
-                   int max_qubits, int max_extra_flops, std::vector<qcw_gate> *out_gates,
-                   std::vector<qcw_c64> *out_mats) {
+                   int max_qubits, int max_extra_flops, bool regroup,
+                   std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats) {
   if (max_qubits < 1 || max_qubits > 3) return fail(QCW_EINVAL, "max_qubits=%d outside [1, 3]", max_qubits);
   out_gates->clear();
   out_mats->clear();
   out_gates->reserve((size_t)n);
   out_mats->reserve((size_t)64 * n);
-  Block cur;
-  int run = 0;               // gates in the current block
-  const qcw_gate *first = nullptr;
-  auto flush = [&]() {
-    if (!run) return;
+  auto qmask = [](const qcw_gate &g) {
+    uint64_t m = 0;
+    for (int j = 0; j < g.k; ++j) m |= 1ull << g.q[j];
+    return m;
+  };
+  // Emits one block: a lone gate as given (same bits as unfused), else the
+  // product matrix on the block's qubits.
+  auto emit = [&](const Block &b, const qcw_gate *lone) {
     qcw_gate g;
     memset(&g, 0, sizeof g);
     g.mat = (int64_t)out_mats->size();
-    if (run == 1) {  // a lone gate is kept as given (same bits as unfused)
-      g.k = first->k;
-      for (int j = 0; j < first->k; ++j) g.q[j] = first->q[j];
-      out_mats->insert(out_mats->end(), mats + first->mat, mats + first->mat + (1 << (2 * first->k)));
+    if (lone) {
+      g.k = lone->k;
+      for (int j = 0; j < lone->k; ++j) g.q[j] = lone->q[j];
+      out_mats->insert(out_mats->end(), mats + lone->mat, mats + lone->mat + (1 << (2 * lone->k)));
     } else {
-      g.k = cur.u;
-      for (int j = 0; j < cur.u; ++j) g.q[j] = cur.q[j];
-      for (int e = 0; e < (1 << (2 * cur.u)); ++e) out_mats->push_back({cur.M[e].real(), cur.M[e].imag()});
+      g.k = b.u;
+      for (int j = 0; j < b.u; ++j) g.q[j] = b.q[j];
+      for (int e = 0; e < (1 << (2 * b.u)); ++e) out_mats->push_back({b.M[e].real(), b.M[e].imag()});
     }
     out_gates->push_back(g);
-    run = 0;
   };
-  for (int i = 0; i < n; ++i) {
-    const qcw_gate &g = gates[idx ? idx[i] : i];
-    int fresh = 0;
-    for (int j = 0; j < g.k; ++j) fresh += local_bit(cur, g.q[j]) < 0;
-    if (run && (cur.u + fresh > max_qubits ||
-                gate_flops(cur.u + fresh) - gate_flops(cur.u) - gate_flops(g.k) > max_extra_flops))
-      flush();
-    if (!run) {
-      start(cur, g, mats + g.mat);
-      first = &g;
-    } else {
-      for (int j = 0; j < g.k; ++j)
-        if (local_bit(cur, g.q[j]) < 0) grow(cur, g.q[j]);
-      apply_gate(cur, g, mats + g.mat);
+  // Gates still to place, in order.  A block starts with the first of them
+  // and scans the rest: a gate joins when the block stays within max_qubits
+  // qubits and max_extra_flops, and (regroup) it shares no qubit with a gate
+  // the scan has passed over -- such a gate commutes with everything it moves
+  // ahead of.  Without regroup the scan stops at the first gate that cannot
+  // join, so blocks are runs of consecutive gates.
+  std::vector<int> rest(n), left;
+  for (int i = 0; i < n; ++i) rest[i] = idx ? idx[i] : i;
+  size_t head = 0;
+  Block cur;
+  while (head < rest.size()) {
+    const qcw_gate &g0 = gates[rest[head]];
+    start(cur, g0, mats + g0.mat);
+    int members = 1;
+    uint64_t skipped = 0;
+    left.clear();
+    size_t i = head + 1;
+    for (; i < rest.size(); ++i) {
+      const qcw_gate &g = gates[rest[i]];
+      int fresh = 0;
+      for (int j = 0; j < g.k; ++j) fresh += local_bit(cur, g.q[j]) < 0;
+      const bool fits = !(qmask(g) & skipped) && cur.u + fresh <= max_qubits &&
+                        gate_flops(cur.u + fresh) - gate_flops(cur.u) - gate_flops(g.k) <=
+                            max_extra_flops;
+      if (fits) {
+        for (int j = 0; j < g.k; ++j)
+          if (local_bit(cur, g.q[j]) < 0) grow(cur, g.q[j]);
+        apply_gate(cur, g, mats + g.mat);
+        ++members;
+      } else if (regroup) {
+        skipped |= qmask(g);
+        left.push_back(rest[i]);
+      } else {
+        break;
+      }
     }
-    ++run;
+    emit(cur, members == 1 ? &g0 : nullptr);
+    if (regroup) {
+      rest.swap(left);
+      head = 0;
+    } else {
+      head = i;
+    }
   }
-  flush();
   return QCW_OK;
 }
 
 int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats, int64_t nmats,
-                 int max_qubits, std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats) {
+                 int max_qubits, bool regroup, std::vector<qcw_gate> *out_gates,
+                 std::vector<qcw_c64> *out_mats) {
   for (int i = 0; i < ngates; ++i) {
     const qcw_gate &g = gates[i];
     Geom geo;
@@ -157,7 +186,8 @@ int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
     if (g.mat < 0 || g.mat + ((int64_t)1 << (2 * g.k)) > nmats)
       return fail(QCW_EINVAL, "gate %d: matrix offset outside mats", i);
   }
-  return fuse_gate_list(gates, nullptr, ngates, mats, max_qubits, INT_MAX, out_gates, out_mats);
+  return fuse_gate_list(gates, nullptr, ngates, mats, max_qubits, INT_MAX, regroup, out_gates,
+                        out_mats);
 }
 
 }  // namespace qcw
@@ -165,7 +195,7 @@ int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
 using namespace qcw;
 
 extern "C" int qcw_fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-                                int64_t nmats, int max_qubits, qcw_gate *out_gates,
+                                int64_t nmats, int max_qubits, int regroup, qcw_gate *out_gates,
                                 int *out_ngates, qcw_c64 *out_mats, int64_t out_mats_cap,
                                 int64_t *out_nmats) {
   clear_error();
@@ -175,7 +205,8 @@ extern "C" int qcw_fuse_circuit(int nq, const qcw_gate *gates, int ngates, const
     return fail(QCW_EINVAL, "NULL argument");
   std::vector<qcw_gate> g;
   std::vector<qcw_c64> m;
-  int rc = fuse_circuit(nq, gates, ngates, mats, nmats, max_qubits, &g, &m);
+  if (regroup != 0 && regroup != 1) return fail(QCW_EINVAL, "regroup=%d is not 0 or 1", regroup);
+  int rc = fuse_circuit(nq, gates, ngates, mats, nmats, max_qubits, regroup != 0, &g, &m);
   if (rc) return rc;
   if ((int64_t)m.size() > out_mats_cap || (!m.empty() && !out_mats))
     return fail(QCW_EINVAL, "out_mats holds %lld entries, %zu needed", (long long)out_mats_cap,

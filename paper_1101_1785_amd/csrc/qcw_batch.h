@@ -88,10 +88,13 @@ int tune_load(const char *path, TuneTable *t);
 // Geometry of a gate for the batch kernel; validates like make_geom.
 int make_bgate(int nq, const qcw_gate &g, int64_t nmats, BGate *out);
 
-// Fuses runs of consecutive gates spanning at most max_qubits qubits into one
-// gate each (gate_fusion.cpp); output matrix offsets index *out_mats.
+// Fuses gates spanning at most max_qubits qubits into one gate per block
+// (gate_fusion.cpp): runs of consecutive gates, or with regroup also gates
+// that commute past the ones between them; output matrix offsets index
+// *out_mats.
 int fuse_circuit(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats, int64_t nmats,
-                 int max_qubits, std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats);
+                 int max_qubits, bool regroup, std::vector<qcw_gate> *out_gates,
+                 std::vector<qcw_c64> *out_mats);
 
 // Sizes both persistent kernels for n_exact and n_mfma items of at most
 // max_nq qubits (a kernel with no items gets no grid).

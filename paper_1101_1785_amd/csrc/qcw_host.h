@@ -38,13 +38,15 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
 int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits,
                      int plan, int *pass_of, int *order);
 // Gate fusion (gate_fusion.cpp): gates idx[0..n) (all n gates when idx is
-// NULL), in that order, merged greedily into runs spanning at most max_qubits
-// qubits, one gate per run; a gate joins the current run only if the merged
-// gate costs at most max_extra_flops more flops per amplitude than the run and
-// the gate apart (8 * 2^k - 2 for k qubits).  Output matrix offsets index
+// NULL), in that order, merged greedily into blocks spanning at most
+// max_qubits qubits, one gate per block; a gate joins a block only if the
+// merged gate costs at most max_extra_flops more flops per amplitude than the
+// block and the gate apart (8 * 2^k - 2 for k qubits).  Without regroup a
+// block is a run of consecutive gates; with it, a gate may also join ahead of
+// gates it shares no qubit with (they commute).  Output matrix offsets index
 // *out_mats.  The gates must already be valid.
 int fuse_gate_list(const qcw_gate *gates, const int *idx, int n, const qcw_c64 *mats,
-                   int max_qubits, int max_extra_flops, std::vector<qcw_gate> *out_gates,
-                   std::vector<qcw_c64> *out_mats);
+                   int max_qubits, int max_extra_flops, bool regroup,
+                   std::vector<qcw_gate> *out_gates, std::vector<qcw_c64> *out_mats);
 
 }  // namespace qcw

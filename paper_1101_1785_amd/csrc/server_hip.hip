@@ -70,7 +70,7 @@ class HipExecutor : public Executor {
     std::vector<qcw_gate> fg;
     std::vector<qcw_c64> fm;
     int rc = fuse_circuit(r->nq, r->gates.data(), r->ngates, r->mats.data(),
-                          (int64_t)r->mats.size(), std::min(3, r->nq), &fg, &fm);
+                          (int64_t)r->mats.size(), std::min(3, r->nq), true, &fg, &fm);
     if (rc) return rc;
     r->gates.swap(fg);
     r->mats.swap(fm);

@@ -6,7 +6,11 @@ circuit moves every state as the original does (oracle on both, FP64
 tolerance); two one-qubit gates on different qubits fuse to their Kronecker
 product (first listed qubit most significant); a circuit followed by its
 inverse fuses to the identity map; runs of one gate are copied bit for bit;
-no run spans more than max_qubits qubits and no gate is reordered.
+no run spans more than max_qubits qubits and no gate is reordered.  With
+regroup, a gate may join a block ahead of gates it shares no qubit with; the
+fused circuit still moves every state as the original does, has at most as
+many gates as consecutive fusion, and a gate that shares a qubit with a gate
+it would pass stays behind it.
 """
 import numpy as np
 import pytest
@@ -108,3 +112,39 @@ def test_fusion_validation(L):
         L.fuse_circuit(3, qi.Circuit(4).add(qi.X, 4))   # qubit outside [1, nq]
     g, m = L.fuse_circuit(4, qi.Circuit(4))
     assert g.size == 0 and m.size == 0
+
+
+@pytest.mark.parametrize("nq,G,seed", [(3, 12, 21), (5, 30, 22), (7, 28, 23), (9, 36, 24)])
+def test_regrouped_circuit_matches_original(L, nq, G, seed):
+    c = qi.circuit(seed, nq, G, 0)
+    fg, fm = L.fuse_circuit(nq, c, regroup=True)
+    f = _unpack(nq, fg, fm)
+    cg, _ = L.fuse_circuit(nq, c)
+    assert 1 <= len(f) <= len(cg)
+    assert all(1 <= k <= 3 for k in f.ks)
+    psi = qi.state(seed, nq, 1)
+    a, b = oracle.circuit(c, psi), oracle.circuit(f, psi)
+    assert np.linalg.norm(a - b) <= TOL * np.linalg.norm(a)
+
+
+def test_regroup_moves_only_commuting_gates(L):
+    rng = np.random.default_rng(31)
+    A, C = qi.random_unitary(rng, 2), qi.random_unitary(rng, 2)
+    B = qi.random_unitary(rng, 8)
+    # C commutes past B (disjoint qubits) and merges with A: C.A on qubit 1
+    c = qi.Circuit(4).add(A, 1).add(B, 2, 3, 4).add(C, 1)
+    fg, fm = L.fuse_circuit(4, c, regroup=True)
+    assert len(fg) == 2
+    assert int(fg[0]["k"]) == 1 and int(fg[0]["q"][0]) == 1
+    np.testing.assert_allclose(fm[:4].reshape(2, 2), C @ A, rtol=0, atol=1e-15)
+    assert int(fg[1]["k"]) == 3 and list(fg[1]["q"][:3]) == [2, 3, 4]
+    assert np.array_equal(fm[4:], B.reshape(-1))                 # lone gate copied
+    assert len(L.fuse_circuit(4, c)[0]) == 3                     # consecutive: no merge
+    # D shares qubit 2 with B, so it may not move ahead of B
+    D = qi.random_unitary(rng, 4)
+    d = qi.Circuit(4).add(A, 1).add(B, 2, 3, 4).add(D, 1, 2)
+    fg, fm = L.fuse_circuit(4, d, regroup=True)
+    assert len(fg) == 3 and [int(k) for k in fg["k"]] == [1, 3, 2]
+    psi = qi.state(31, 4, 1)
+    np.testing.assert_allclose(oracle.circuit(_unpack(4, fg, fm), psi), oracle.circuit(d, psi),
+                               rtol=0, atol=1e-14)
