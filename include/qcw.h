@@ -135,7 +135,10 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
  * applies every gate of the run there with the one-gate sweep's arithmetic,
  * and stores it back, so a run of gates costs one read and one write of the
  * state instead of one per gate.  States below 9 qubits use one sweep per
- * gate.  Synchronises `stream` once, to hand the pass plan to the device.
+ * gate.  Synchronises `stream` once, to hand the pass plan to the device,
+ * unless the stream's previous call had the same request (shape, flags,
+ * gates and matrix entries): its plan is kept on the device per stream and
+ * reused, and the call then only enqueues the passes.
  */
 int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                       const qcw_c64 *mats, int64_t nmats, int tile_bits, void *stream);

@@ -121,6 +121,31 @@ def test_fused_plan_ghz_and_inverse(L):
     assert np.abs(back - qi.basis_state(nq, 0)).max() <= 16 * 2.0 ** -53
 
 
+def test_fused_plan_cache_follows_the_request(L):
+    """A stream reuses its last plan only for the same request: the same
+    circuit twice, then the same gate list with one matrix entry changed, then
+    other plan flags, each equal to the plain path."""
+    nq = 16
+    c = qi.circuit(15, nq, 40)
+    g, m = L.pack_circuit(c)
+    psi0 = qi.state(15, nq)
+    a = torch.from_numpy(psi0).to("cuda")
+    b = a.clone()
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        L.qcw_circuit_fused_ex(a, nq, g, len(c), m, m.size, 12, 4, 0, COMMUTE | FUSE, s)
+        L.qcw_circuit(b, nq, g, len(c), m, m.size, s)
+    torch.cuda.synchronize()
+    assert _close(a.cpu().numpy(), b.cpu().numpy(), 2 * len(c))
+    m2 = m.copy()
+    m2[5] *= -1j                                     # linear update: any matrix is fine
+    for plan in (COMMUTE | FUSE, 0):
+        L.qcw_circuit_fused_ex(a, nq, g, len(c), m2, m2.size, 12, 4, 0, plan, s)
+        L.qcw_circuit(b, nq, g, len(c), m2, m2.size, s)
+        torch.cuda.synchronize()
+        assert _close(a.cpu().numpy(), b.cpu().numpy(), 4 * len(c))
+
+
 def test_fused_fewer_passes(L):
     c = qi.circuit(1, 31, 124)
     g, m = L.pack_circuit(c)

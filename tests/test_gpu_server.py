@@ -66,17 +66,28 @@ def test_alone_equals_in_the_mix(L, gpt):
         assert np.linalg.norm(out - r) <= 1e-12 * max(1, len(c) / 64) * np.linalg.norm(r)
 
 
+def _device_bytes(nq, c):
+    """A request's arena footprint as the server accounts it: state, 64-B gate
+    rows and matrices, each rounded up to 256 B.  A server without a tune table
+    runs the exact tile shapes, which take the circuit as given (no fusion)."""
+    r = lambda x: (x + 255) // 256 * 256
+    return r(16 << nq) + r(64 * len(c)) + r(16 * sum(x.size for x in c.mats))
+
+
 def test_small_budget_admission_on_gpu(L):
+    """A budget below the three smallest requests but above the largest: every
+    request runs, never more than two at once."""
     inst = qi.batch(4, 40, 8, 9)
-    need = max((16 << nq) + 64 * len(c) + 16 * sum(x.size for x in c.mats) + 768
-               for nq, _, c in inst)
-    s = L.Server(hbm_budget_bytes=2 * need, max_slots=64)
+    fp = sorted(_device_bytes(nq, c) for nq, _, c in inst)
+    budget = fp[0] + fp[1] + fp[2] - 256
+    assert budget >= fp[-1]
+    s = L.Server(hbm_budget_bytes=budget, max_slots=64)
     tickets = [s.submit(nq, c, p) for nq, p, c in inst]
     for t, (nq, p, c) in zip(tickets, inst):
         out, st = s.wait(t, nq)
         assert np.array_equal(out, _alone(L, nq, p, c))
     cnt = s.counters()
-    assert cnt["peak_active"] <= 2 and cnt["completed"] == 40
+    assert 1 <= cnt["peak_active"] <= 2 and cnt["completed"] == 40
     s.close()
 
 
