@@ -463,6 +463,106 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
             "fidelity_after": ob["fidelity"], **spectral}
 
 
+def bench_config0(torch, L, qi, reps=10000):
+    """Config 0: the paper's first worked-example size (nq = 3), one 12-gate
+    random circuit (seed 0) on the plain path, one solve at a time: latency of
+    single solves (host clock around a solve and its synchronisation; p50/p99
+    over `reps`), throughput of back-to-back solves, and the error of one solve
+    against the oracle."""
+    import oracle
+    nq, G = 3, 12
+    psi0 = qi.state(0, nq)
+    c = qi.circuit(0, nq, G)
+    g, m = L.pack_circuit(c)
+    psi = torch.from_numpy(psi0).to("cuda")
+    L.qcw_circuit(psi, nq, g, len(c), m, m.size)
+    torch.cuda.synchronize()
+    ref = oracle.circuit(c, psi0)
+    err = float(np.linalg.norm(psi.cpu().numpy() - ref) / np.linalg.norm(ref))
+    lat = np.empty(reps)
+    for i in range(reps):
+        t0 = time.perf_counter()
+        L.qcw_circuit(psi, nq, g, len(c), m, m.size)
+        torch.cuda.synchronize()
+        lat[i] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.qcw_circuit(psi, nq, g, len(c), m, m.size)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"nq": nq, "gates": G, "seed": 0, "solves": reps,
+            "p50_us": float(np.percentile(lat, 50) * 1e6),
+            "p99_us": float(np.percentile(lat, 99) * 1e6),
+            "back_to_back_solves_per_s": reps / dt,
+            "rel_err_vs_oracle": err}
+
+
+def bench_sweeps(torch, L, qi, sizes=(26, 28, 30, 31), reps=5):
+    """Config 1 as single sweeps: one gate per launch, k = 1, 2, 3 with targets
+    on the lowest qubits, the highest, or both ends, at several sizes; GB/s
+    (32 B per amplitude) against the 8 TB/s peak and against a plain copy
+    kernel measured here (torch copy_ of 16 GiB).  Also OmegaALL (H on every
+    qubit) at the largest size, as fused passes and as one sweep per qubit."""
+    print("[bench] sweeps: copy kernel", file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    a = torch.zeros(1 << 30, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 2 * a.numel() * 16 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(1)
+    rows = []
+    omega = None
+    for nq in sizes:
+        print(f"[bench] sweeps: nq={nq}", file=sys.stderr, flush=True)
+        N = 1 << nq
+        psi = torch.randn(N, dtype=torch.complex128, device="cuda")
+        for k in (1, 2, 3):
+            classes = (("lowest", tuple(range(nq, nq - k, -1))),
+                       ("highest", tuple(range(1, k + 1))),
+                       ("mixed", ((nq // 2,), (1, nq), (1, nq // 2, nq))[k - 1]))
+            for cls, targets in classes:
+                U = qi.random_unitary(rng, 1 << k)
+                L.qcw_opk(k, targets, U, psi)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    L.qcw_opk(k, targets, U, psi)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                gbs = 32 * N / (ms * 1e-3) / 1e9
+                rows.append({"nq": nq, "k": k, "targets": cls, "qubits": list(targets),
+                             "ms": ms, "GB/s": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
+                             "frac_of_copy": gbs / copy_gbs})
+        if nq == sizes[-1]:
+            L.qcw_omega_all(qi.H, psi)
+            torch.cuda.synchronize()
+            e0.record()
+            L.qcw_omega_all(qi.H, psi)
+            e1.record()
+            torch.cuda.synchronize()
+            fused_ms = e0.elapsed_time(e1)
+            e0.record()
+            for q in range(1, nq + 1):
+                L.qcw_op1(qi.H, q, psi)
+            e1.record()
+            torch.cuda.synchronize()
+            omega = {"nq": nq, "fused_passes_ms": fused_ms,
+                     "one_sweep_per_qubit_ms": e0.elapsed_time(e1)}
+        del psi
+        torch.cuda.empty_cache()
+    return {"copy_kernel_GB/s": copy_gbs, "rows": rows, "omega_all_H": omega}
+
+
 def bench_plain_small(torch, L, qi, nq, seed, reps=2000):
     """Literal paper size: one nq-qubit state, one 4*nq-gate circuit per solve."""
     psi = torch.from_numpy(qi.state(seed, nq)).to("cuda")
@@ -620,6 +720,8 @@ def main():
                                                  label="4096 x nq 3..7")
         extra["batched_config4"] = bench_batched(torch, L, qi, 4, 4096, 9, 9, tt,
                                                  label="4096 x nq 9")
+        extra["config0_plain_nq3"] = bench_config0(torch, L, qi)
+        extra["sweeps_config1"] = bench_sweeps(torch, L, qi)
         extra["plain_nq9"] = bench_plain_small(torch, L, qi, 9, 1)
         extra["grover_n6"] = bench_grover(torch, L, qi, tt)
         extra["shard_nq32"] = bench_shard(torch, L, qi)

@@ -104,7 +104,10 @@ int qcw_opk(int k, const int *targets, const qcw_c64 *U, qcw_c64 *psi, int nq,
 int qcw_opk_to(int k, const int *targets, const qcw_c64 *U,
                const qcw_c64 *psi_in, qcw_c64 *psi_out, int nq, void *stream);
 
-/* OmegaALL[U, psi] (§4a): the same 2 x 2 U on every qubit, qubit 1 first. */
+/* OmegaALL[U, psi] (§4a): the same 2 x 2 U on every qubit, qubit 1 first.
+ * From 22 qubits on it runs as list-order fused passes (about nq/8 passes
+ * over HBM instead of nq sweeps; bit for bit the same result, and the stream
+ * is synchronised once when the pass plan changes, as in qcw_circuit_fused). */
 int qcw_omega_all(const qcw_c64 *U, qcw_c64 *psi, int nq, void *stream);
 
 /*

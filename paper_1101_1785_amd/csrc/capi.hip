@@ -157,12 +157,33 @@ int qcw_op3(const qcw_c64 *W, int is1, int is2, int is3, qcw_c64 *psi, int nq, v
   return qcw_opk(3, t, W, psi, nq, stream);
 }
 
+// OmegaALL runs as fused passes from this many qubits on (a pass then moves at
+// least 64 MiB, so the plan's one-off synchronisation is small beside the
+// sweeps it saves); tile shape as qcw_circuit_fused's default.
+constexpr int kOmegaFusedMinQubits = 22;
+constexpr int kOmegaTileBits = 12;
+constexpr int kOmegaLowBits = 4;
+
 int qcw_omega_all(const qcw_c64 *U, qcw_c64 *psi, int nq, void *stream) {
   clear_error();
   if (!U) return fail(QCW_EINVAL, "matrix is NULL");
   if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
   int rc = check_device_range(psi, ((uint64_t)1 << nq) * sizeof(qcw_c64), "psi");
   if (rc) return rc;
+  if (nq >= kOmegaFusedMinQubits) {
+    // the nq one-qubit gates as list-order fused passes: bit for bit the
+    // sweeps below, in ~nq/8 passes over HBM instead of nq
+    std::vector<qcw_gate> gl((size_t)nq);
+    for (int q = 1; q <= nq; ++q) {
+      qcw_gate &g = gl[q - 1];
+      memset(&g, 0, sizeof g);
+      g.k = 1;
+      g.q[0] = q;
+      g.mat = 0;
+    }
+    return run_fused(psi, nq, gl.data(), nq, U, kOmegaTileBits, kOmegaLowBits, 0, 0,
+                     (hipStream_t)stream);
+  }
   for (int q = 1; q <= nq; ++q) {
     Geom g;
     if ((rc = make_geom(nq, 1, &q, &g))) return rc;

@@ -1,4 +1,6 @@
 // One-gate sweep: QCWAVE's Op1 / Op2 / Op3 (§3a-§3c) on a state in HBM.
+// (Gates on the two lowest qubits and others among the lowest 12 run as
+// contiguous LDS tiles instead: sweep_low_kernel below.)
 //
 // Each thread takes GPT groups (pairs, quartets or octets).  Group j's base
 // label comes from inserting zero bits at the sorted target positions; member
@@ -120,8 +122,78 @@ static int launch_k(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 
   return QCW_OK;
 }
 
+// Gates whose targets all lie in the lowest kLowTileBits label bits and
+// include bits 0 and 1: a group's members then form runs of 4 or 8 adjacent
+// amplitudes, and in sweep_kernel each member load of a wavefront touches a
+// separate cache line per lane.  Here each block instead moves one contiguous
+// tile of 2^kLowTileBits amplitudes through LDS with coalesced loads and
+// stores, and applies the gate to the tile's groups there, with the same
+// products in the same order as sweep_kernel (so the same bits).
+constexpr int kLowTileBits = 12;
+constexpr int kLowBlock = 512;
+
+template <int K>
+__global__ __launch_bounds__(kLowBlock) void sweep_low_kernel(const double2 *in, double2 *out,
+                                                              SweepArg<uint32_t> a, MatArg<K> U) {
+  constexpr int M = 1 << K;
+  constexpr int TILE = 1 << kLowTileBits;
+  constexpr int PER = TILE / kLowBlock;
+  constexpr int G = (TILE / M) / kLowBlock;  // groups per thread
+  extern __shared__ double2 S[];
+  const uint64_t t0 = (uint64_t)blockIdx.x << kLowTileBits;
+  v2d v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    v[q] = *reinterpret_cast<const v2d *>(in + t0 + q * kLowBlock + threadIdx.x);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) S[q * kLowBlock + threadIdx.x] = make_double2(v[q].x, v[q].y);
+  __syncthreads();
+  double2 x[G][M];
+  uint32_t base[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    base[i] = insert_zeros<K, uint32_t>(i * kLowBlock + threadIdx.x, a.sb0, a.sb1, a.sb2);
+#pragma unroll
+    for (int r = 0; r < M; ++r) x[i][r] = S[base[i] + a.off[r]];
+  }
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    double2 y[M];
+    group_matvec<M>(x[i], y, [&](int r, int c) { return U.u[r * M + c]; });
+#pragma unroll
+    for (int r = 0; r < M; ++r) S[base[i] + a.off[r]] = y[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const double2 y = S[q * kLowBlock + threadIdx.x];
+    *reinterpret_cast<v2d *>(out + t0 + q * kLowBlock + threadIdx.x) = v2d{y.x, y.y};
+  }
+}
+
+template <int K>
+static int launch_low(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *out,
+                      hipStream_t s) {
+  MatArg<K> m;
+  for (int i = 0; i < (1 << K) * (1 << K); ++i) m.u[i] = make_double2(U[i].re, U[i].im);
+  SweepArg<uint32_t> a = sweep_arg<uint32_t>(g);
+  const uint64_t blocks = (uint64_t)1 << (g.nq - kLowTileBits);
+  if (blocks > 0x7fffffffULL) return fail(QCW_EINVAL, "state too large for one launch");
+  const size_t lds = sizeof(double2) << kLowTileBits;
+  TimedLaunch t(K, s);
+  hipLaunchKernelGGL((sweep_low_kernel<K>), dim3((unsigned)blocks), dim3(kLowBlock), lds, s,
+                     reinterpret_cast<const double2 *>(in), reinterpret_cast<double2 *>(out), a, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(QCW_EHIP, "sweep launch: %s", hipGetErrorString(e));
+  return QCW_OK;
+}
+
 int launch_sweep(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *out,
                  hipStream_t s) {
+  // Targets within the lowest tile bits, including bits 0 and 1: LDS tiles.
+  if (g.k >= 2 && g.nq >= kLowTileBits && g.nq <= 31 && g.sb[0] == 0 && g.sb[1] == 1 &&
+      g.sb[g.k - 1] < kLowTileBits)
+    return g.k == 2 ? launch_low<2>(g, U, in, out, s) : launch_low<3>(g, U, in, out, s);
   // 32-bit labels while every label and shift fits (nq <= 31), 64-bit above.
   const bool small = g.nq <= 31;
   switch (g.k) {

@@ -151,6 +151,54 @@ def test_omega_all(L, nq):
     close(host(psi), ref, G=nq)
 
 
+def _low_cases(nq):
+    return [(nq, nq - 1), (nq - 1, nq), (nq, nq - 1, nq - 2), (nq - 2, nq, nq - 1),
+            (nq - 1, nq, nq - 11), (nq - 11, nq - 1, nq)]
+
+
+@pytest.mark.parametrize("nq", [12, 13, 17, 22])
+def test_lowest_qubit_gates_tile_kernel(L, nq):
+    """Gates on qubits nq and nq-1 with every target among the lowest 12 label
+    bits run as contiguous LDS tiles: within the FP64 tolerance of the oracle,
+    and bit for bit the one-gate fused pass (the sweep's arithmetic), in place
+    and out of place."""
+    print(f"[gpu] lowest-qubit tile kernel nq={nq}", flush=True)
+    rng = np.random.default_rng(200 + nq)
+    psi0 = rand_state(rng, nq)
+    for t in _low_cases(nq):
+        k = len(t)
+        U = qi.random_unitary(rng, 1 << k)
+        a = dev(psi0)
+        L.qcw_opk(k, t, U, a)
+        b = dev(psi0)
+        L.circuit_fused(b, qi.Circuit(nq).add(U, *t), 12, low_bits=3)
+        c = torch.empty_like(a)
+        L.qcw_opk_to(k, t, U, dev(psi0), c)
+        ha = host(a)
+        assert np.array_equal(ha, host(b)), t
+        assert np.array_equal(ha, host(c)), t
+        close(ha, oracle.apply(U, t, psi0), G=1)
+
+
+@pytest.mark.parametrize("nq", [21, 22, 25])
+def test_omega_all_large_equals_sweeps_bitwise(L, nq):
+    """From 22 qubits OmegaALL runs as fused passes: bit for bit the nq
+    one-qubit sweeps (21 still runs the sweeps), and H on |0..0> gives the
+    closed form 2^(-nq/2) everywhere."""
+    print(f"[gpu] omega_all nq={nq}", flush=True)
+    rng = np.random.default_rng(100 + nq)
+    psi0 = rand_state(rng, nq)
+    U = qi.random_unitary(rng, 2)
+    a, b = dev(psi0), dev(psi0)
+    L.qcw_omega_all(U, a)
+    for q in range(1, nq + 1):
+        L.qcw_op1(U, q, b)
+    assert np.array_equal(host(a), host(b))
+    psi = dev(qi.basis_state(nq, 0))
+    L.qcw_omega_all(qi.H, psi)
+    assert np.max(np.abs(host(psi) - 2.0 ** (-nq / 2))) <= 4 * nq * 2.0 ** -53
+
+
 def test_permutation_gates_bit_exact(L):
     rng = np.random.default_rng(3)
     nq = 12
