@@ -17,7 +17,9 @@ events recorded by the library on the launch stream), the CPU oracle timed on
 a bounded sample of the same solve, and sections for the batched (4096
 instances) and served (open-loop Poisson) forms.
 
---counters runs each kernel once at nq = 28 beside a plain copy of known size,
+--counters runs each kernel once at nq = 28 beside a plain copy of known size
+(the sweep for k = 1, 2, 3, once more on the three lowest qubits, and one fused
+solve),
 for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; it prints what it launched.
 """
 from __future__ import annotations
@@ -591,7 +593,7 @@ def counters_run(torch, L, qi):
     del src, dst
     psi = torch.from_numpy(qi.state(1, nq)).to("cuda")
     rng = np.random.default_rng(0)
-    for k, t in ((1, (14,)), (2, (3, 20)), (3, (10, 4, 25))):
+    for k, t in ((1, (14,)), (2, (3, 20)), (3, (10, 4, 25)), (3, (nq, nq - 1, nq - 2))):
         L.qcw_opk(k, t, qi.random_unitary(rng, 1 << k), psi)
     c = qi.circuit(1, nq, 4 * nq)
     g, m = L.pack_circuit(c)
@@ -599,7 +601,7 @@ def counters_run(torch, L, qi):
     torch.cuda.synchronize()
     print(json.dumps({"counters_run": {
         "copy_bytes_read": 16 << 27, "copy_bytes_written": 16 << 27,
-        "sweep_launches": 3, "sweep_bytes_per_launch": 32 * N,
+        "sweep_launches": 4, "sweep_bytes_per_launch": 32 * N,
         "fused_passes": L.qcw_fused_pass_count(nq, g, len(c), 0, 0, 3),
         "fused_bytes_per_pass": 32 * N, "nq": nq}}), flush=True)
 
