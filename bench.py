@@ -6,9 +6,10 @@ with probabilities .50/.35/.15, random ordered targets, random unitaries)
 applied in place to one nq-qubit complex FP64 state that is already resident
 in HBM.  The default workload is the largest single state the 64 GB device
 budget admits, nq = 31 (2^31 amplitudes, 32 GiB), seed 1, run by the fused
-multi-gate path (qcw_circuit_fused_ex with both plan flags: gates on disjoint
-qubits reordered into fewer passes, gates merged inside a pass; --plan 0 for
-the bit-exact list-order passes, --path plain for one sweep per gate).
+multi-gate path (qcw_circuit_fused_ex with all plan flags: gates on disjoint
+qubits reordered into fewer passes, gates merged inside a pass, the
+three-product complex arithmetic; --plan 0 for the bit-exact list-order
+passes, --path plain for one sweep per gate).
 
 Prints ONE JSON line with the throughput (solves/s), the roofline of the
 dominant kernel (algorithmic bytes 32 * 2^nq per launch -- one pass reads and
@@ -51,8 +52,9 @@ def _args():
     p.add_argument("--path", choices=["fused", "plain"], default="fused",
                    help="fused multi-gate passes (default) or one sweep per gate")
     p.add_argument("--tile-bits", type=int, default=0)
-    p.add_argument("--plan", type=int, choices=[0, 1, 2, 3], default=3,
-                   help="fused plan flags: 1 = QCW_PLAN_COMMUTE, 2 = QCW_PLAN_FUSE (default both)")
+    p.add_argument("--plan", type=int, choices=range(8), default=7,
+                   help="fused plan flags: 1 = QCW_PLAN_COMMUTE, 2 = QCW_PLAN_FUSE, "
+                        "4 = QCW_PLAN_3M (default all three)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-log2", type=int, default=26,
                    help="contiguous outputs per gate timed on the CPU oracle")
@@ -597,12 +599,12 @@ def counters_run(torch, L, qi):
         L.qcw_opk(k, t, qi.random_unitary(rng, 1 << k), psi)
     c = qi.circuit(1, nq, 4 * nq)
     g, m = L.pack_circuit(c)
-    L.qcw_circuit_fused_ex(psi, nq, g, len(c), m, m.size, 0, 0, 0, 3)
+    L.qcw_circuit_fused_ex(psi, nq, g, len(c), m, m.size, 0, 0, 0, 7)
     torch.cuda.synchronize()
     print(json.dumps({"counters_run": {
         "copy_bytes_read": 16 << 27, "copy_bytes_written": 16 << 27,
         "sweep_launches": 4, "sweep_bytes_per_launch": 32 * N,
-        "fused_passes": L.qcw_fused_pass_count(nq, g, len(c), 0, 0, 3),
+        "fused_passes": L.qcw_fused_pass_count(nq, g, len(c), 0, 0, 7),
         "fused_bytes_per_pass": 32 * N, "nq": nq}}), flush=True)
 
 
@@ -754,8 +756,9 @@ def main():
                         f"seed {a.seed}",
             "nq": nq, "gates": G, "seed": a.seed,
             "path": "qcw_circuit_fused_ex" if a.path == "fused" else "qcw_circuit",
-            "plan": ({0: "list order (bit-exact)", 1: "QCW_PLAN_COMMUTE", 2: "QCW_PLAN_FUSE",
-                      3: "QCW_PLAN_COMMUTE|QCW_PLAN_FUSE"}[a.plan] if a.path == "fused" else None),
+            "plan": (("|".join(n for b, n in ((1, "QCW_PLAN_COMMUTE"), (2, "QCW_PLAN_FUSE"),
+                                               (4, "QCW_PLAN_3M")) if a.plan & b)
+                      or "list order (bit-exact)") if a.path == "fused" else None),
             "passes_per_solve": npass,
             **other,
         },

@@ -160,6 +160,13 @@ enum {
    * one gate (their product, computed on the host), so a tile goes through
    * LDS fewer times (124 gates become about 70 for the circuit above). */
   QCW_PLAN_FUSE = 2,
+  /* Each gate inside a tile uses the three-product form of the complex
+   * matrix-vector product (U = A + iB on x = a + ib: Re y = A(a+b) - (A+B)b,
+   * Im y = A(a+b) + (B-A)a, with A+B and B-A formed on the host): 3m instead
+   * of 4m FMAs per amplitude for an m x m gate.  Its rounding error stays
+   * within a small factor of the direct product's for matrices of modest
+   * norm, such as unitaries. */
+  QCW_PLAN_3M = 4,
 };
 
 /* The same with the number of contiguous low label bits every tile keeps
@@ -168,12 +175,13 @@ enum {
  * the gates' targets; the threads per tile (256 or 512 for tile_bits 11;
  * 256, 512 or 1024 for 12 and 13, where 12 with 1024 is a warp-specialised
  * pipelined kernel; 0 = the tuned default); and the plan flags
- * (QCW_PLAN_COMMUTE | QCW_PLAN_FUSE, or 0; other bits are QCW_EINVAL). */
+ * (any of QCW_PLAN_COMMUTE | QCW_PLAN_FUSE | QCW_PLAN_3M, or 0; other bits are
+ * QCW_EINVAL). */
 int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
                          int threads, int plan, void *stream);
 /* Number of passes qcw_circuit_fused_ex makes for this gate list and plan
- * (host only; QCW_PLAN_FUSE does not change it). */
+ * (host only; QCW_PLAN_FUSE and QCW_PLAN_3M do not change it). */
 int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits,
                          int low_bits, int plan);
 /* The same plan in full (host only): pass_of[g] receives the pass of gate g

@@ -34,8 +34,11 @@ constexpr int fused_block(int T) { return T <= 11 ? 256 : (1 << (T - 3)); }
 struct alignas(16) FusedGate {
   int32_t k;
   int32_t sb0, sb1, sb2;  // local (tile-index) target bits, ascending
+  int32_t m3;             // 0: u is U; 1: three-product form (u = (A, -(A+B)), d = B - A)
+  int32_t pad[3];
   uint32_t off[8];        // local member offsets, local index order
-  double2 u[64];          // m x m matrix, row-major
+  double2 u[64];          // m x m, row-major (see m3)
+  double d[64];           // m x m, row-major, three-product form only
 };
 
 struct alignas(16) FusedPass {
@@ -81,6 +84,71 @@ __device__ __forceinline__ void tile_gate(double2 *S, const FusedGate &g) {
   }
 }
 
+// The same gate in the three-product form (U = A + iB on x = a + ib):
+//   Re y = A (a + b) - (A + B) b,   Im y = A (a + b) + (B - A) a,
+// with A + B and B - A formed on the host: per output row one shared real
+// product A (a + b) and one more real product for each part, 3m FMAs instead
+// of 4m (plus m additions for a + b per group).  The rounding differs from
+// the direct product (each term is bounded by a small multiple of |U| |x|, so
+// the error stays within a small factor of it).
+template <int K, int NT, int T>
+__device__ __forceinline__ void tile_gate3m(double2 *S, const FusedGate &g) {
+  constexpr int M = 1 << K;
+  constexpr uint32_t NG = 1u << (T - K);
+  constexpr int G = NG >= NT ? (int)(NG / NT) : 1;
+  const uint32_t tid = threadIdx.x % NT;
+  double2 x[G][M];
+  uint32_t base[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    const uint32_t j = i * NT + tid;
+    base[i] = insert_zeros<K, uint32_t>(j, g.sb0, g.sb1, g.sb2);
+    if (NG >= NT || j < NG) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) x[i][r] = S[base[i] + g.off[r]];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    const uint32_t j = i * NT + tid;
+    if (NG >= NT || j < NG) {
+      double sum[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) sum[c] = x[i][c].x + x[i][c].y;
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) t = __fma_rn(g.u[r * M + c].x, sum[c], t);
+        double re = t, im = t;
+#pragma unroll
+        for (int c = 0; c < M; ++c) re = __fma_rn(g.u[r * M + c].y, x[i][c].y, re);
+#pragma unroll
+        for (int c = 0; c < M; ++c) im = __fma_rn(g.d[r * M + c], x[i][c].x, im);
+        S[base[i] + g.off[r]] = make_double2(re, im);
+      }
+    }
+  }
+}
+
+// One gate of a pass on a tile, in the form its plan chose.
+template <int NT, int T>
+__device__ __forceinline__ void tile_apply(double2 *S, const FusedGate &g) {
+  if (g.m3) {
+    switch (g.k) {
+      case 1: tile_gate3m<1, NT, T>(S, g); break;
+      case 2: tile_gate3m<2, NT, T>(S, g); break;
+      default: tile_gate3m<3, NT, T>(S, g); break;
+    }
+  } else {
+    switch (g.k) {
+      case 1: tile_gate<1, NT, T>(S, g); break;
+      case 2: tile_gate<2, NT, T>(S, g); break;
+      default: tile_gate<3, NT, T>(S, g); break;
+    }
+  }
+}
+
 // Each thread stages 2^T / NT amplitudes of the tile.
 template <int T, int L, int NT = fused_block(T)>
 __global__ __launch_bounds__(NT) void fused_pass_kernel(double2 *psi,
@@ -113,11 +181,7 @@ __global__ __launch_bounds__(NT) void fused_pass_kernel(double2 *psi,
   __syncthreads();
   for (int gi = 0; gi < P.ngates; ++gi) {
     const FusedGate &g = gates[P.gate_off + gi];
-    switch (g.k) {
-      case 1: tile_gate<1, NT, T>(S, g); break;
-      case 2: tile_gate<2, NT, T>(S, g); break;
-      default: tile_gate<3, NT, T>(S, g); break;
-    }
+    tile_apply<NT, T>(S, g);
     __syncthreads();
   }
 #pragma unroll
@@ -174,11 +238,7 @@ __global__ __launch_bounds__(NT) void fused_persistent_kernel(double2 *psi,
     }
     for (int gi = 0; gi < P.ngates; ++gi) {
       const FusedGate &g = gates[P.gate_off + gi];
-      switch (g.k) {
-        case 1: tile_gate<1, NT, T>(S, g); break;
-        case 2: tile_gate<2, NT, T>(S, g); break;
-        default: tile_gate<3, NT, T>(S, g); break;
-      }
+      tile_apply<NT, T>(S, g);
       __syncthreads();
     }
 #pragma unroll
@@ -273,11 +333,7 @@ __global__ __launch_bounds__(1024) void fused_ws_kernel(double2 *psi,
     for (int gi = 0; gi < ng; ++gi) {
       if (!mem) {
         const FusedGate &g = gates[P.gate_off + gi];
-        switch (g.k) {
-          case 1: tile_gate<1, NC, T>(X, g); break;
-          case 2: tile_gate<2, NC, T>(X, g); break;
-          default: tile_gate<3, NC, T>(X, g); break;
-        }
+        tile_apply<NC, T>(X, g);
       } else if (gi == ng - 1 && has_next) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) Y[q * 512 + tm] = make_double2(w[q].x, w[q].y);
@@ -327,7 +383,9 @@ static int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 //   merged into one gate (their matrix product, the first gate rightmost), so
 //   the tile makes fewer LDS round trips.  Alone it merges runs of
 //   consecutive gates; with QCW_PLAN_COMMUTE a gate may also join a block
-//   ahead of gates of the pass it shares no qubit with.  A merge may add at
+//   ahead of gates of the pass it shares no qubit with.
+// * QCW_PLAN_3M: the tile applies each gate in the three-product form
+//   (tile_gate3m), 3m instead of 4m FMAs per amplitude.  A merge may add at
 //   most kFuseExtraFlops flops per amplitude: two one-qubit gates, or two
 //   two-qubit gates sharing a qubit, are merged; a one-qubit gate and a
 //   disjoint two-qubit gate (44 -> 62 flops) are not, since the in-tile work
@@ -606,7 +664,15 @@ static int plan_passes(int nq, const std::vector<Geom> &geo, const qcw_gate *gat
         G.off[rr] = o;
       }
       const qcw_c64 *U = pu[i];
-      for (int e = 0; e < (1 << (2 * G.k)); ++e) G.u[e] = make_double2(U[e].re, U[e].im);
+      G.m3 = (plan & QCW_PLAN_3M) ? 1 : 0;
+      for (int e = 0; e < (1 << (2 * G.k)); ++e) {
+        if (G.m3) {
+          G.u[e] = make_double2(U[e].re, -(U[e].re + U[e].im));
+          G.d[e] = U[e].im - U[e].re;
+        } else {
+          G.u[e] = make_double2(U[e].re, U[e].im);
+        }
+      }
       fg.push_back(G);
     }
     passes.push_back(P);
@@ -892,8 +958,8 @@ int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
                          int threads, int plan, void *stream) {
   clear_error();
-  if (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE))
-    return fail(QCW_EINVAL, "plan=%d has bits other than QCW_PLAN_COMMUTE and QCW_PLAN_FUSE", plan);
+  if (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE | QCW_PLAN_3M))
+    return fail(QCW_EINVAL, "plan=%d has bits other than QCW_PLAN_COMMUTE, QCW_PLAN_FUSE and QCW_PLAN_3M", plan);
   if (nq < 1 || nq > kMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kMaxQubits);
   if (ngates < 0) return fail(QCW_EINVAL, "ngates < 0");
   if (ngates > 0 && (!gates || !mats)) return fail(QCW_EINVAL, "gates or mats is NULL");
@@ -935,7 +1001,7 @@ int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bit
   if (low_bits == 0) low_bits = kFusedDefaultLow;
   if (nq < 1 || nq > kMaxQubits || ngates < 0 || (ngates > 0 && !gates) || tile_bits < 8 ||
       tile_bits > 13 || low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree ||
-      (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE)))
+      (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE | QCW_PLAN_3M)))
     return fail(QCW_EINVAL, "invalid arguments");
   int n = fused_pass_count(nq, gates, ngates, tile_bits, low_bits, plan, nullptr, nullptr);
   return n < 0 ? fail(QCW_EINVAL, "invalid gate") : n;
@@ -948,7 +1014,7 @@ int qcw_fused_plan(int nq, const qcw_gate *gates, int ngates, int tile_bits, int
   if (low_bits == 0) low_bits = kFusedDefaultLow;
   if (nq < 1 || nq > kMaxQubits || ngates < 0 || (ngates > 0 && (!gates || !pass_of || !order)) ||
       tile_bits < 8 || tile_bits > 13 || low_bits < 3 || low_bits > 5 ||
-      tile_bits - low_bits > kFusedMaxFree || (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE)))
+      tile_bits - low_bits > kFusedMaxFree || (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE | QCW_PLAN_3M)))
     return fail(QCW_EINVAL, "invalid arguments");
   int n = fused_pass_count(nq, gates, ngates, tile_bits, low_bits, plan, pass_of, order);
   return n < 0 ? fail(QCW_EINVAL, "invalid gate") : n;

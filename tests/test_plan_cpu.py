@@ -20,7 +20,7 @@ import oracle
 import qcw_inputs as qi
 
 TOL = 1e-12
-COMMUTE, FUSE = 1, 2
+COMMUTE, FUSE, M3 = 1, 2, 4
 
 
 @pytest.fixture(scope="module")
@@ -62,6 +62,7 @@ def test_commute_plan_is_a_valid_reordering(L, nq, seed, tile_bits, low_bits):
     n0 = L.qcw_fused_pass_count(nq, g, len(c), tile_bits, low_bits, 0)
     assert n <= n0
     assert L.qcw_fused_pass_count(nq, g, len(c), tile_bits, low_bits, COMMUTE | FUSE) == n
+    assert L.qcw_fused_pass_count(nq, g, len(c), tile_bits, low_bits, COMMUTE | FUSE | M3) == n
 
 
 @pytest.mark.parametrize("nq,seed", [(9, 5), (11, 6), (13, 7)])
@@ -120,7 +121,7 @@ def test_plan_validation(L):
     c = qi.circuit(0, 12, 8)
     g, _ = L.pack_circuit(c)
     with pytest.raises(L.QcwError):
-        L.qcw_fused_plan(12, g, len(c), 12, 4, 4)
+        L.qcw_fused_plan(12, g, len(c), 12, 4, 8)
     with pytest.raises(L.QcwError):
         L.qcw_fused_pass_count(12, g, len(c), 12, 4, -1)
     with pytest.raises(L.QcwError):
