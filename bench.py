@@ -204,6 +204,24 @@ def bench_batched(torch, L, qi, seed, count, lo, hi, tune_table, reps=50, plain=
         pg = np.concatenate([p.cpu().numpy() for p in psis])
         out["batched_equals_plain_bitwise"] = bool(np.array_equal(pg, got))
         out["max_abs_diff_vs_plain"] = float(np.max(np.abs(pg - got)))
+        # one persistent-kernel launch per instance (eager), over the first
+        # `single` instances; set-up outside the timed region
+        single = min(count, 512)
+        one = [L.Batch([(nq, c)], ps, tune_table=tune_table)
+               for (nq, _, c), ps in zip(inst[:single], psis[:single])]
+        for x in one:
+            x.run_eager()
+        torch.cuda.synchronize()
+        e0.record()
+        for x in one:
+            x.run_eager()
+        e1.record()
+        torch.cuda.synchronize()
+        sm = e0.elapsed_time(e1)
+        for x in one:
+            x.close()
+        out["single_launch_per_instance_solves_per_s"] = single / (sm * 1e-3)
+        out["single_launch_instances_timed"] = single
     return out
 
 
