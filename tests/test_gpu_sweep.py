@@ -261,6 +261,31 @@ def full_state():
     return psi0
 
 
+@pytest.fixture(scope="module")
+def state28():
+    free, _ = torch.cuda.mem_get_info()
+    if free < (2 * (16 << 28) + (4 << 30)):
+        pytest.skip("not enough device memory")
+    print("[gpu] generating the nq=28 state", flush=True)
+    return qi.state(28, 28)
+
+
+@pytest.mark.parametrize("k,targets", [(1, (15,)), (2, (28, 27)), (3, (1, 14, 28))])
+def test_full_compare_nq28(L, state28, k, targets):
+    """nq = 28 (4 GiB): every output of one gate against the oracle, the full
+    elementwise comparison of the measurement plan (k = 2 on the two lowest
+    qubits runs as LDS tiles)."""
+    print(f"[gpu] full compare nq=28 k={k} targets={targets}", flush=True)
+    rng = np.random.default_rng(280 + k)
+    U = qi.random_unitary(rng, 1 << k)
+    psi = dev(state28)
+    L.qcw_opk(k, targets, U, psi)
+    got = host(psi)
+    del psi
+    torch.cuda.empty_cache()
+    close(got, oracle.apply(U, targets, state28), G=1)
+
+
 @pytest.mark.parametrize("k,targets", [
     (1, (FULL_NQ,)), (1, (1,)), (1, (16,)),
     (2, (FULL_NQ, FULL_NQ - 1)), (2, (1, 2)), (2, (3, 29)),
