@@ -487,7 +487,7 @@ class FrontPlanner {
   }
 
   // Plan built pass by pass: each pass is the best of `trials` candidates
-  // (the greedy one and trials - 1 with random ties), judged by the greedy
+  // (the greedy one and trials - 1 with random ties), scored by the greedy
   // completion's pass count (lookahead < 0) or by the gates placed after
   // `lookahead` more greedy passes.  Stops early once it cannot beat `bound`
   // passes (returns an empty plan then).
@@ -533,7 +533,7 @@ class FrontPlanner {
 // Search effort for the commute planner: only for states of at least
 // kSearchMinQubits qubits, where one pass takes well over a millisecond and
 // a plan is cached per stream, and for lists of at most kSearchMaxGates gates
-// (kRolloutMaxGates for the full-completion judge).  Measured on random
+// (kRolloutMaxGates for scoring by full greedy completion).  Measured on random
 // 124-gate circuits at nq = 31: ~8% fewer passes than the greedy plan.
 constexpr int kSearchMinQubits = 24;
 constexpr int kSearchMaxGates = 2048;
@@ -571,7 +571,7 @@ static std::vector<PlanRun> plan_runs(int nq, const std::vector<Geom> &geo, Fuse
   FrontPlanner fp(gm, T, low);
   runs = fp.finish(fp.start());
   if (nq >= kSearchMinQubits && ng <= kSearchMaxGates) {
-    // a small portfolio of judges; the plan with the fewest passes wins
+    // a small portfolio of scoring rules; the plan with the fewest passes wins
     // (the earliest on ties)
     const int lookaheads[3] = {-1, 1, 2};
     for (int la : lookaheads) {
