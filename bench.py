@@ -424,17 +424,22 @@ def bench_shard(torch, L, qi, nq=32):
     return out
 
 
-def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
+def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="pauli"):
     """Multiverse density-matrix steps (Eq. rhoE4): channel of n_p single-hit and
-    n_p double-hit Pauli paths (weights eps*p_s/n_p, p1=.95, p2=.05, p_keep=1-eps),
-    then one algorithm gate (H_1 or a CNOT of the GHZ chain) by conjugation."""
+    n_p double-hit paths (weights eps*p_s/n_p, p1=.95, p2=.05, p_keep=1-eps) whose
+    hit operators are Pauli operators or (noise="rotation") random rotations
+    exp(-i theta n.sigma/2), then one algorithm gate (H_1 or a CNOT of the GHZ
+    chain) by conjugation."""
     rng = np.random.default_rng([seed, 7])
     P = [qi.X, qi.Y, qi.Z]
+
+    def hit():
+        return qi.random_rotation(rng) if noise == "rotation" else P[int(rng.integers(3))]
     terms = []
     for s, ps in ((1, 0.95), (2, 0.05)):
         for _ in range(n_p):
             qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
-            terms.append((eps * ps / n_p, {q: P[int(rng.integers(3))] for q in qs}))
+            terms.append((eps * ps / n_p, {q: hit() for q in qs}))
     ch = L.Channel(nq, 1 - eps, terms)
     psi0 = qi.basis_state(nq, 0)
     a = torch.from_numpy(np.outer(psi0, psi0.conj()).reshape(-1)).to("cuda")
@@ -469,14 +474,15 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20):
         rho0 = torch.from_numpy(np.outer(psi0, psi0.conj()).reshape(-1)).to("cuda")
         t0 = time.perf_counter()
         F = L.qcw_rho_fidelity(x, rho0)
-        spectral = {"entropy_bits_after": S, "max_eigenvalue_after": float(ev[-1]),
+        spectral = {"entropy_bits_after": S, "entropy_nats_after": S * float(np.log(2.0)),
+                    "max_eigenvalue_after": float(ev[-1]),
                     "general_fidelity_after": F,
                     "fidelity_call_ms": (time.perf_counter() - t0) * 1e3}
     NN = 1 << (2 * nq)
     fl = ch.flops_per_element() * NN
     cavg = cms / max(n, 1)
     ch.close()
-    return {"nq": nq, "paths": 2 * n_p, "steps_per_s": 1e3 / ms, "ms_per_step": ms,
+    return {"nq": nq, "paths": 2 * n_p, "noise": noise, "steps_per_s": 1e3 / ms, "ms_per_step": ms,
             "channel_ms": cavg, "channel_fp64_tflops": fl / (cavg * 1e-3) / 1e12,
             "channel_fp64_frac": fl / (cavg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
             "channel_gbs_read_write_once": 32 * NN / (cavg * 1e-3) / 1e9,
@@ -749,6 +755,8 @@ def main():
         extra["shard_nq32"] = bench_shard(torch, L, qi)
         extra["multiverse_nq12"] = bench_multiverse(torch, L, qi, 12, 5)
         extra["multiverse_nq5"] = bench_multiverse(torch, L, qi, 5, 5, steps=200)
+        extra["multiverse_nq5_rotation_noise"] = bench_multiverse(torch, L, qi, 5, 6, steps=200,
+                                                                  noise="rotation")
         extra["serving_config3"] = bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9, tt)
         if a.serve_sweep_seconds > 0:
             extra["serving_rate_sweep"] = bench_serving_sweep(torch, L, qi, tt,

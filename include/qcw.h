@@ -370,7 +370,8 @@ int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
  *
  * qcw_rho_eigvals writes 2^nq + 1 doubles to out_host: the eigenvalues in
  * ascending order, then the von Neumann entropy -sum lambda log2 lambda in
- * bits (over lambda > 0; in the classical limit it tends to nq).
+ * bits (over lambda > 0; in the classical limit it tends to nq).  The paper
+ * writes S = -Tr rho ln rho; its value in nats is the bits value times ln 2.
  * qcw_rho_fidelity writes F = Tr sqrt(sqrt(rho0) rho sqrt(rho0)) (the root
  * fidelity, 1/sqrt2 after one Hadamard on |0>) for a general rho0.
  * qcw_rho_partial_trace (asynchronous) writes the reduced density matrix of

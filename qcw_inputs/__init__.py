@@ -243,6 +243,23 @@ TOFFOLI = np.eye(8, dtype=np.complex128)
 TOFFOLI[6:8, 6:8] = X                                        # |110> <-> |111>
 
 
+def random_rotation(rng: np.random.Generator) -> np.ndarray:
+    """A general one-qubit rotation, the alternative noise operator of the
+    multiverse scheme (§5, the general-rotation option beside the Pauli
+    operators): exp(-i theta n.sigma / 2) = cos(theta/2) I - i sin(theta/2)
+    (n_x X + n_y Y + n_z Z), with theta uniform on [0, 2 pi) and the axis n
+    uniform on the unit sphere (z = cos of the polar angle uniform on [-1, 1],
+    azimuth uniform on [0, 2 pi)).  Draw order: theta, z, azimuth."""
+    theta = rng.uniform(0.0, 2.0 * np.pi)
+    z = rng.uniform(-1.0, 1.0)
+    phi = rng.uniform(0.0, 2.0 * np.pi)
+    r = np.sqrt(max(0.0, 1.0 - z * z))
+    nx, ny = r * np.cos(phi), r * np.sin(phi)
+    c, sn = np.cos(theta / 2), np.sin(theta / 2)
+    return np.array([[c - 1j * sn * z, -1j * sn * (nx - 1j * ny)],
+                     [-1j * sn * (nx + 1j * ny), c + 1j * sn * z]], dtype=np.complex128)
+
+
 def cphase(phi: float) -> np.ndarray:
     """Controlled phase: diag(1, 1, 1, e^{i phi}) (§4b)."""
     return np.diag([1, 1, 1, np.exp(1j * phi)]).astype(np.complex128)

@@ -276,3 +276,24 @@ def test_channel_mixed_monomial_and_dense_terms(L, nq):
     ch.apply(a, b)
     assert np.max(np.abs(host(b, nq) - D.channel(rho0, 0.8, terms))) <= TOL
     ch.close()
+
+
+@pytest.mark.parametrize("nq", [2, 5])
+def test_channel_random_rotation_noise(L, nq):
+    """The general-rotation noise option of the multiverse scheme (random
+    rotations exp(-i theta n.sigma/2) as the hit operators instead of Pauli
+    operators), single and double hits: equal to the oracle, trace and
+    hermiticity kept."""
+    rng = np.random.default_rng(90 + nq)
+    rho0 = _rand_rho(rng, nq)
+    terms = []
+    for i in range(8):
+        qs = [int(x) + 1 for x in rng.choice(nq, min(nq, 1 + i % 2), replace=False)]
+        terms.append((0.2 / 8, {q: qi.random_rotation(rng) for q in qs}))
+    ch = L.Channel(nq, 0.8, terms)
+    a, b = dev(rho0), torch.empty(1 << (2 * nq), dtype=torch.complex128, device="cuda")
+    ch.apply(a, b)
+    out = host(b, nq)
+    assert np.max(np.abs(out - D.channel(rho0, 0.8, terms))) <= TOL
+    assert abs(np.trace(out) - 1) <= TOL and np.max(np.abs(out - out.conj().T)) <= TOL
+    ch.close()

@@ -55,3 +55,38 @@ def test_named_gates_unitary():
     for U in (qi.H, qi.X, qi.Y, qi.Z, qi.CNOT, qi.CZ, qi.SWAP, qi.TOFFOLI, qi.cphase(0.3)):
         m = U.shape[0]
         assert np.allclose(U.conj().T @ U, np.eye(m), atol=1e-15)
+
+
+def test_random_rotation_is_the_exponential_of_a_spin_rotation():
+    """UE1-style noise operator: exp(-i theta n.sigma/2) for a unit axis n,
+    checked against scipy's matrix exponential of the same generator (theta
+    and n read back from the draw order), and SU(2): unitary, det 1."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        st = rng.bit_generator.state
+        R = qi.random_rotation(rng)
+        r2 = np.random.default_rng(0)
+        r2.bit_generator.state = st
+        theta, z, phi = r2.uniform(0, 2 * np.pi), r2.uniform(-1, 1), r2.uniform(0, 2 * np.pi)
+        n = np.array([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z])
+        G = n[0] * qi.X + n[1] * qi.Y + n[2] * qi.Z
+        np.testing.assert_allclose(R, expm(-0.5j * theta * G), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(R @ R.conj().T, np.eye(2), rtol=0, atol=1e-14)
+        assert abs(np.linalg.det(R) - 1) <= 1e-14
+
+
+def test_random_rotation_axis_is_isotropic():
+    """Axis uniform on the sphere: E[n] = 0 and E[n_i^2] = 1/3, read off the
+    rotations themselves (R - R^dagger = -2i sin(theta/2) n.sigma)."""
+    rng = np.random.default_rng(4)
+    ns = []
+    for _ in range(20000):
+        R = qi.random_rotation(rng)
+        A = (R - R.conj().T) / -2j               # sin(theta/2) n.sigma
+        v = np.array([A[0, 1].real, -A[0, 1].imag, A[0, 0].real])
+        if np.linalg.norm(v) > 1e-3:
+            ns.append(v / np.linalg.norm(v))
+    ns = np.array(ns)
+    assert np.all(np.abs(ns.mean(axis=0)) < 0.03)
+    assert np.all(np.abs((ns ** 2).mean(axis=0) - 1 / 3) < 0.02)
