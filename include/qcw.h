@@ -28,7 +28,9 @@
  *   - Gate matrices, gate lists and target arrays are HOST pointers; they
  *     are consumed before the call returns and may be freed right after.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
- *     asynchronously on it; the call does not synchronise.
+ *     asynchronously on it; the call does not synchronise unless its
+ *     description says so (the fused passes and OmegaALL when they upload a
+ *     new pass plan, the observables, eigenvalue and autotune calls).
  *
  * Errors: every call returns QCW_OK or a negative code synchronously and
  * raises no exception.  QCW_EINVAL: null pointer, nq outside [1, 34],
@@ -457,9 +459,9 @@ int qcw_server_destroy(qcw_server *s);
  * qcw_timing_read synchronises those events and returns, for one kernel
  * family, the number of launches and their summed duration in milliseconds
  * since the last reset.  Families: QCW_KERNEL_SWEEP1..3 (one-gate sweeps of
- * k = 1, 2, 3), QCW_KERNEL_BATCH (batch executions), QCW_KERNEL_FUSED
- * (fused passes).  Launches recorded
- * into a hipGraph are not timed individually.
+ * k = 1, 2, 3, in either sweep kernel), QCW_KERNEL_BATCH (batch executions),
+ * QCW_KERNEL_FUSED (fused passes), QCW_KERNEL_CHANNEL (channel applications).
+ * Launches recorded into a hipGraph are not timed individually.
  */
 enum {
   QCW_KERNEL_SWEEP1 = 1,
