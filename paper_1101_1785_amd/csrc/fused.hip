@@ -367,9 +367,9 @@ static int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 // lowest unused bits (larger contiguous chunks).
 //
 // By default a pass is a run of consecutive gates, extended while its bits
-// fit, and results equal the one-sweep-per-gate path bit for bit.  Two plan
-// flags trade that for less work; both leave the circuit's operator unchanged
-// and change only the rounding:
+// fit, and results equal the one-sweep-per-gate path bit for bit.  Three plan
+// flags trade that for less work; each leaves the circuit's operator
+// unchanged and changes only the rounding:
 // * QCW_PLAN_COMMUTE: a pass may take any gate of the front, i.e. any gate
 //   not yet placed that shares no qubit with an earlier gate not yet placed.
 //   Gates on disjoint qubits commute (the tensor structure of §2c), so moving
