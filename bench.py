@@ -397,6 +397,61 @@ def bench_serving_sweep(torch, L, qi, tt, seconds, rates=(2000, 8000, 12000, 160
                       "~1/client_submit_us the client, not the server, sets the rate"}
 
 
+def bench_serving_native(L, qi, tt, seconds, rates=(8000, 16000, 32000, 48000, 64000),
+                         clients=2, pool=4096, seed=3, lo=3, hi=9):
+    """Config 3 driven by the native open-loop load generator (serve_load, built
+    beside the library): requests submitted from `clients` C++ threads at
+    Poisson arrival times, results copied to host memory in submission order.
+    Same request mix and server settings as bench_serving; latency from each
+    request's scheduled arrival to its completion."""
+    import subprocess
+    import tempfile
+    exe = os.path.join(ROOT, "paper_1101_1785_amd", "serve_load")
+    if not os.path.exists(exe):
+        return {"skipped": "serve_load not built"}
+    inst = qi.batch(seed, pool, lo, hi)
+    out = {"seconds_per_rate": seconds, "client_threads": clients, "nq_range": [lo, hi],
+           "seed": seed, "request_pool": pool, "server": []}
+    with tempfile.TemporaryDirectory() as d:
+        pool_path = os.path.join(d, "pool.bin")
+        with open(pool_path, "wb") as f:
+            np.array([pool], dtype=np.int32).tofile(f)
+            for nq, p, c in inst:
+                g, m = L.pack_circuit(c)
+                np.array([nq, len(g)], dtype=np.int32).tofile(f)
+                np.array([m.size], dtype=np.int64).tofile(f)
+                g.tofile(f)
+                np.ascontiguousarray(m, dtype=np.complex128).tofile(f)
+                np.ascontiguousarray(p, dtype=np.complex128).tofile(f)
+        rec = np.dtype([("sched", "<i8"), ("done", "<i8"), ("status", "<i4")])
+        for rate in rates:
+            print(f"[bench] serving (native client): {rate}/s for {seconds}s", file=sys.stderr,
+                  flush=True)
+            arr = qi.poisson_arrivals(seed, rate, seconds)
+            arr_path, res_path = os.path.join(d, "arr.bin"), os.path.join(d, "res.bin")
+            with open(arr_path, "wb") as f:
+                np.array([arr.size], dtype=np.int64).tofile(f)
+                arr.astype(np.float64).tofile(f)
+            r = subprocess.run([exe, pool_path, arr_path, res_path, str(1 << 30), "1024", str(hi),
+                                tt or "-", str(clients)], capture_output=True, text=True,
+                               timeout=seconds * 10 + 120)
+            if r.returncode not in (0, 1) or not os.path.exists(res_path):
+                out["server"].append({"rate_per_s": rate, "error": r.stderr[-300:]})
+                break
+            raw = np.fromfile(res_path, dtype=np.uint8)
+            n, ticks, peak = np.frombuffer(raw[:24].tobytes(), dtype=np.int64)
+            recs = np.frombuffer(raw[24:].tobytes(), dtype=rec)
+            okm = recs["status"] == 0
+            lat = (recs["done"][okm] - recs["sched"][okm]) / 1e6
+            span = (recs["done"][okm].max() - recs["sched"].min()) / 1e9
+            out["server"].append({
+                "rate_per_s": rate, "requests": int(n), "failed": int((~okm).sum()),
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "solves_per_s": float(okm.sum() / span), "ticks": int(ticks),
+                "peak_active": int(peak)})
+    return out
+
+
 def bench_grover(torch, L, qi, tt, count=1024, n=6, seed=9):
     """Textbook Grover search (qcw_inputs.workloads) over n data qubits, at the
     optimal iteration count, for `count` random marked items in one batched
@@ -804,6 +859,8 @@ def main():
         if a.serve_sweep_seconds > 0:
             extra["serving_rate_sweep"] = bench_serving_sweep(torch, L, qi, tt,
                                                               a.serve_sweep_seconds)
+            extra["serving_native_sweep"] = bench_serving_native(L, qi, tt,
+                                                                 a.serve_sweep_seconds)
 
     out = {
         "metric": METRIC,

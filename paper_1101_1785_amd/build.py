@@ -1,7 +1,8 @@
 """Builds libqcw.so (HIP, gfx950) in-tree with hipcc.
 
 Every HIP source under csrc/ is compiled for gfx950 into one shared library
-next to this file.  Packed FP32 instruction selection is disabled for all
+next to this file; the request server's load generator (loadgen/) is built
+beside it against that library.  Packed FP32 instruction selection is disabled for all
 device code.  Usage: python -m paper_1101_1785_amd.build
 """
 from __future__ import annotations
@@ -58,7 +59,23 @@ def build(jobs: int = 8) -> str:
            "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_loadgen()
     return LIB
+
+
+LOADGEN_SRC = os.path.join(HERE, "loadgen", "serve_load.cpp")
+LOADGEN = os.path.join(HERE, "serve_load")
+
+
+def build_loadgen() -> str:
+    """The open-loop load generator for the request server (host code only,
+    linked against libqcw.so next to it)."""
+    tmp = LOADGEN + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-Wall", f"-I{INCLUDE}", LOADGEN_SRC, "-o", tmp,
+           f"-L{HERE}", "-lqcw", "-Wl,-rpath,$ORIGIN", "-lpthread"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LOADGEN)
+    return LOADGEN
 
 
 if __name__ == "__main__":
