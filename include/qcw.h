@@ -403,7 +403,11 @@ int qcw_rho_partial_trace(const qcw_c64 *rho, int nq, const int *keep, int nkeep
  * circuit is fused at submit and results agree to FP64 rounding.
  *
  * All request arrays are HOST pointers copied by qcw_server_submit, which
- * does not block on the GPU.  A request that can never run (invalid gates,
+ * does not block on the GPU.  Uploads and result copies are batched per
+ * tick: beside the arena the server holds a staging buffer of 64 MiB (or the
+ * budget, if smaller) and a result buffer of min(budget, max_slots * 16 *
+ * 2^max_nq) bytes, each on the device and in pinned host memory.  A request
+ * that can never run (invalid gates,
  * nq above the limit, more memory than the whole budget) is rejected with
  * QCW_EINVAL at submit and affects no other request.
  */

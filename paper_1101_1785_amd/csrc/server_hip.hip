@@ -2,11 +2,18 @@
 //
 // Device memory: one arena of the configured budget.  An admitted request
 // occupies [state | gate table | matrices] at its arena offset until it
-// completes, so its state stays resident across ticks.  A tick uploads the
-// small instance and work-item tables of the resident requests (pinned host
-// buffers, async copies), runs ONE persistent batch launch (the same kernel
-// as qcw_batch_run) over them, copies the states of finishing requests to
-// pinned host buffers and waits for the tick's event.
+// completes, so its state stays resident across ticks.
+//
+// Host traffic is batched per tick.  Admission packs each request's region,
+// laid out as in the arena, into a pinned staging buffer and returns without
+// touching the GPU.  A tick then appends its small tables (copy lists,
+// instances, work items) behind the staged requests and issues, on one
+// stream: one host-to-device copy of the staging buffer into its device
+// mirror, a copy-list kernel that scatters the staged requests into their
+// arena regions, ONE persistent batch launch (the same kernel as
+// qcw_batch_run) over the resident requests, a copy-list kernel that gathers
+// the states of finishing requests into one contiguous buffer, one
+// device-to-host copy of that buffer into pinned memory, and one wait.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -23,16 +30,39 @@ namespace {
 
 uint64_t round256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+static_assert(sizeof(qcw_c64) == sizeof(double2), "qcw_c64 is stored as double2");
+
+// One contiguous device-to-device copy of `bytes` (a multiple of 16) bytes.
+struct CopyEnt {
+  uint64_t src, dst, bytes, pad;
+};
+static_assert(sizeof(CopyEnt) == 32, "CopyEnt layout");
+
+constexpr int kCopyThreads = 256;
+constexpr int kCopyMaxSplit = 64;                  // blocks per entry at most
+constexpr uint64_t kStageBlobBytes = 64ull << 20;  // staged requests between two ticks
+
+// Block (x, y) copies the 16-byte words y*256 + t, stepping 256*gridDim.y, of
+// entry x.
+__global__ void __launch_bounds__(kCopyThreads) copy_list_kernel(const CopyEnt *__restrict__ ents) {
+  const CopyEnt e = ents[blockIdx.x];
+  const uint4 *__restrict__ src = (const uint4 *)e.src;
+  uint4 *__restrict__ dst = (uint4 *)e.dst;
+  const uint64_t words = e.bytes >> 4;
+  const uint64_t step = (uint64_t)kCopyThreads * gridDim.y;
+  for (uint64_t i = (uint64_t)blockIdx.y * kCopyThreads + threadIdx.x; i < words; i += step)
+    dst[i] = src[i];
+}
+
 class HipExecutor : public Executor {
  public:
   ~HipExecutor() override {
     if (stream_) (void)hipStreamSynchronize(stream_);
     (void)hipFree(arena_);
-    (void)hipFree(inst_d_);
-    (void)hipFree(items_d_);
+    (void)hipFree(mirror_d_);
+    (void)hipFree(res_d_);
     (void)hipFree(counter_d_);
-    (void)hipHostFree(inst_h_);
-    (void)hipHostFree(items_h_);
+    (void)hipHostFree(stage_h_);
     (void)hipHostFree(result_h_);
     if (done_) (void)hipEventDestroy(done_);
     if (stream_) (void)hipStreamDestroy(stream_);
@@ -49,17 +79,23 @@ class HipExecutor : public Executor {
     if (hipEventCreateWithFlags(&done_, hipEventDisableTiming) != hipSuccess)
       return hip_fail("event");
     arena_bytes_ = cfg.hbm_budget_bytes & ~uint64_t(255);
+    // Every state that finishes in one tick was resident in the arena.
+    res_cap_ = std::min<uint64_t>(arena_bytes_, (uint64_t)max_slots_ * (16ull << max_nq_));
+    blob_cap_ = std::min<uint64_t>(arena_bytes_, kStageBlobBytes);
+    const uint64_t ms = (uint64_t)max_slots_;
+    table_cap_ = 2 * round256(ms * sizeof(CopyEnt)) + round256(ms * sizeof(BInst)) +
+                 round256(ms * sizeof(BItem));
     if (hipMalloc(&arena_, std::max<uint64_t>(arena_bytes_, 256)) != hipSuccess)
       return mem_fail("arena", arena_bytes_);
-    if (hipMalloc(&inst_d_, sizeof(BInst) * max_slots_) != hipSuccess ||
-        hipMalloc(&items_d_, sizeof(BItem) * max_slots_) != hipSuccess ||
+    if (hipMalloc(&mirror_d_, blob_cap_ + table_cap_) != hipSuccess ||
+        hipMalloc(&res_d_, std::max<uint64_t>(res_cap_, 256)) != hipSuccess ||
         hipMalloc(&counter_d_, 2 * sizeof(int)) != hipSuccess)
-      return mem_fail("tables", 0);
-    if (hipHostMalloc(&inst_h_, sizeof(BInst) * max_slots_) != hipSuccess ||
-        hipHostMalloc(&items_h_, sizeof(BItem) * max_slots_) != hipSuccess ||
-        hipHostMalloc(&result_h_, sizeof(qcw_c64) * ((size_t)max_slots_ << max_nq_)) != hipSuccess)
-      return mem_fail("pinned host buffers", 0);
+      return mem_fail("staging and tables", blob_cap_ + table_cap_ + res_cap_);
+    if (hipHostMalloc(&stage_h_, blob_cap_ + table_cap_) != hipSuccess ||
+        hipHostMalloc(&result_h_, std::max<uint64_t>(res_cap_, 256)) != hipSuccess)
+      return mem_fail("pinned host buffers", blob_cap_ + table_cap_ + res_cap_);
     slots_.resize(max_slots_);
+    ups_.reserve(max_slots_);
     return QCW_OK;
   }
 
@@ -78,90 +114,132 @@ class HipExecutor : public Executor {
     return QCW_OK;
   }
 
+  // Packs the request into the staging buffer; the next tick uploads it.
   int load(int slot, uint64_t off, const ServeRequest &r) override {
     (void)hipSetDevice(dev_);
-    SlotInfo &s = slots_[slot];
+    if (sticky_) return sticky_fail();
     const uint64_t sbytes = round256((uint64_t)16 << r.nq);
-    const uint64_t gbytes = round256((uint64_t)64 * r.ngates);
-    s.nq = r.nq;
-    s.ngates = r.ngates;
-    s.state_off = (int64_t)(off / 16);
-    s.gate_off = (int64_t)((off + sbytes) / 64);
+    const uint64_t gbytes = round256((uint64_t)sizeof(BGate) * r.ngates);
+    const uint64_t need = request_device_bytes(r.nq, r.ngates, (int64_t)r.mats.size());
+    if ((off & 255) || off > arena_bytes_ || need > arena_bytes_ - off)
+      return fail(QCW_EINVAL, "server: arena region [%llu, +%llu) outside the arena",
+                  (unsigned long long)off, (unsigned long long)need);
     const int64_t mat_base = (int64_t)((off + sbytes + gbytes) / 16);
-    std::vector<BGate> bg(r.ngates);
+    const bool staged = need <= blob_cap_;
+    char *h = nullptr;
+    std::vector<char> own;
+    if (staged) {
+      if (need > blob_cap_ - blob_used_ || (int)ups_.size() == max_slots_) {
+        int rc = flush_uploads();
+        if (rc) return rc;
+      }
+      h = stage_h_ + blob_used_;
+    } else {
+      own.resize(need);  // larger than the staging buffer: uploaded on its own
+      h = own.data();
+    }
+    memcpy(h, r.psi0.data(), (size_t)16 << r.nq);
+    BGate *bg = (BGate *)(h + sbytes);
     for (int g = 0; g < r.ngates; ++g) {
       int rc = make_bgate(r.nq, r.gates[g], (int64_t)r.mats.size(), &bg[g]);
       if (rc) return rc;
       bg[g].mat_off += mat_base;
     }
-    std::vector<double2> m2(r.mats.size());
-    for (size_t i = 0; i < m2.size(); ++i) m2[i] = make_double2(r.mats[i].re, r.mats[i].im);
-    char *base = (char *)arena_;
-    if (hipMemcpyAsync(base + off, r.psi0.data(), (size_t)16 << r.nq, hipMemcpyHostToDevice,
-                       stream_) != hipSuccess ||
-        (r.ngates && hipMemcpyAsync(base + off + sbytes, bg.data(), bg.size() * sizeof(BGate),
-                                    hipMemcpyHostToDevice, stream_) != hipSuccess) ||
-        (!m2.empty() && hipMemcpyAsync(base + off + sbytes + gbytes, m2.data(),
-                                       m2.size() * sizeof(double2), hipMemcpyHostToDevice,
-                                       stream_) != hipSuccess))
-      return hip_fail("request upload");
-    // The host vectors die with this call: make sure the copies have consumed them.
-    if (hipStreamSynchronize(stream_) != hipSuccess) return hip_fail("upload sync");
+    if (!r.mats.empty()) memcpy(h + sbytes + gbytes, r.mats.data(), 16 * r.mats.size());
+    SlotInfo &s = slots_[slot];
+    s.nq = r.nq;
+    s.ngates = r.ngates;
+    s.state_off = (int64_t)(off / 16);
+    s.gate_off = (int64_t)((off + sbytes) / 64);
+    if (!staged) {
+      if (hipMemcpyAsync((char *)arena_ + off, h, need, hipMemcpyHostToDevice, stream_) !=
+              hipSuccess ||
+          hipStreamSynchronize(stream_) != hipSuccess)
+        return bail(hip_fail("request upload"));
+      return QCW_OK;
+    }
+    ups_.push_back({blob_used_, off, need});
+    blob_used_ += need;
     return QCW_OK;
   }
 
   int tick(const std::vector<TickItem> &items) override {
     (void)hipSetDevice(dev_);
+    if (sticky_) return sticky_fail();
     const int n = (int)items.size();
+    if (n < 1 || n > max_slots_) return bail(fail(QCW_EINVAL, "server: tick of %d items", n));
+    // Tables behind the staged requests: [uploads | gathers | instances | items].
+    const uint64_t t_up = blob_used_;
+    const uint64_t t_ga = t_up + round256(ups_.size() * sizeof(CopyEnt));
+    const uint64_t t_in = t_ga + round256((uint64_t)n * sizeof(CopyEnt));
+    const uint64_t t_it = t_in + round256((uint64_t)n * sizeof(BInst));
+    const uint64_t t_end = t_it + round256((uint64_t)n * sizeof(BItem));
+    fill_uploads((CopyEnt *)(stage_h_ + t_up));
+    BInst *inst_h = (BInst *)(stage_h_ + t_in);
+    BItem *items_h = (BItem *)(stage_h_ + t_it);
     int max_nq = 1;
     for (int i = 0; i < n; ++i) {
       const SlotInfo &s = slots_[items[i].slot];
-      inst_h_[i] = {s.nq, s.ngates, s.state_off, s.gate_off};
-      items_h_[i] = {i, tune_.variant[s.nq], items[i].g_begin, items[i].g_end};
+      inst_h[i] = {s.nq, s.ngates, s.state_off, s.gate_off};
+      items_h[i] = {i, tune_.variant[s.nq], items[i].g_begin, items[i].g_end};
       max_nq = std::max(max_nq, s.nq);
     }
     // As in the batched form: exact-kernel items first, then matrix-core
     // items; the most work first in each.
-    std::stable_sort(items_h_, items_h_ + n, [&](const BItem &a, const BItem &b) {
+    std::stable_sort(items_h, items_h + n, [&](const BItem &a, const BItem &b) {
       const bool ma = a.variant == kVarAmp4Mfma, mb = b.variant == kVarAmp4Mfma;
       if (ma != mb) return mb;
-      return ((int64_t)(a.g_end - a.g_begin) << inst_h_[a.inst].nq) >
-             ((int64_t)(b.g_end - b.g_begin) << inst_h_[b.inst].nq);
+      return ((int64_t)(a.g_end - a.g_begin) << inst_h[a.inst].nq) >
+             ((int64_t)(b.g_end - b.g_begin) << inst_h[b.inst].nq);
     });
     int n_exact = 0;
-    for (int i = 0; i < n; ++i) n_exact += items_h_[i].variant != kVarAmp4Mfma;
+    for (int i = 0; i < n; ++i) n_exact += items_h[i].variant != kVarAmp4Mfma;
+    // States of finishing requests, packed one after another.
+    CopyEnt *ga = (CopyEnt *)(stage_h_ + t_ga);
+    int nga = 0;
+    uint64_t res_bytes = 0, ga_max = 0;
+    for (const TickItem &it : items) {
+      if (!it.finishes) continue;
+      SlotInfo &s = slots_[it.slot];
+      const uint64_t b = (uint64_t)16 << s.nq, src = (uint64_t)s.state_off * 16;
+      if (src > arena_bytes_ || b > arena_bytes_ - src || b > res_cap_ - res_bytes)
+        return bail(fail(QCW_EINVAL, "server: result copy outside its buffers"));
+      ga[nga++] = {(uint64_t)(uintptr_t)arena_ + src, (uint64_t)(uintptr_t)res_d_ + res_bytes, b, 0};
+      s.res_off = res_bytes;
+      res_bytes += b;
+      ga_max = std::max(ga_max, b);
+    }
     BatchLaunch L{};
     int rc = plan(max_nq, n_exact, n - n_exact, &L);
-    if (rc) return rc;
-    L.items = items_d_;
+    if (rc) return bail(rc);
+    char *mir = (char *)mirror_d_;
+    L.items = (const BItem *)(mir + t_it);
     L.nitems = n;
     L.n_exact = n_exact;
-    L.inst = inst_d_;
+    L.inst = (const BInst *)(mir + t_in);
     L.gates = (const BGate *)arena_;
     L.mats = (const double2 *)arena_;
     L.states = (double2 *)arena_;
     L.counter = counter_d_;
-    if (hipMemcpyAsync(inst_d_, inst_h_, sizeof(BInst) * n, hipMemcpyHostToDevice, stream_) !=
-            hipSuccess ||
-        hipMemcpyAsync(items_d_, items_h_, sizeof(BItem) * n, hipMemcpyHostToDevice, stream_) !=
-            hipSuccess)
-      return hip_fail("tick tables");
-    if ((rc = launch_batch(L, stream_))) return rc;
-    for (const TickItem &it : items) {
-      if (!it.finishes) continue;
-      const SlotInfo &s = slots_[it.slot];
-      if (hipMemcpyAsync(result_h_ + ((size_t)it.slot << max_nq_),
-                         (char *)arena_ + (uint64_t)s.state_off * 16, (size_t)16 << s.nq,
-                         hipMemcpyDeviceToHost, stream_) != hipSuccess)
-        return hip_fail("result copy");
-    }
-    if (hipEventRecord(done_, stream_) != hipSuccess) return hip_fail("event record");
-    if (hipEventSynchronize(done_) != hipSuccess) return hip_fail("tick");
+    if (hipMemcpyAsync(mirror_d_, stage_h_, t_end, hipMemcpyHostToDevice, stream_) != hipSuccess)
+      return bail(hip_fail("tick upload"));
+    if ((rc = launch_copies((const CopyEnt *)(mir + t_up), (int)ups_.size(), up_max_)) ||
+        (rc = launch_batch(L, stream_)) ||
+        (rc = launch_copies((const CopyEnt *)(mir + t_ga), nga, ga_max)))
+      return bail(rc);
+    if (res_bytes && hipMemcpyAsync(result_h_, res_d_, res_bytes, hipMemcpyDeviceToHost,
+                                    stream_) != hipSuccess)
+      return bail(hip_fail("result copy"));
+    if (hipEventRecord(done_, stream_) != hipSuccess) return bail(hip_fail("event record"));
+    if (hipEventSynchronize(done_) != hipSuccess) return bail(hip_fail("tick"));
+    ups_.clear();
+    up_max_ = 0;
+    blob_used_ = 0;  // the staging buffer is free again once the tick is done
     return QCW_OK;
   }
 
   int fetch(int slot, int nq, qcw_c64 *out) override {
-    memcpy(out, result_h_ + ((size_t)slot << max_nq_), (size_t)16 << nq);
+    memcpy(out, (const char *)result_h_ + slots_[slot].res_off, (size_t)16 << nq);
     return QCW_OK;
   }
 
@@ -171,7 +249,68 @@ class HipExecutor : public Executor {
   struct SlotInfo {
     int nq = 0, ngates = 0;
     int64_t state_off = 0, gate_off = 0;
+    uint64_t res_off = 0;  // of the final state in the result buffer
   };
+  struct Upload {
+    uint64_t stage_off, arena_off, bytes;
+  };
+
+  // Copy entries of the staged requests: staging mirror -> arena.
+  void fill_uploads(CopyEnt *out) {
+    up_max_ = 0;
+    for (size_t i = 0; i < ups_.size(); ++i) {
+      const Upload &u = ups_[i];
+      out[i] = {(uint64_t)(uintptr_t)mirror_d_ + u.stage_off,
+                (uint64_t)(uintptr_t)arena_ + u.arena_off, u.bytes, 0};
+      up_max_ = std::max(up_max_, u.bytes);
+    }
+  }
+
+  int launch_copies(const CopyEnt *ents_d, int n, uint64_t max_bytes) {
+    if (n <= 0) return QCW_OK;
+    const uint64_t per_block = (uint64_t)kCopyThreads * 16 * 4;
+    const unsigned split =
+        (unsigned)std::min<uint64_t>(kCopyMaxSplit, std::max<uint64_t>(1, (max_bytes + per_block - 1) / per_block));
+    hipLaunchKernelGGL(copy_list_kernel, dim3((unsigned)n, split), dim3(kCopyThreads), 0, stream_,
+                       ents_d);
+    if (hipGetLastError() != hipSuccess) return hip_fail("copy-list launch");
+    return QCW_OK;
+  }
+
+  // The staging buffer is full before the tick: upload and scatter what it
+  // holds, wait for the copy, and start it over.
+  int flush_uploads() {
+    if (ups_.empty()) return QCW_OK;
+    const uint64_t t_up = blob_used_;
+    const uint64_t t_end = t_up + round256(ups_.size() * sizeof(CopyEnt));
+    fill_uploads((CopyEnt *)(stage_h_ + t_up));
+    int rc = QCW_OK;
+    if (hipMemcpyAsync(mirror_d_, stage_h_, t_end, hipMemcpyHostToDevice, stream_) != hipSuccess)
+      rc = hip_fail("staged upload");
+    else if ((rc = launch_copies((const CopyEnt *)((char *)mirror_d_ + t_up), (int)ups_.size(),
+                                 up_max_)) == QCW_OK &&
+             hipStreamSynchronize(stream_) != hipSuccess)
+      rc = hip_fail("staged upload sync");
+    ups_.clear();
+    up_max_ = 0;
+    blob_used_ = 0;
+    return rc ? sticky_set(rc) : QCW_OK;
+  }
+
+  // A failed upload or tick leaves requests half-loaded: every later load and
+  // tick fails.  The staged uploads are dropped, so none can land in arena
+  // regions that the scheduler hands out again.
+  int sticky_set(int rc) {
+    if (!sticky_) sticky_ = rc;
+    return rc;
+  }
+  int bail(int rc) {
+    ups_.clear();
+    up_max_ = 0;
+    blob_used_ = 0;
+    return sticky_set(rc);
+  }
+  int sticky_fail() { return fail(sticky_, "server executor failed earlier; restart the server"); }
 
   int plan(int max_nq, int n_exact, int n_mfma, BatchLaunch *L) {
     auto &c = plans_[max_nq];
@@ -211,10 +350,18 @@ class HipExecutor : public Executor {
   hipEvent_t done_ = nullptr;
   void *arena_ = nullptr;
   uint64_t arena_bytes_ = 0;
-  BInst *inst_d_ = nullptr, *inst_h_ = nullptr;
-  BItem *items_d_ = nullptr, *items_h_ = nullptr;
-  int *counter_d_ = nullptr;
+  // Staging: requests packed since the last tick [0, blob_used_), then the
+  // tick's tables; mirror_d_ is its device copy.
+  char *stage_h_ = nullptr;
+  void *mirror_d_ = nullptr;
+  uint64_t blob_cap_ = 0, table_cap_ = 0, blob_used_ = 0, up_max_ = 0;
+  std::vector<Upload> ups_;
+  // Final states of the last tick's finishing requests.
+  void *res_d_ = nullptr;
   qcw_c64 *result_h_ = nullptr;
+  uint64_t res_cap_ = 0;
+  int *counter_d_ = nullptr;
+  int sticky_ = QCW_OK;
   std::vector<SlotInfo> slots_;
   PlanCache plans_[kBatchMaxNq + 1];
 };
