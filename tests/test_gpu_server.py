@@ -136,3 +136,63 @@ def test_mfma_table_server_equals_batch_alone(L, tmp_path):
         torch.cuda.synchronize()
         assert np.array_equal(one.cpu().numpy(), outs[i]), i
         b.close()
+
+
+def _burst_request(rng, pool, nq=11, G=500):
+    """nq-qubit request of G three-qubit gates, matrices drawn from `pool` and
+    stored one per gate (so the request carries 1 KiB of matrices per gate)."""
+    from paper_1101_1785_amd import _lib
+    gates = np.zeros(G, dtype=_lib.GATE_DTYPE)
+    gates["k"] = 3
+    gates["q"] = np.argsort(rng.random((G, nq)), axis=1)[:, :3] + 1
+    gates["mat"] = np.arange(G, dtype=np.int64) * 64
+    mats = np.ascontiguousarray(pool[rng.integers(0, len(pool), G)].reshape(-1))
+    psi = qi.state(int(rng.integers(1 << 30)), nq)
+    return gates, mats, psi
+
+
+def test_staging_overflow_and_direct_upload(L):
+    """Admission stages requests in a 64 MiB pinned buffer that each tick
+    uploads.  Two paths beyond the common one:
+    * a request larger than the staging buffer (1 100 001 X gates on 11 qubits,
+      ~70 MiB of gate rows) is uploaded on its own; X gates only permute, so
+      its result is exactly the input with qubit 1 flipped (each other qubit
+      takes an even number of X);
+    * a burst of 140 requests (~79 MiB) that queues while that request's long
+      tick runs is admitted at once, so the staging buffer fills mid-admission
+      and is flushed; every result must equal the plain path alone, bit for bit.
+    """
+    nq0, G0 = 11, 1_100_001
+    print(f"[gpu] server staging: direct request of {G0} gates, then a 140-request burst", flush=True)
+    g0 = np.zeros(G0, dtype=L.GATE_DTYPE)
+    g0["k"] = 1
+    g0["q"][:, 0] = np.arange(G0) % nq0 + 1
+    m0 = np.ascontiguousarray(qi.X.reshape(-1))
+    p0 = qi.state(70, nq0)
+    rng = np.random.default_rng(71)
+    pool = np.stack([qi.random_unitary(rng, 8) for _ in range(32)])
+    burst = [_burst_request(rng, pool) for _ in range(140)]
+    s = L.Server(hbm_budget_bytes=1 << 30, max_slots=256)
+    t0 = s.submit(nq0, psi0=p0, gates=g0, mats=m0)
+    time.sleep(0.05)                                   # its tick is running
+    tickets = [s.submit(11, psi0=p, gates=g, mats=m) for g, m, p in burst]
+    out0, st0 = s.wait(t0, nq0, timeout_s=100.0)
+    assert out0 is not None and st0.status == 0
+    flip = np.arange(1 << nq0) ^ (1 << (nq0 - 1))
+    assert np.array_equal(out0, p0[flip])
+    outs, admits, dones = [], [], []
+    for t in tickets:
+        out, st = s.wait(t, 11, timeout_s=100.0)
+        assert out is not None and st.status == 0
+        outs.append(out)
+        admits.append(st.t_admit_ns)
+        dones.append(st.t_done_ns)
+    s.close()
+    # The whole burst was admitted before any of it completed: one admission,
+    # ~79 MiB staged against a 64 MiB buffer.
+    assert min(admits) >= st0.t_done_ns and max(admits) <= min(dones)
+    for i, ((g, m, p), out) in enumerate(zip(burst, outs)):
+        psi = torch.from_numpy(p).to("cuda")
+        L.qcw_circuit(psi, 11, g, len(g), m, m.size)
+        torch.cuda.synchronize()
+        assert np.array_equal(psi.cpu().numpy(), out), i
