@@ -86,16 +86,11 @@ __device__ __forceinline__ double2 pick4(const double2 (&c)[4], int r, int cc) {
   return r ? hi : lo;
 }
 
-// out = p rho + sum_t w_t K_t rho K_t^dagger, one thread per output element.
-// Permutation-type terms first, one gather per flip-mask group; then the
-// dense terms from their coefficient tables.
-__global__ __launch_bounds__(256) void channel_kernel(
+// One output element x = n * 2^nq + m of the channel.
+__device__ __forceinline__ void channel_one(
     const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
     const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm,
-    const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef) {
-  const uint64_t NN = 1ull << (2 * nq);
-  const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= NN) return;
+    const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef, uint64_t x) {
   const uint64_t N = 1ull << nq;
   const uint64_t n = x >> nq, m = x & (N - 1);
   const double2 r = rho[x];
@@ -149,6 +144,49 @@ __global__ __launch_bounds__(256) void channel_kernel(
     acc_all.y = __fma_rn(T.weight, acc.y, acc_all.y);
   }
   out[x] = acc_all;
+}
+
+constexpr int kChanThreadBits = 8;
+constexpr int kChanThreads = 1 << kChanThreadBits;
+constexpr int kChanChunkBits = 4;              // 2^4 columns = one 256-byte chunk
+constexpr int kXcdBits = 3;                    // 8 XCDs
+constexpr unsigned kChanMaxBlocks = 1u << 20;  // a multiple of the XCD count
+
+// Element (n * 2^nq + m) that thread `threadIdx.x` of virtual block vb
+// handles: a bijection of the 4^nq elements.  A permutation-type term links
+// (n, m) with (n ^ f, m ^ f), and both share o = (n >> L) ^ (m >> L) for
+// L = kChanChunkBits.  Ids run over one o at a time (all 2^nq rows, each at
+// its 2^L-column chunk), so a block's gathers stay among the 2^(nq+L)
+// elements of its o.  Blocks are dealt to the XCDs in turn, so block vb takes
+// an o congruent to vb mod 8: each XCD works through its own o values, whose
+// elements stay in that XCD's L2.  Below 8 values of o, plain order.
+__device__ __forceinline__ uint64_t channel_element(uint64_t vb, int nq) {
+  constexpr int L = kChanChunkBits;
+  if (nq < L + kXcdBits) return vb * kChanThreads + threadIdx.x;
+  const int gb = nq + L - kChanThreadBits;  // log2 of the blocks per value of o
+  const uint64_t j = vb >> kXcdBits;
+  const uint64_t o = ((j >> gb) << kXcdBits) | (vb & ((1u << kXcdBits) - 1));
+  const uint64_t i = (o << (nq + L)) | ((j & ((1ull << gb) - 1)) << kChanThreadBits) | threadIdx.x;
+  const uint64_t n = (i >> L) & ((1ull << nq) - 1);
+  const uint64_t m = ((o ^ (n >> L)) << L) | (i & ((1ull << L) - 1));
+  return (n << nq) | m;
+}
+
+// out = p rho + sum_t w_t K_t rho K_t^dagger, one thread per output element
+// (blocks stride over the virtual blocks).  Permutation-type terms first, one
+// gather per flip-mask group; then the dense terms from their coefficient
+// tables.
+__global__ __launch_bounds__(kChanThreads) void channel_kernel(
+    const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
+    const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm,
+    const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef) {
+  const uint64_t NN = 1ull << (2 * nq);
+  const uint64_t nvb = (NN + kChanThreads - 1) / kChanThreads;
+  for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    if (vb * kChanThreads + threadIdx.x >= NN) continue;
+    channel_one(rho, out, nq, p_keep, groups, ngroups, perm, terms, nterms, coef,
+                channel_element(vb, nq));
+  }
 }
 
 // ------------------------------------------------------------------ observables
@@ -419,9 +457,9 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   int rc;
   if ((rc = check_device_range(rho_in, bytes, "rho_in")) || (rc = check_device_range(rho_out, bytes, "rho_out")))
     return rc;
-  const unsigned blocks = (unsigned)((NN + 255) / 256);
+  const unsigned blocks = (unsigned)std::min<uint64_t>((NN + kChanThreads - 1) / kChanThreads, kChanMaxBlocks);
   TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
-  hipLaunchKernelGGL(channel_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+  hipLaunchKernelGGL(channel_kernel, dim3(blocks), dim3(kChanThreads), 0, (hipStream_t)stream,
                      reinterpret_cast<const double2 *>(rho_in), reinterpret_cast<double2 *>(rho_out),
                      c->nq, c->p_keep, c->groups_d, c->ngroups, c->perm_d, c->terms_d, c->nterms,
                      c->coef_d);

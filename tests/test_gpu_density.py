@@ -51,6 +51,26 @@ def _terms(rng, nq, n_p, eps, unitary=True):
     return terms
 
 
+@pytest.mark.parametrize("nq", [2, 5, 7, 9])
+def test_pauli_channel_matches_oracle(L, nq):
+    """Pauli-type hits (each output element gathers the flipped elements): at
+    nq >= 7 the kernel visits elements in its cache-ordered sequence, which
+    must not change any result."""
+    rng = np.random.default_rng(90 + nq)
+    rho0 = _rand_rho(rng, nq)
+    P = [qi.X, qi.Y, qi.Z]
+    terms = []
+    for s, ps in ((1, 0.95), (2, 0.05)):
+        for _ in range(16):
+            qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
+            terms.append((0.2 * ps / 16, {q: P[int(rng.integers(3))] for q in qs}))
+    ch = L.Channel(nq, 0.8, terms)
+    a, b = dev(rho0), torch.empty(1 << (2 * nq), dtype=torch.complex128, device="cuda")
+    ch.apply(a, b)
+    assert np.max(np.abs(host(b, nq) - D.channel(rho0, 0.8, terms))) <= TOL
+    ch.close()
+
+
 @pytest.mark.parametrize("nq", [1, 2, 3, 5, 7])
 def test_conjugate_matches_oracle(L, nq):
     rng = np.random.default_rng(nq)
@@ -297,3 +317,46 @@ def test_channel_random_rotation_noise(L, nq):
     assert np.max(np.abs(out - D.channel(rho0, 0.8, terms))) <= TOL
     assert abs(np.trace(out) - 1) <= TOL and np.max(np.abs(out - out.conj().T)) <= TOL
     ch.close()
+
+
+def test_pauli_channel_16_qubits_basis_state(L):
+    """nq = 16: 2^32 elements, more than one launch grid can address, so the
+    kernel's blocks stride over the matrix.  On |0..0><0..0| a Pauli hit
+    moves weight w_t to the diagonal element at its flip mask (X and Y flip
+    their qubit, Z does not; |entries| = 1), so the output is p at (0, 0) plus
+    the weights of the flip-free hits, w summed per flip mask f at (f, f), and
+    zero everywhere else (the output starts as NaN, so every element must be
+    written)."""
+    nq = 16
+    N = 1 << nq
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 2 * 16 * N * N + (8 << 30):
+        pytest.skip("needs 128 GiB of free device memory")
+    print(f"[gpu] pauli channel nq={nq} on a basis state", flush=True)
+    rng = np.random.default_rng(16)
+    P = {"X": qi.X, "Y": qi.Y, "Z": qi.Z}
+    terms, expect = [], {0: 0.8}
+    for s, ps in ((1, 0.95), (2, 0.05)):
+        for _ in range(16):
+            qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
+            names = {q: "XYZ"[int(rng.integers(3))] for q in qs}
+            w = 0.2 * ps / 16
+            terms.append((w, {q: P[n] for q, n in names.items()}))
+            f = sum(1 << (nq - q) for q, n in names.items() if n != "Z")
+            expect[f] = expect.get(f, 0.0) + w
+    ch = L.Channel(nq, 0.8, terms)
+    a = torch.zeros(N * N, dtype=torch.complex128, device="cuda")
+    a[0] = 1.0
+    b = torch.full_like(a, float("nan"))
+    ch.apply(a, b)
+    ch.close()
+    del a
+    assert not bool(torch.isnan(b).any())
+    assert int(torch.count_nonzero(b).item()) == len(expect)
+    idx = torch.tensor([f * N + f for f in expect], device="cuda")
+    got = b[idx].cpu().numpy()
+    assert np.allclose(got, list(expect.values()), rtol=0, atol=1e-15)
+    assert abs(complex(b.sum().item()) - 1.0) <= 1e-14
+    del b
+    torch.cuda.empty_cache()
