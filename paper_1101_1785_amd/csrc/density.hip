@@ -80,11 +80,26 @@ __global__ void channel_coef_kernel(const DevTerm *__restrict__ terms, int nterm
   }
 }
 
+// A wave-uniform double, pinned to a scalar register: the entries of a
+// coefficient table are read once per wave (scalar loads) and chosen between
+// as values.  (Left alone, the compiler turns the choice into a per-lane
+// address and a vector load per term, whose wait also drains the gathers.)
+__device__ __forceinline__ double uniform_double(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double2 pick4(const double2 (&c)[4], int r, int cc) {
-  const double2 lo = cc ? c[1] : c[0];
-  const double2 hi = cc ? c[3] : c[2];
+  double2 e[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) e[k] = make_double2(uniform_double(c[k].x), uniform_double(c[k].y));
+  const double2 lo = cc ? e[1] : e[0];
+  const double2 hi = cc ? e[3] : e[2];
   return r ? hi : lo;
 }
+
+constexpr int kChanBatch = 8;  // flip-mask groups gathered together
 
 // One output element x = n * 2^nq + m of the channel.
 __device__ __forceinline__ void channel_one(
@@ -93,21 +108,38 @@ __device__ __forceinline__ void channel_one(
     const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef, uint64_t x) {
   const uint64_t N = 1ull << nq;
   const uint64_t n = x >> nq, m = x & (N - 1);
+  const uint32_t n32 = (uint32_t)n, m32 = (uint32_t)m;  // nq <= kRhoMaxQubits < 32
   const double2 r = rho[x];
   double2 acc_all = make_double2(p_keep * r.x, p_keep * r.y);
-  for (int g = 0; g < ngroups; ++g) {
-    const uint64_t flip = groups[g].flip;
-    const int first = groups[g].first, count = groups[g].count;
-    const double2 v = flip ? rho[((n ^ flip) << nq) | (m ^ flip)] : r;
-    double2 cs = make_double2(0.0, 0.0);
-    for (int t = first; t < first + count; ++t) {
-      const PermTerm &T = perm[t];
-      double2 c = pick4(T.c0, (int)((n >> T.bit0) & 1), (int)((m >> T.bit0) & 1));
-      if (T.nops == 2) c = cmul(c, pick4(T.c1, (int)((n >> T.bit1) & 1), (int)((m >> T.bit1) & 1)));
-      cs.x += c.x;
-      cs.y += c.y;
+  // The gathers of kChanBatch flip-mask groups are issued before their
+  // coefficients are summed, so several are in flight per thread; the
+  // accumulation still runs in group order.
+  for (int g0 = 0; g0 < ngroups; g0 += kChanBatch) {
+    double2 v[kChanBatch];
+#pragma unroll
+    for (int k = 0; k < kChanBatch; ++k) {
+      v[k] = r;
+      if (g0 + k < ngroups) {
+        const uint32_t flip = (uint32_t)groups[g0 + k].flip;
+        if (flip) v[k] = rho[((uint64_t)(n32 ^ flip) << nq) | (m32 ^ flip)];
+      }
     }
-    acc_all = cmad(acc_all, cs, v);
+#pragma unroll
+    for (int k = 0; k < kChanBatch; ++k) {
+      const int g = g0 + k;
+      if (g >= ngroups) continue;
+      const int first = groups[g].first, count = groups[g].count;
+      double2 cs = make_double2(0.0, 0.0);
+      for (int t = first; t < first + count; ++t) {
+        const PermTerm &T = perm[t];
+        double2 c = pick4(T.c0, (int)((n32 >> T.bit0) & 1u), (int)((m32 >> T.bit0) & 1u));
+        if (T.nops == 2)
+          c = cmul(c, pick4(T.c1, (int)((n32 >> T.bit1) & 1u), (int)((m32 >> T.bit1) & 1u)));
+        cs.x += c.x;
+        cs.y += c.y;
+      }
+      acc_all = cmad(acc_all, cs, v[k]);
+    }
   }
   for (int t = 0; t < nterms; ++t) {
     const DevTerm &T = terms[t];
