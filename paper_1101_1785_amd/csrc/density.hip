@@ -105,10 +105,16 @@ constexpr int kChanBatch = 8;  // flip-mask groups gathered together
 __device__ __forceinline__ void channel_one(
     const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
     const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm,
-    const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef, uint64_t x) {
+    const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef, uint64_t x,
+    uint32_t lane_bits) {
   const uint64_t N = 1ull << nq;
   const uint64_t n = x >> nq, m = x & (N - 1);
   const uint32_t n32 = (uint32_t)n, m32 = (uint32_t)m;  // nq <= kRhoMaxQubits < 32
+  // Bits of n and m outside lane_bits are the same in every lane of the
+  // wavefront: a hit on such qubits has one coefficient per wave, chosen
+  // from the first lane's n and m with scalar selects.
+  const uint32_t nu = __builtin_amdgcn_readfirstlane(n32);
+  const uint32_t mu = __builtin_amdgcn_readfirstlane(m32);
   const double2 r = rho[x];
   double2 acc_all = make_double2(p_keep * r.x, p_keep * r.y);
   // The gathers of kChanBatch flip-mask groups are issued before their
@@ -132,9 +138,17 @@ __device__ __forceinline__ void channel_one(
       double2 cs = make_double2(0.0, 0.0);
       for (int t = first; t < first + count; ++t) {
         const PermTerm &T = perm[t];
-        double2 c = pick4(T.c0, (int)((n32 >> T.bit0) & 1u), (int)((m32 >> T.bit0) & 1u));
-        if (T.nops == 2)
-          c = cmul(c, pick4(T.c1, (int)((n32 >> T.bit1) & 1u), (int)((m32 >> T.bit1) & 1u)));
+        const uint32_t tb = (1u << T.bit0) | (T.nops == 2 ? 1u << T.bit1 : 0u);
+        double2 c;
+        if ((tb & lane_bits) == 0) {  // wave-uniform branch
+          c = pick4(T.c0, (int)((nu >> T.bit0) & 1u), (int)((mu >> T.bit0) & 1u));
+          if (T.nops == 2)
+            c = cmul(c, pick4(T.c1, (int)((nu >> T.bit1) & 1u), (int)((mu >> T.bit1) & 1u)));
+        } else {
+          c = pick4(T.c0, (int)((n32 >> T.bit0) & 1u), (int)((m32 >> T.bit0) & 1u));
+          if (T.nops == 2)
+            c = cmul(c, pick4(T.c1, (int)((n32 >> T.bit1) & 1u), (int)((m32 >> T.bit1) & 1u)));
+        }
         cs.x += c.x;
         cs.y += c.y;
       }
@@ -204,6 +218,18 @@ __device__ __forceinline__ uint64_t channel_element(uint64_t vb, int nq) {
   return (n << nq) | m;
 }
 
+// Bits of n and m that can differ between the 64 lanes of a wavefront under
+// channel_element's order: in the cache order, lanes vary the low L bits of m
+// and the two lowest bits of n (a subset); in plain order a wavefront spans
+// 64 consecutive elements, the low six bits of n * 2^nq + m.
+__device__ __forceinline__ uint32_t channel_lane_bits(int nq) {
+  constexpr int L = kChanChunkBits;
+  if (nq >= L + kXcdBits) return (1u << L) - 1;
+  const uint32_t vm = (1u << (nq < 6 ? nq : 6)) - 1;
+  const uint32_t vn = nq < 6 ? (1u << (6 - nq)) - 1 : 0u;
+  return vm | vn;
+}
+
 // out = p rho + sum_t w_t K_t rho K_t^dagger, one thread per output element
 // (blocks stride over the virtual blocks).  Permutation-type terms first, one
 // gather per flip-mask group; then the dense terms from their coefficient
@@ -217,7 +243,7 @@ __global__ __launch_bounds__(kChanThreads) void channel_kernel(
   for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     if (vb * kChanThreads + threadIdx.x >= NN) continue;
     channel_one(rho, out, nq, p_keep, groups, ngroups, perm, terms, nterms, coef,
-                channel_element(vb, nq));
+                channel_element(vb, nq), channel_lane_bits(nq));
   }
 }
 
