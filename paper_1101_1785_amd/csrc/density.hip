@@ -99,14 +99,19 @@ __device__ __forceinline__ double2 pick4(const double2 (&c)[4], int r, int cc) {
   return r ? hi : lo;
 }
 
-constexpr int kChanBatch = 8;  // flip-mask groups gathered together
+constexpr int kChanBatch = 8;             // flip-mask groups gathered together
+constexpr int kChanTableMaxTerms = 256;   // permutation terms staged in LDS (32 KiB)
 
-// One output element x = n * 2^nq + m of the channel.
+// One output element x = n * 2^nq + m of the channel.  With TAB, ctab holds
+// every permutation term's coefficients in LDS (term t: c0 at 8t .. 8t+3, c1
+// at 8t+4 .. 8t+7), so a lane-dependent coefficient is one LDS read instead
+// of selects between scalar values (each of which costs a move as well).
+template <bool TAB>
 __device__ __forceinline__ void channel_one(
     const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
     const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm,
     const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef, uint64_t x,
-    uint32_t lane_bits) {
+    uint32_t lane_bits, const double2 *ctab) {
   const uint64_t N = 1ull << nq;
   const uint64_t n = x >> nq, m = x & (N - 1);
   const uint32_t n32 = (uint32_t)n, m32 = (uint32_t)m;  // nq <= kRhoMaxQubits < 32
@@ -144,6 +149,10 @@ __device__ __forceinline__ void channel_one(
           c = pick4(T.c0, (int)((nu >> T.bit0) & 1u), (int)((mu >> T.bit0) & 1u));
           if (T.nops == 2)
             c = cmul(c, pick4(T.c1, (int)((nu >> T.bit1) & 1u), (int)((mu >> T.bit1) & 1u)));
+        } else if (TAB) {
+          const double2 *e = ctab + 8 * t;
+          c = e[((n32 >> T.bit0) & 1u) * 2 + ((m32 >> T.bit0) & 1u)];
+          if (T.nops == 2) c = cmul(c, e[4 + ((n32 >> T.bit1) & 1u) * 2 + ((m32 >> T.bit1) & 1u)]);
         } else {
           c = pick4(T.c0, (int)((n32 >> T.bit0) & 1u), (int)((m32 >> T.bit0) & 1u));
           if (T.nops == 2)
@@ -234,16 +243,25 @@ __device__ __forceinline__ uint32_t channel_lane_bits(int nq) {
 // (blocks stride over the virtual blocks).  Permutation-type terms first, one
 // gather per flip-mask group; then the dense terms from their coefficient
 // tables.
+template <bool TAB>
 __global__ __launch_bounds__(kChanThreads) void channel_kernel(
     const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
-    const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm,
+    const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm, int nperm,
     const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef) {
+  extern __shared__ double2 ctab[];
+  if (TAB) {
+    for (int e = threadIdx.x; e < 8 * nperm; e += kChanThreads) {
+      const PermTerm &T = perm[e >> 3];
+      ctab[e] = (e & 4) ? T.c1[e & 3] : T.c0[e & 3];
+    }
+    __syncthreads();
+  }
   const uint64_t NN = 1ull << (2 * nq);
   const uint64_t nvb = (NN + kChanThreads - 1) / kChanThreads;
   for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     if (vb * kChanThreads + threadIdx.x >= NN) continue;
-    channel_one(rho, out, nq, p_keep, groups, ngroups, perm, terms, nterms, coef,
-                channel_element(vb, nq), channel_lane_bits(nq));
+    channel_one<TAB>(rho, out, nq, p_keep, groups, ngroups, perm, terms, nterms, coef,
+                     channel_element(vb, nq), channel_lane_bits(nq), ctab);
   }
 }
 
@@ -339,6 +357,7 @@ struct qcw_channel {
   double p_keep = 0;
   int nterms = 0;
   int ngroups = 0;
+  int nperm = 0;               // permutation terms (in groups)
   DevTerm *terms_d = nullptr;  // dense terms
   double2 *coef_d = nullptr;
   PermGroup *groups_d = nullptr;
@@ -472,6 +491,7 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
   c->p_keep = p_keep;
   c->nterms = (int)dt.size();
   c->ngroups = (int)groups.size();
+  c->nperm = (int)perm.size();
   c->flops_per_element = flops;
   if (!groups.empty()) {
     if (hipMalloc(&c->groups_d, sizeof(PermGroup) * groups.size()) != hipSuccess ||
@@ -517,10 +537,16 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
     return rc;
   const unsigned blocks = (unsigned)std::min<uint64_t>((NN + kChanThreads - 1) / kChanThreads, kChanMaxBlocks);
   TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
-  hipLaunchKernelGGL(channel_kernel, dim3(blocks), dim3(kChanThreads), 0, (hipStream_t)stream,
-                     reinterpret_cast<const double2 *>(rho_in), reinterpret_cast<double2 *>(rho_out),
-                     c->nq, c->p_keep, c->groups_d, c->ngroups, c->perm_d, c->terms_d, c->nterms,
-                     c->coef_d);
+  const double2 *in = reinterpret_cast<const double2 *>(rho_in);
+  double2 *o = reinterpret_cast<double2 *>(rho_out);
+  if (c->nperm > 0 && c->nperm <= kChanTableMaxTerms)
+    hipLaunchKernelGGL(channel_kernel<true>, dim3(blocks), dim3(kChanThreads),
+                       sizeof(double2) * 8 * c->nperm, (hipStream_t)stream, in, o, c->nq, c->p_keep,
+                       c->groups_d, c->ngroups, c->perm_d, c->nperm, c->terms_d, c->nterms, c->coef_d);
+  else
+    hipLaunchKernelGGL(channel_kernel<false>, dim3(blocks), dim3(kChanThreads), 0,
+                       (hipStream_t)stream, in, o, c->nq, c->p_keep, c->groups_d, c->ngroups,
+                       c->perm_d, c->nperm, c->terms_d, c->nterms, c->coef_d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(e));
   return QCW_OK;

@@ -71,6 +71,25 @@ def test_pauli_channel_matches_oracle(L, nq):
     ch.close()
 
 
+def test_pauli_channel_many_terms_matches_oracle(L):
+    """300 Pauli-type hits: more than the kernel stages in LDS (256), so the
+    channel takes its path that chooses coefficients from scalar registers."""
+    nq = 7
+    rng = np.random.default_rng(97)
+    rho0 = _rand_rho(rng, nq)
+    P = [qi.X, qi.Y, qi.Z]
+    terms = []
+    for s, ps in ((1, 0.95), (2, 0.05)):
+        for _ in range(150):
+            qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
+            terms.append((0.2 * ps / 150, {q: P[int(rng.integers(3))] for q in qs}))
+    ch = L.Channel(nq, 0.8, terms)
+    a, b = dev(rho0), torch.empty(1 << (2 * nq), dtype=torch.complex128, device="cuda")
+    ch.apply(a, b)
+    assert np.max(np.abs(host(b, nq) - D.channel(rho0, 0.8, terms))) <= TOL
+    ch.close()
+
+
 @pytest.mark.parametrize("nq", [1, 2, 3, 5, 7])
 def test_conjugate_matches_oracle(L, nq):
     rng = np.random.default_rng(nq)
