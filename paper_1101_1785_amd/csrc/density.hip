@@ -104,8 +104,10 @@ constexpr int kChanTableMaxTerms = 256;   // permutation terms staged in LDS (32
 
 // One output element x = n * 2^nq + m of the channel.  With TAB, ctab holds
 // every permutation term's coefficients in LDS (term t: c0 at 8t .. 8t+3, c1
-// at 8t+4 .. 8t+7), so a lane-dependent coefficient is one LDS read instead
-// of selects between scalar values (each of which costs a move as well).
+// at 8t+4 .. 8t+7), and each hit's coefficient is one LDS read at a 2-bit
+// index.  Without it, coefficients are chosen between scalar values: with
+// scalar selects when the hit's qubits are the same in every lane, else with
+// vector selects (each of which costs a move as well).
 template <bool TAB>
 __device__ __forceinline__ void channel_one(
     const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
@@ -143,16 +145,16 @@ __device__ __forceinline__ void channel_one(
       double2 cs = make_double2(0.0, 0.0);
       for (int t = first; t < first + count; ++t) {
         const PermTerm &T = perm[t];
-        const uint32_t tb = (1u << T.bit0) | (T.nops == 2 ? 1u << T.bit1 : 0u);
         double2 c;
-        if ((tb & lane_bits) == 0) {  // wave-uniform branch
-          c = pick4(T.c0, (int)((nu >> T.bit0) & 1u), (int)((mu >> T.bit0) & 1u));
-          if (T.nops == 2)
-            c = cmul(c, pick4(T.c1, (int)((nu >> T.bit1) & 1u), (int)((mu >> T.bit1) & 1u)));
-        } else if (TAB) {
+        if (TAB) {
           const double2 *e = ctab + 8 * t;
           c = e[((n32 >> T.bit0) & 1u) * 2 + ((m32 >> T.bit0) & 1u)];
           if (T.nops == 2) c = cmul(c, e[4 + ((n32 >> T.bit1) & 1u) * 2 + ((m32 >> T.bit1) & 1u)]);
+        } else if ((((1u << T.bit0) | (T.nops == 2 ? 1u << T.bit1 : 0u)) & lane_bits) == 0) {
+          // wave-uniform hit
+          c = pick4(T.c0, (int)((nu >> T.bit0) & 1u), (int)((mu >> T.bit0) & 1u));
+          if (T.nops == 2)
+            c = cmul(c, pick4(T.c1, (int)((nu >> T.bit1) & 1u), (int)((mu >> T.bit1) & 1u)));
         } else {
           c = pick4(T.c0, (int)((n32 >> T.bit0) & 1u), (int)((m32 >> T.bit0) & 1u));
           if (T.nops == 2)
