@@ -124,46 +124,54 @@ __device__ __forceinline__ void channel_one(
   const uint32_t mu = __builtin_amdgcn_readfirstlane(m32);
   const double2 r = rho[x];
   double2 acc_all = make_double2(p_keep * r.x, p_keep * r.y);
+  // Sum of the coefficients of the hits in flip-mask group g at (n, m).
+  auto group_sum = [&](int g) {
+    const int first = groups[g].first, count = groups[g].count;
+    double2 cs = make_double2(0.0, 0.0);
+    for (int t = first; t < first + count; ++t) {
+      const PermTerm &T = perm[t];
+      double2 c;
+      if (TAB) {
+        const double2 *e = ctab + 8 * t;
+        c = e[((n32 >> T.bit0) & 1u) * 2 + ((m32 >> T.bit0) & 1u)];
+        if (T.nops == 2) c = cmul(c, e[4 + ((n32 >> T.bit1) & 1u) * 2 + ((m32 >> T.bit1) & 1u)]);
+      } else if ((((1u << T.bit0) | (T.nops == 2 ? 1u << T.bit1 : 0u)) & lane_bits) == 0) {
+        // wave-uniform hit
+        c = pick4(T.c0, (int)((nu >> T.bit0) & 1u), (int)((mu >> T.bit0) & 1u));
+        if (T.nops == 2)
+          c = cmul(c, pick4(T.c1, (int)((nu >> T.bit1) & 1u), (int)((mu >> T.bit1) & 1u)));
+      } else {
+        c = pick4(T.c0, (int)((n32 >> T.bit0) & 1u), (int)((m32 >> T.bit0) & 1u));
+        if (T.nops == 2)
+          c = cmul(c, pick4(T.c1, (int)((n32 >> T.bit1) & 1u), (int)((m32 >> T.bit1) & 1u)));
+      }
+      cs.x += c.x;
+      cs.y += c.y;
+    }
+    return cs;
+  };
+  // Groups are sorted by flip mask, so only the first can be flip-free; it
+  // takes rho[x] itself.
+  int gstart = 0;
+  if (ngroups > 0 && groups[0].flip == 0) {
+    acc_all = cmad(acc_all, group_sum(0), r);
+    gstart = 1;
+  }
   // The gathers of kChanBatch flip-mask groups are issued before their
   // coefficients are summed, so several are in flight per thread; the
   // accumulation still runs in group order.
-  for (int g0 = 0; g0 < ngroups; g0 += kChanBatch) {
+  for (int g0 = gstart; g0 < ngroups; g0 += kChanBatch) {
     double2 v[kChanBatch];
 #pragma unroll
     for (int k = 0; k < kChanBatch; ++k) {
-      v[k] = r;
       if (g0 + k < ngroups) {
         const uint32_t flip = (uint32_t)groups[g0 + k].flip;
-        if (flip) v[k] = rho[((uint64_t)(n32 ^ flip) << nq) | (m32 ^ flip)];
+        v[k] = rho[((uint64_t)(n32 ^ flip) << nq) | (m32 ^ flip)];
       }
     }
 #pragma unroll
     for (int k = 0; k < kChanBatch; ++k) {
-      const int g = g0 + k;
-      if (g >= ngroups) continue;
-      const int first = groups[g].first, count = groups[g].count;
-      double2 cs = make_double2(0.0, 0.0);
-      for (int t = first; t < first + count; ++t) {
-        const PermTerm &T = perm[t];
-        double2 c;
-        if (TAB) {
-          const double2 *e = ctab + 8 * t;
-          c = e[((n32 >> T.bit0) & 1u) * 2 + ((m32 >> T.bit0) & 1u)];
-          if (T.nops == 2) c = cmul(c, e[4 + ((n32 >> T.bit1) & 1u) * 2 + ((m32 >> T.bit1) & 1u)]);
-        } else if ((((1u << T.bit0) | (T.nops == 2 ? 1u << T.bit1 : 0u)) & lane_bits) == 0) {
-          // wave-uniform hit
-          c = pick4(T.c0, (int)((nu >> T.bit0) & 1u), (int)((mu >> T.bit0) & 1u));
-          if (T.nops == 2)
-            c = cmul(c, pick4(T.c1, (int)((nu >> T.bit1) & 1u), (int)((mu >> T.bit1) & 1u)));
-        } else {
-          c = pick4(T.c0, (int)((n32 >> T.bit0) & 1u), (int)((m32 >> T.bit0) & 1u));
-          if (T.nops == 2)
-            c = cmul(c, pick4(T.c1, (int)((n32 >> T.bit1) & 1u), (int)((m32 >> T.bit1) & 1u)));
-        }
-        cs.x += c.x;
-        cs.y += c.y;
-      }
-      acc_all = cmad(acc_all, cs, v[k]);
+      if (g0 + k < ngroups) acc_all = cmad(acc_all, group_sum(g0 + k), v[k]);
     }
   }
   for (int t = 0; t < nterms; ++t) {
