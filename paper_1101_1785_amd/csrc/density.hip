@@ -53,6 +53,8 @@ struct PermTerm {
 struct PermGroup {
   uint64_t flip;
   int32_t first, count;
+  int32_t n1;   // hits with one operator; they come first in the group
+  int32_t pad;
 };
 
 // Coefficient tables, built once on the device when a channel is created.
@@ -100,12 +102,12 @@ __device__ __forceinline__ double2 pick4(const double2 (&c)[4], int r, int cc) {
 }
 
 constexpr int kChanBatch = 8;             // flip-mask groups gathered together
-constexpr int kChanTableMaxTerms = 256;   // permutation terms staged in LDS (32 KiB)
+constexpr int kChanTableMaxTerms = 256;   // permutation terms staged in LDS (34 KiB)
 
 // One output element x = n * 2^nq + m of the channel.  With TAB, ctab holds
 // every permutation term's coefficients in LDS (term t: c0 at 8t .. 8t+3, c1
-// at 8t+4 .. 8t+7), and each hit's coefficient is one LDS read at a 2-bit
-// index.  Without it, coefficients are chosen between scalar values: with
+// at 8t+4 .. 8t+7), followed by the terms' bit positions (int2 per term),
+// and each hit's coefficient is one LDS read at a 2-bit index.  Without it, coefficients are chosen between scalar values: with
 // scalar selects when the hit's qubits are the same in every lane, else with
 // vector selects (each of which costs a move as well).
 template <bool TAB>
@@ -113,7 +115,7 @@ __device__ __forceinline__ void channel_one(
     const double2 *__restrict__ rho, double2 *__restrict__ out, int nq, double p_keep,
     const PermGroup *__restrict__ groups, int ngroups, const PermTerm *__restrict__ perm,
     const DevTerm *__restrict__ terms, int nterms, const double2 *__restrict__ coef, uint64_t x,
-    uint32_t lane_bits, const double2 *ctab) {
+    uint32_t lane_bits, const double2 *ctab, int nperm) {
   const uint64_t N = 1ull << nq;
   const uint64_t n = x >> nq, m = x & (N - 1);
   const uint32_t n32 = (uint32_t)n, m32 = (uint32_t)m;  // nq <= kRhoMaxQubits < 32
@@ -128,14 +130,30 @@ __device__ __forceinline__ void channel_one(
   auto group_sum = [&](int g) {
     const int first = groups[g].first, count = groups[g].count;
     double2 cs = make_double2(0.0, 0.0);
+    if (TAB) {
+      // One-operator hits, then two-operator hits; each hit's bit positions
+      // come from the LDS table too, so a hit costs no scalar load.
+      const int2 *dsc = reinterpret_cast<const int2 *>(ctab + 8 * nperm);
+      const int mid = first + groups[g].n1;
+      for (int t = first; t < mid; ++t) {
+        const int b0 = dsc[t].x;
+        const double2 c = ctab[8 * t + ((n32 >> b0) & 1u) * 2 + ((m32 >> b0) & 1u)];
+        cs.x += c.x;
+        cs.y += c.y;
+      }
+      for (int t = mid; t < first + count; ++t) {
+        const int2 b = dsc[t];
+        const double2 c = cmul(ctab[8 * t + ((n32 >> b.x) & 1u) * 2 + ((m32 >> b.x) & 1u)],
+                               ctab[8 * t + 4 + ((n32 >> b.y) & 1u) * 2 + ((m32 >> b.y) & 1u)]);
+        cs.x += c.x;
+        cs.y += c.y;
+      }
+      return cs;
+    }
     for (int t = first; t < first + count; ++t) {
       const PermTerm &T = perm[t];
       double2 c;
-      if (TAB) {
-        const double2 *e = ctab + 8 * t;
-        c = e[((n32 >> T.bit0) & 1u) * 2 + ((m32 >> T.bit0) & 1u)];
-        if (T.nops == 2) c = cmul(c, e[4 + ((n32 >> T.bit1) & 1u) * 2 + ((m32 >> T.bit1) & 1u)]);
-      } else if ((((1u << T.bit0) | (T.nops == 2 ? 1u << T.bit1 : 0u)) & lane_bits) == 0) {
+      if ((((1u << T.bit0) | (T.nops == 2 ? 1u << T.bit1 : 0u)) & lane_bits) == 0) {
         // wave-uniform hit
         c = pick4(T.c0, (int)((nu >> T.bit0) & 1u), (int)((mu >> T.bit0) & 1u));
         if (T.nops == 2)
@@ -264,6 +282,8 @@ __global__ __launch_bounds__(kChanThreads) void channel_kernel(
       const PermTerm &T = perm[e >> 3];
       ctab[e] = (e & 4) ? T.c1[e & 3] : T.c0[e & 3];
     }
+    int2 *dsc = reinterpret_cast<int2 *>(ctab + 8 * nperm);
+    for (int t = threadIdx.x; t < nperm; t += kChanThreads) dsc[t] = make_int2(perm[t].bit0, perm[t].bit1);
     __syncthreads();
   }
   const uint64_t NN = 1ull << (2 * nq);
@@ -271,7 +291,7 @@ __global__ __launch_bounds__(kChanThreads) void channel_kernel(
   for (uint64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     if (vb * kChanThreads + threadIdx.x >= NN) continue;
     channel_one<TAB>(rho, out, nq, p_keep, groups, ngroups, perm, terms, nterms, coef,
-                     channel_element(vb, nq), channel_lane_bits(nq), ctab);
+                     channel_element(vb, nq), channel_lane_bits(nq), ctab, nperm);
   }
 }
 
@@ -473,20 +493,23 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
       dt.push_back(d);
     }
   }
-  // Group the permutation terms by flip mask (stable: equal masks keep input order).
+  // Group the permutation terms by flip mask, one-operator hits first in
+  // each group (stable: otherwise input order).
   std::stable_sort(pt.begin(), pt.end(),
                    [](const std::pair<uint64_t, PermTerm> &a, const std::pair<uint64_t, PermTerm> &b) {
-                     return a.first < b.first;
+                     if (a.first != b.first) return a.first < b.first;
+                     return a.second.nops < b.second.nops;
                    });
   std::vector<PermGroup> groups;
   std::vector<PermTerm> perm;
   int64_t flops = 2;  // p_keep * rho
   for (size_t i = 0; i < pt.size(); ++i) {
     if (groups.empty() || groups.back().flip != pt[i].first) {
-      groups.push_back(PermGroup{pt[i].first, (int32_t)i, 0});
+      groups.push_back(PermGroup{pt[i].first, (int32_t)i, 0, 0, 0});
       flops += 8;  // one complex multiply-add per group
     }
     ++groups.back().count;
+    if (pt[i].second.nops == 1) ++groups.back().n1;
     perm.push_back(pt[i].second);
     flops += pt[i].second.nops == 1 ? 2 : 8;  // sum of the coefficient (and its product)
   }
@@ -551,7 +574,8 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   double2 *o = reinterpret_cast<double2 *>(rho_out);
   if (c->nperm > 0 && c->nperm <= kChanTableMaxTerms)
     hipLaunchKernelGGL(channel_kernel<true>, dim3(blocks), dim3(kChanThreads),
-                       sizeof(double2) * 8 * c->nperm, (hipStream_t)stream, in, o, c->nq, c->p_keep,
+                       (sizeof(double2) * 8 + sizeof(int) * 2) * c->nperm, (hipStream_t)stream, in,
+                       o, c->nq, c->p_keep,
                        c->groups_d, c->ngroups, c->perm_d, c->nperm, c->terms_d, c->nterms, c->coef_d);
   else
     hipLaunchKernelGGL(channel_kernel<false>, dim3(blocks), dim3(kChanThreads), 0,
