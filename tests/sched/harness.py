@@ -30,10 +30,13 @@ def build():
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     srcs = [os.path.join(CSRC, "server_core.cpp"), os.path.join(CSRC, "common.cpp"),
             os.path.join(HERE, "sched_harness.cpp")]
+    # A temporary name per process: parallel test workers may build at once,
+    # and each then renames its own complete file into place.
+    tmp = f"{OUT}.{os.getpid()}.tmp"
     cmd = ["g++", "-O1", "-g", "-std=c++17", "-shared", "-fPIC", "-pthread",
-           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", "-o", OUT + ".tmp", *srcs]
+           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", "-o", tmp, *srcs]
     subprocess.check_call(cmd)
-    os.replace(OUT + ".tmp", OUT)
+    os.replace(tmp, OUT)
     return OUT
 
 
