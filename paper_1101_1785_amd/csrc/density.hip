@@ -102,12 +102,22 @@ __device__ __forceinline__ double2 pick4(const double2 (&c)[4], int r, int cc) {
 }
 
 constexpr int kChanBatch = 8;             // flip-mask groups gathered together
+constexpr int kChanTableMaxQubits = 16;   // the interleaved row/column index fits 32 bits
+
+// Bit b of x (b < 16) moved to bit 2b.
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
 constexpr int kChanTableMaxTerms = 256;   // permutation terms staged in LDS (34 KiB)
 
 // One output element x = n * 2^nq + m of the channel.  With TAB, ctab holds
 // every permutation term's coefficients in LDS (term t: c0 at 8t .. 8t+3, c1
-// at 8t+4 .. 8t+7), followed by the terms' bit positions (int2 per term),
-// and each hit's coefficient is one LDS read at a 2-bit index.  Without it, coefficients are chosen between scalar values: with
+// at 8t+4 .. 8t+7), followed by the terms' doubled bit positions (int2 per
+// term), and each hit's coefficient is one LDS read at a 2-bit index.  Without it, coefficients are chosen between scalar values: with
 // scalar selects when the hit's qubits are the same in every lane, else with
 // vector selects (each of which costs a move as well).
 template <bool TAB>
@@ -126,25 +136,27 @@ __device__ __forceinline__ void channel_one(
   const uint32_t mu = __builtin_amdgcn_readfirstlane(m32);
   const double2 r = rho[x];
   double2 acc_all = make_double2(p_keep * r.x, p_keep * r.y);
+  // With TAB (nq <= 16): bits 2b+1 and 2b of nm are bit b of n and of m, so
+  // (nm >> 2b) & 3 indexes a hit's coefficient table at its qubit bit b.
+  const uint32_t nm = TAB ? (spread16(n32) << 1) | spread16(m32) : 0u;
   // Sum of the coefficients of the hits in flip-mask group g at (n, m).
   auto group_sum = [&](int g) {
     const int first = groups[g].first, count = groups[g].count;
     double2 cs = make_double2(0.0, 0.0);
     if (TAB) {
       // One-operator hits, then two-operator hits; each hit's bit positions
-      // come from the LDS table too, so a hit costs no scalar load.
+      // (doubled, as shifts into nm) come from the LDS table too, so a hit
+      // costs no scalar load, and its 2-bit index is one bit-field extract.
       const int2 *dsc = reinterpret_cast<const int2 *>(ctab + 8 * nperm);
       const int mid = first + groups[g].n1;
       for (int t = first; t < mid; ++t) {
-        const int b0 = dsc[t].x;
-        const double2 c = ctab[8 * t + ((n32 >> b0) & 1u) * 2 + ((m32 >> b0) & 1u)];
+        const double2 c = ctab[8 * t + ((nm >> dsc[t].x) & 3u)];
         cs.x += c.x;
         cs.y += c.y;
       }
       for (int t = mid; t < first + count; ++t) {
         const int2 b = dsc[t];
-        const double2 c = cmul(ctab[8 * t + ((n32 >> b.x) & 1u) * 2 + ((m32 >> b.x) & 1u)],
-                               ctab[8 * t + 4 + ((n32 >> b.y) & 1u) * 2 + ((m32 >> b.y) & 1u)]);
+        const double2 c = cmul(ctab[8 * t + ((nm >> b.x) & 3u)], ctab[8 * t + 4 + ((nm >> b.y) & 3u)]);
         cs.x += c.x;
         cs.y += c.y;
       }
@@ -283,7 +295,8 @@ __global__ __launch_bounds__(kChanThreads) void channel_kernel(
       ctab[e] = (e & 4) ? T.c1[e & 3] : T.c0[e & 3];
     }
     int2 *dsc = reinterpret_cast<int2 *>(ctab + 8 * nperm);
-    for (int t = threadIdx.x; t < nperm; t += kChanThreads) dsc[t] = make_int2(perm[t].bit0, perm[t].bit1);
+    for (int t = threadIdx.x; t < nperm; t += kChanThreads)
+      dsc[t] = make_int2(2 * perm[t].bit0, 2 * perm[t].bit1);
     __syncthreads();
   }
   const uint64_t NN = 1ull << (2 * nq);
@@ -572,7 +585,7 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
   const double2 *in = reinterpret_cast<const double2 *>(rho_in);
   double2 *o = reinterpret_cast<double2 *>(rho_out);
-  if (c->nperm > 0 && c->nperm <= kChanTableMaxTerms)
+  if (c->nperm > 0 && c->nperm <= kChanTableMaxTerms && c->nq <= kChanTableMaxQubits)
     hipLaunchKernelGGL(channel_kernel<true>, dim3(blocks), dim3(kChanThreads),
                        (sizeof(double2) * 8 + sizeof(int) * 2) * c->nperm, (hipStream_t)stream, in,
                        o, c->nq, c->p_keep,
