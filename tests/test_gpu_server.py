@@ -196,3 +196,21 @@ def test_staging_overflow_and_direct_upload(L):
         L.qcw_circuit(psi, 11, g, len(g), m, m.size)
         torch.cuda.synchronize()
         assert np.array_equal(psi.cpu().numpy(), out), i
+
+
+def test_native_load_generator(L):
+    """The native open-loop client (serve_load, built beside the library)
+    drives the server with Poisson arrivals from two threads and collects
+    every result: all requests complete, latencies are positive."""
+    import os
+    import bench
+    exe = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1101_1785_amd", "serve_load")
+    if not os.path.exists(exe):
+        pytest.skip("serve_load not built")
+    print("[gpu] native load generator, 2000 req/s for 0.3 s", flush=True)
+    r = bench.bench_serving_native(L, qi, None, 0.3, rates=(2000,), pool=64)
+    (row,) = r["server"]
+    assert "error" not in row, row
+    assert row["requests"] > 300 and row["failed"] == 0
+    assert 0 < row["p50_ms"] <= row["p99_ms"]
