@@ -22,6 +22,8 @@ instances) and served (open-loop Poisson) forms.
 (the sweep for k = 1, 2, 3, once more on the three lowest qubits, and one fused
 solve),
 for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; it prints what it launched.
+--section NAME runs one of the extra sections alone (e.g. multiverse_nq12) and
+prints its JSON object, for profiling that section's kernels.
 """
 from __future__ import annotations
 
@@ -68,6 +70,8 @@ def _args():
                         "kernel trace holds only the timed launches")
     p.add_argument("--skip-extra", action="store_true",
                    help="only the headline workload (no batched/serving sections)")
+    p.add_argument("--section", default="",
+                   help="run one of the extra sections alone and print its JSON (for profiling)")
     p.add_argument("--counters", action="store_true",
                    help="launch each kernel once at nq=28 next to a 2 GiB copy, then exit")
     p.add_argument("--tune-table", default=os.path.join(ROOT, "paper_1101_1785_amd", "tune",
@@ -730,6 +734,34 @@ def counters_run(torch, L, qi):
         "fused_bytes_per_pass": 32 * N, "nq": nq}}), flush=True)
 
 
+def extra_sections(torch, L, qi, a):
+    """The sections reported beside the headline, in report order (name -> run)."""
+    tt = a.tune_table if a.tune_table and os.path.exists(a.tune_table) else None
+    secs = {
+        "batched_config2": lambda: bench_batched(torch, L, qi, 2, 4096, 3, 7, tt,
+                                                 label="4096 x nq 3..7"),
+        "batched_config4": lambda: bench_batched(torch, L, qi, 4, 4096, 9, 9, tt,
+                                                 label="4096 x nq 9"),
+        "config0_plain_nq3": lambda: bench_config0(torch, L, qi),
+        "sweeps_config1": lambda: bench_sweeps(torch, L, qi),
+        "plain_nq9": lambda: bench_plain_small(torch, L, qi, 9, 1),
+        "grover_n6": lambda: bench_grover(torch, L, qi, tt),
+        "shard_nq32": lambda: bench_shard(torch, L, qi),
+        "multiverse_nq12": lambda: bench_multiverse(torch, L, qi, 12, 5),
+        "multiverse_nq5": lambda: bench_multiverse(torch, L, qi, 5, 5, steps=200),
+        "multiverse_nq5_rotation_noise": lambda: bench_multiverse(torch, L, qi, 5, 6, steps=200,
+                                                                  noise="rotation"),
+        "serving_config3": lambda: bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9,
+                                                 tt),
+    }
+    if a.serve_sweep_seconds > 0:
+        secs["serving_rate_sweep"] = lambda: bench_serving_sweep(torch, L, qi, tt,
+                                                                 a.serve_sweep_seconds)
+        secs["serving_native_sweep"] = lambda: bench_serving_native(L, qi, tt,
+                                                                    a.serve_sweep_seconds)
+    return secs
+
+
 def main():
     a = _args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -745,6 +777,15 @@ def main():
 
     if a.counters:
         counters_run(torch, L, qi)
+        return
+    if a.section:
+        # One section alone (for profiling it): its JSON object, not the
+        # headline record.
+        secs = extra_sections(torch, L, qi, a)
+        if a.section not in secs:
+            print(f"unknown section {a.section!r}; one of: {', '.join(secs)}", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({a.section: secs[a.section]()}))
         return
 
     nq = a.nq
@@ -841,26 +882,8 @@ def main():
 
     extra = {}
     if not a.skip_extra:
-        tt = a.tune_table if a.tune_table and os.path.exists(a.tune_table) else None
-        extra["batched_config2"] = bench_batched(torch, L, qi, 2, 4096, 3, 7, tt,
-                                                 label="4096 x nq 3..7")
-        extra["batched_config4"] = bench_batched(torch, L, qi, 4, 4096, 9, 9, tt,
-                                                 label="4096 x nq 9")
-        extra["config0_plain_nq3"] = bench_config0(torch, L, qi)
-        extra["sweeps_config1"] = bench_sweeps(torch, L, qi)
-        extra["plain_nq9"] = bench_plain_small(torch, L, qi, 9, 1)
-        extra["grover_n6"] = bench_grover(torch, L, qi, tt)
-        extra["shard_nq32"] = bench_shard(torch, L, qi)
-        extra["multiverse_nq12"] = bench_multiverse(torch, L, qi, 12, 5)
-        extra["multiverse_nq5"] = bench_multiverse(torch, L, qi, 5, 5, steps=200)
-        extra["multiverse_nq5_rotation_noise"] = bench_multiverse(torch, L, qi, 5, 6, steps=200,
-                                                                  noise="rotation")
-        extra["serving_config3"] = bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9, tt)
-        if a.serve_sweep_seconds > 0:
-            extra["serving_rate_sweep"] = bench_serving_sweep(torch, L, qi, tt,
-                                                              a.serve_sweep_seconds)
-            extra["serving_native_sweep"] = bench_serving_native(L, qi, tt,
-                                                                 a.serve_sweep_seconds)
+        for name, fn in extra_sections(torch, L, qi, a).items():
+            extra[name] = fn()
 
     out = {
         "metric": METRIC,
