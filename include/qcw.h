@@ -196,6 +196,29 @@ int qcw_fused_plan(int nq, const qcw_gate *gates, int ngates, int tile_bits, int
                    int plan, int *pass_of, int *order);
 
 /*
+ * Test only (host code; no GPU is touched): the pass plan that
+ * qcw_circuit_fused_ex would upload for this request (nq >= 9), as the device
+ * tables hold it.  Pass p (p < *npass <= pass_cap): pass_hdr[4p .. 4p+3] =
+ * {first gate in the gate table, gate count, tile bits T, low bits L};
+ * outer_pos[40p + j] = the label bit of bit j of the block index (j < nq - T;
+ * -1 beyond); chunk_off[1024p + c] = the label offset of chunk c of the tile
+ * (c < 2^(T-L)).  The kernels give the amplitude of local index i (0 <= i <
+ * 2^T) in the tile of block b the label
+ *   sum_j bit_j(b) 2^outer_pos[j] + chunk_off[i >> L] + (i & (2^L - 1)).
+ * Gate g (g < *ngate <= gate_cap): gate_hdr[13g .. 13g+12] = {k, sb0, sb1,
+ * sb2 (local target bits, ascending), m3 (1: the three-product form), off[0..7]
+ * (local member offsets, local index order)}; gate_mat[64g ...] its m x m
+ * matrix row-major (with m3, the pairs (Re U, -(Re U + Im U))).  All arrays
+ * are caller-owned host memory.  Returns QCW_OK or QCW_EINVAL (also when a cap
+ * is too small; *npass and *ngate then hold the sizes needed).
+ */
+int qcw_debug_fused_tables(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
+                           int64_t nmats, int tile_bits, int low_bits, int plan, int pass_cap,
+                           int gate_cap, int32_t *pass_hdr, int32_t *outer_pos,
+                           uint64_t *chunk_off, int32_t *gate_hdr, qcw_c64 *gate_mat,
+                           int *npass, int *ngate);
+
+/*
  * One GPU's part of a gate on a state split over two GPUs by qubit 1 (the most
  * significant bit, §2c), the distribution of the paper's MPI predecessor (§5,
  * general remarks).  The full state has nq qubits (2 <= nq <= 34); this GPU's
@@ -365,22 +388,52 @@ int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
 
 /*
- * Eigenvalue-based observables (§5, classical-limit discussion), for
- * nq <= 6 (a 64 x 64 rho, the paper's examples use 1, 2 and 5 qubits), by a
- * parallel cyclic Jacobi eigensolver in one workgroup.  Both calls are
- * synchronous and take the Hermitian part (rho + rho^dagger) / 2.
+ * Eigenvalue-based observables (§5, classical-limit discussion: the paper
+ * follows entropy, purity, fidelity and the eigenvalues of rho at every stage),
+ * for nq <= 6 (a 64 x 64 rho; the paper's examples use 1, 2 and 5 qubits), by
+ * a parallel cyclic Jacobi eigensolver, one workgroup per matrix with the
+ * matrix in LDS.  Every call takes the Hermitian part (rho + rho^dagger) / 2.
  *
- * qcw_rho_eigvals writes 2^nq + 1 doubles to out_host: the eigenvalues in
- * ascending order, then the von Neumann entropy -sum lambda log2 lambda in
- * bits (over lambda > 0; in the classical limit it tends to nq).  The paper
- * writes S = -Tr rho ln rho; its value in nats is the bits value times ln 2.
- * qcw_rho_fidelity writes F = Tr sqrt(sqrt(rho0) rho sqrt(rho0)) (the root
- * fidelity, 1/sqrt2 after one Hadamard on |0>) for a general rho0.
+ * qcw_rho_eigvals_batch: `count` matrices, matrix i at rho + i * stride
+ * (device, stride >= 4^nq elements); writes the eigenvalues of matrix i in
+ * ascending order to eig[i * 2^nq ...] (device, count * 2^nq doubles) and the
+ * von Neumann entropy -sum lambda log2 lambda in bits (over lambda > 0; it
+ * tends to nq in the classical limit; the paper writes S = -Tr rho ln rho, and
+ * the value in nats is the bits value times ln 2) to entropy[i] (device, count
+ * doubles, or NULL).  One persistent launch on `stream`: asynchronous, no
+ * device memory allocated, no synchronisation.  Eigenvalues agree with a
+ * Hermitian LAPACK solver to ~1e-15 (absolute, trace-one rho).
+ *
+ * qcw_rho_fidelity_batch: F_i = Tr sqrt(sqrt(rho0_i) rho_i sqrt(rho0_i)), the
+ * root fidelity (1/sqrt2 after one Hadamard on |0>, §5), for pairs rho_i =
+ * rho + i * rho_stride, rho0_i = rho0 + i * rho0_stride (rho0_stride = 0: one
+ * reference for all); fidelity: device, count doubles.  Asynchronous, no
+ * allocation.  It is evaluated on the range of rho0: with rho0's eigenvalues
+ * l above n * eps * l_max and their eigenvectors V_r, F = Tr sqrt(K) for the
+ * r x r matrix K = diag(sqrt l) V_r^dagger rho V_r diag(sqrt l), whose nonzero
+ * eigenvalues are those of sqrt(rho0) rho sqrt(rho0); eigenvalues of K at or
+ * below r * eps * max(K) are taken as zero.  A pure reference gives r = 1 and
+ * F = sqrt(<psi0|rho|psi0>).  Accuracy ~1e-15 when K's eigenvalues are
+ * either rounding-level or well above it; the definition itself is
+ * ill-conditioned at rank-deficient inputs (the square root of an eigenvalue
+ * d moves by d / (2 sqrt d)), so an input perturbed at the rounding level
+ * can move F by ~sqrt(eps) ~ 1e-8 through eigenvalues just above the cut.
+ *
+ * qcw_rho_eigvals and qcw_rho_fidelity are the same for one matrix with host
+ * outputs (synchronous): qcw_rho_eigvals writes 2^nq + 1 doubles to out_host
+ * (the eigenvalues ascending, then the entropy in bits); qcw_rho_fidelity
+ * writes F.  They share a small device buffer per device, allocated on first
+ * use and kept, and serialise on it.
  * qcw_rho_partial_trace (asynchronous) writes the reduced density matrix of
  * the nkeep qubits keep[] (1-based, distinct) to the device array out
  * (2^nkeep x 2^nkeep, the lowest-numbered kept qubit most significant), for
  * subsystem entropies and eigenvalues.
  */
+int qcw_rho_eigvals_batch(const qcw_c64 *rho, int nq, int64_t count, int64_t stride, double *eig,
+                          double *entropy, void *stream);
+int qcw_rho_fidelity_batch(const qcw_c64 *rho, int64_t rho_stride, const qcw_c64 *rho0,
+                           int64_t rho0_stride, int nq, int64_t count, double *fidelity,
+                           void *stream);
 int qcw_rho_eigvals(const qcw_c64 *rho, int nq, double *out_host, void *stream);
 int qcw_rho_fidelity(const qcw_c64 *rho, const qcw_c64 *rho0, int nq, double *out_host,
                      void *stream);

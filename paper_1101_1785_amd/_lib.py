@@ -70,6 +70,8 @@ _SIGS = {
     "qcw_fused_pass_count": ([_i32, _P, _i32, _i32, _i32, _i32], _i32),
     "qcw_fused_plan": ([_i32, _P, _i32, _i32, _i32, _i32, _P, _P], _i32),
     "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),
+    "qcw_debug_fused_tables": ([_i32, _P, _i32, _P, _i64, _i32, _i32, _i32, _i32, _i32, _P, _P,
+                                _P, _P, _P, _P, _P], _i32),
     "qcw_op_shard": ([_i32, _P, _P, _i32, _P, _P, _i32, _P], _i32),
     "qcw_batch_create": ([_P, _P, _i32, _P, _i64, _P, _i64, _P, _i64, ctypes.c_char_p, _P], _i32),
     "qcw_batch_run": ([_P, _P], _i32),
@@ -86,6 +88,8 @@ _SIGS = {
     "qcw_channel_flops_per_element": ([_P], _i64),
     "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_rho_eigvals": ([_P, _i32, _P, _P], _i32),
+    "qcw_rho_eigvals_batch": ([_P, _i32, _i64, _i64, _P, _P, _P], _i32),
+    "qcw_rho_fidelity_batch": ([_P, _i64, _P, _i64, _i32, _i64, _P, _P], _i32),
     "qcw_rho_fidelity": ([_P, _P, _i32, _P, _P], _i32),
     "qcw_rho_partial_trace": ([_P, _i32, _P, _i32, _P, _P], _i32),
     "qcw_server_create": ([_P, _P], _i32),
@@ -276,6 +280,48 @@ def qcw_fused_plan(nq, gates, ngates, tile_bits=0, low_bits=0, plan=0):
     if n < 0:
         raise QcwError(n, "qcw_fused_plan")
     return n, pass_of[:ngates], order[:ngates]
+
+
+def qcw_debug_fused_tables(nq, gates, ngates, mats, tile_bits=0, low_bits=0, plan=0):
+    """The fused pass plan's device tables (host call): a dict with per-pass
+    gate_off, ngates, T, L, outer_pos (list per pass), chunk_off (array per
+    pass, 2^(T-L) entries) and per-gate k, sb (3), m3, off (8), u (m x m)."""
+    cap_p, cap_g = 8, 8
+    while True:
+        ph = np.zeros(4 * cap_p, dtype=np.int32)
+        op = np.zeros(40 * cap_p, dtype=np.int32)
+        co = np.zeros(1024 * cap_p, dtype=np.uint64)
+        gh = np.zeros(13 * cap_g, dtype=np.int32)
+        gm = np.zeros(64 * cap_g, dtype=np.complex128)
+        npass, ngate = ctypes.c_int(0), ctypes.c_int(0)
+        rc = _L.qcw_debug_fused_tables(int(nq), _hptr(gates), int(ngates), _hptr(mats),
+                                       int(mats.size), int(tile_bits), int(low_bits), int(plan),
+                                       cap_p, cap_g, _hptr(ph), _hptr(op), _hptr(co), _hptr(gh),
+                                       _hptr(gm), ctypes.byref(npass), ctypes.byref(ngate))
+        if rc == QCW_OK:
+            break
+        if npass.value > cap_p or ngate.value > cap_g:
+            cap_p, cap_g = max(cap_p, npass.value), max(cap_g, ngate.value)
+            continue
+        _check(rc, "qcw_debug_fused_tables")
+    P, G = npass.value, ngate.value
+    ph = ph.reshape(-1, 4)[:P]
+    passes = []
+    for p in range(P):
+        T, Lb = int(ph[p, 2]), int(ph[p, 3])
+        outer = [int(x) for x in op[40 * p:40 * p + 40] if x >= 0]
+        passes.append({"gate_off": int(ph[p, 0]), "ngates": int(ph[p, 1]), "T": T, "L": Lb,
+                       "outer_pos": outer,
+                       "chunk_off": co[1024 * p:1024 * p + (1 << (T - Lb))].copy()})
+    gates_out = []
+    for g in range(G):
+        h = gh[13 * g:13 * g + 13]
+        k = int(h[0])
+        m = 1 << k
+        gates_out.append({"k": k, "sb": [int(x) for x in h[1:4]], "m3": int(h[4]),
+                          "off": [int(x) for x in h[5:13]],
+                          "u": gm[64 * g:64 * g + m * m].reshape(m, m).copy()})
+    return {"passes": passes, "gates": gates_out}
 
 
 def qcw_debug_pick_device(nq, targets):
@@ -618,6 +664,51 @@ def qcw_rho_fidelity(rho, rho0, nq=None, stream=None):
     _check(_L.qcw_rho_fidelity(_dptr(rho), _dptr(rho0), nq, _hptr(out), _stream(stream)),
            "qcw_rho_fidelity")
     return float(out[0])
+
+
+def _dptr_f64(t):
+    """Device pointer of a contiguous torch float64 GPU tensor (or None)."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda \
+            or not t.is_contiguous():
+        raise TypeError("output must be a contiguous torch.float64 tensor on the GPU")
+    return t.data_ptr()
+
+
+def qcw_rho_eigvals_batch(rho, nq, count, stride=None, eig=None, entropy=None, stream=None):
+    """Eigenvalues (count x 2^nq, ascending) and entropies in bits (count) of
+    `count` density matrices, matrix i at element i * stride of the complex128
+    device tensor rho; outputs are float64 device tensors (allocated here when
+    not given).  Asynchronous on the stream.  Returns (eig, entropy)."""
+    import torch
+    n = 1 << nq
+    stride = n * n if stride is None else stride
+    if eig is None:
+        eig = torch.empty((count, n), dtype=torch.float64, device=rho.device)
+    if entropy is None:
+        entropy = torch.empty(count, dtype=torch.float64, device=rho.device)
+    _check(_L.qcw_rho_eigvals_batch(_dptr(rho), nq, count, stride, _dptr_f64(eig),
+                                    _dptr_f64(entropy), _stream(stream)),
+           "qcw_rho_eigvals_batch")
+    return eig, entropy
+
+
+def qcw_rho_fidelity_batch(rho, rho0, nq, count, rho_stride=None, rho0_stride=None, out=None,
+                           stream=None):
+    """Fidelities of `count` pairs (rho_i, rho0_i); rho0_stride = 0 compares
+    every rho_i with one reference.  Asynchronous; returns the float64 device
+    tensor of count values."""
+    import torch
+    nn = 1 << (2 * nq)
+    rho_stride = nn if rho_stride is None else rho_stride
+    rho0_stride = nn if rho0_stride is None else rho0_stride
+    if out is None:
+        out = torch.empty(count, dtype=torch.float64, device=rho.device)
+    _check(_L.qcw_rho_fidelity_batch(_dptr(rho), rho_stride, _dptr(rho0), rho0_stride, nq, count,
+                                     _dptr_f64(out), _stream(stream)), "qcw_rho_fidelity_batch")
+    return out
 
 
 def qcw_rho_partial_trace(rho, keep, nq=None, stream=None):

@@ -257,24 +257,145 @@ def test_classical_limit_on_gpu(L):
     ch.close()
 
 
-@pytest.mark.parametrize("nq", [1, 2, 4, 6])
+# Fidelity bar.  Full-rank pairs: 1e-12 against the oracle (the definition
+# written out with numpy's Hermitian solver).  Rank-deficient inputs (pure
+# states): the oracle's square roots of rounding-level eigenvalues add ~1e-8
+# each, so those cases are checked against closed forms instead, at 1e-12:
+# F(rho, |psi0><psi0|) = sqrt(<psi0|rho|psi0>), and by the symmetry of F,
+# F(|psi><psi|, rho0) = sqrt(<psi|rho0|psi>); F(rho, rho) = 1.
+FID_TOL = 1e-12
+
+
+@pytest.mark.parametrize("nq", [1, 2, 4, 5, 6])
 def test_general_fidelity(L, nq):
     rng = np.random.default_rng(60 + nq)
     full = 1 << nq
     r, r0 = _rand_rho(rng, nq, full), _rand_rho(rng, nq, full)
-    assert abs(L.qcw_rho_fidelity(dev(r), dev(r0)) - D.fidelity_general(r, r0)) <= 1e-12
-    # pure reference: the closed form sqrt(<psi0|rho|psi0>) (tiny eigenvalues of
-    # sqrt(rho0) rho sqrt(rho0) lose digits under the square root: 1e-6)
+    assert abs(L.qcw_rho_fidelity(dev(r), dev(r0)) - D.fidelity_general(r, r0)) <= FID_TOL
+    # pure reference (the paper's case: fidelity against the initial state)
     psi0 = qi.state(3, nq)
     f = L.qcw_rho_fidelity(dev(r), dev(D.pure(psi0)))
-    assert abs(f - D.observables(r, psi0)["fidelity"]) <= 1e-6
-    assert abs(L.qcw_rho_fidelity(dev(r), dev(r)) - 1.0) <= 1e-6
+    assert abs(f - D.observables(r, psi0)["fidelity"]) <= FID_TOL
+    # pure state against a mixed reference
+    psi = qi.state(4, nq)
+    g = L.qcw_rho_fidelity(dev(D.pure(psi)), dev(r0))
+    assert abs(g - np.sqrt(np.real(psi.conj() @ r0 @ psi))) <= FID_TOL
+    # a state against itself: full rank, rank 3, pure
+    for x in (r, _rand_rho(rng, nq, min(3, full)), D.pure(psi)):
+        assert abs(L.qcw_rho_fidelity(dev(x), dev(x)) - 1.0) <= FID_TOL
 
 
 def test_fidelity_after_one_hadamard_general(L):
+    """§5, MV1-Noise: 1/sqrt2 after one H, through the general (mixed-reference) path."""
     psi0 = qi.basis_state(1, 0)
     rho = D.conjugate(D.pure(psi0), qi.H, (1,))
-    assert abs(L.qcw_rho_fidelity(dev(rho), dev(D.pure(psi0))) - 2 ** -0.5) <= 1e-7
+    assert abs(L.qcw_rho_fidelity(dev(rho), dev(D.pure(psi0))) - 2 ** -0.5) <= 4e-16
+
+
+def test_fidelity_orthogonal_and_mixed_limits(L):
+    """F = 0 for orthogonal pure states; against the maximally mixed reference
+    F = Tr sqrt(rho) / sqrt(n), i.e. sum sqrt(lambda) / sqrt(n)."""
+    nq = 3
+    a, b = qi.basis_state(nq, 0), qi.basis_state(nq, 5)
+    assert abs(L.qcw_rho_fidelity(dev(D.pure(a)), dev(D.pure(b)))) <= FID_TOL
+    rng = np.random.default_rng(61)
+    r = _rand_rho(rng, nq, 8)
+    lam = np.linalg.eigvalsh(r)
+    ref = np.sum(np.sqrt(lam)) / np.sqrt(8)
+    assert abs(L.qcw_rho_fidelity(dev(r), dev(np.eye(8) / 8)) - ref) <= FID_TOL
+
+
+# ------------------------------------------------------------------ batched eigensolver
+def _rho_batch(rng, nq, count):
+    """count density matrices of nq qubits with ranks cycling over 1, 2, 3 and full."""
+    ranks = [1, 2, 3, 1 << nq]
+    return [_rand_rho(rng, nq, min(ranks[i % 4], 1 << nq)) for i in range(count)]
+
+
+@pytest.mark.parametrize("nq,count", [(1, 5), (2, 33), (3, 300), (4, 257), (5, 600), (6, 1100)])
+def test_eigvals_batch_against_lapack(L, nq, count):
+    """Every matrix of one persistent launch (more matrices than resident
+    blocks at nq = 6, so blocks take several) against numpy's Hermitian
+    solver: eigenvalues and entropy within 1e-12; matrices spaced by a stride
+    above 4^nq (the gaps are never read as matrix data)."""
+    rng = np.random.default_rng(300 + nq)
+    n = 1 << nq
+    rhos = _rho_batch(rng, nq, count)
+    stride = n * n + 7
+    flat = np.full(count * stride, np.nan + 1j * np.nan, dtype=np.complex128)
+    for i, r in enumerate(rhos):
+        flat[i * stride:i * stride + n * n] = r.reshape(-1)
+    ev, S = L.qcw_rho_eigvals_batch(dev(flat), nq, count, stride)
+    torch.cuda.synchronize()
+    ev, S = ev.cpu().numpy(), S.cpu().numpy()
+    for i, r in enumerate(rhos):
+        ref = D.eigen_observables(r)
+        assert np.max(np.abs(ev[i] - ref["eigenvalues"])) <= 1e-12, i
+        assert abs(S[i] - ref["entropy_bits"]) <= 1e-12, i
+        assert np.all(np.diff(ev[i]) >= 0)
+
+
+def test_eigvals_batch_equals_single_calls(L):
+    """The synchronous one-matrix call runs the same kernel: same bits."""
+    rng = np.random.default_rng(310)
+    nq = 5
+    rhos = _rho_batch(rng, nq, 12)
+    ev, S = L.qcw_rho_eigvals_batch(dev(np.stack(rhos)), nq, len(rhos))
+    torch.cuda.synchronize()
+    ev, S = ev.cpu().numpy(), S.cpu().numpy()
+    for i, r in enumerate(rhos):
+        e1, s1 = L.qcw_rho_eigvals(dev(r))
+        assert np.array_equal(e1, ev[i]) and s1 == S[i]
+
+
+def test_eigvals_batch_classical_limit_and_pure(L):
+    """Closed forms: the maximally mixed state has every eigenvalue 1/n and
+    entropy nq bits; a pure state has eigenvalues {0, ..., 0, 1} and entropy 0."""
+    nq = 6
+    n = 1 << nq
+    psi = qi.state(5, nq)
+    ev, S = L.qcw_rho_eigvals_batch(dev(np.stack([np.eye(n) / n, D.pure(psi)])), nq, 2)
+    torch.cuda.synchronize()
+    ev, S = ev.cpu().numpy(), S.cpu().numpy()
+    assert np.max(np.abs(ev[0] - 1 / n)) <= 1e-15 and abs(S[0] - nq) <= 1e-13
+    assert np.max(np.abs(ev[1] - np.r_[np.zeros(n - 1), 1.0])) <= 1e-14 and abs(S[1]) <= 1e-12
+
+
+@pytest.mark.parametrize("nq,count", [(2, 40), (5, 300), (6, 520)])
+def test_fidelity_batch(L, nq, count):
+    """Pairs (full-rank rho_i, full-rank rho0_i) against the oracle, and one
+    shared pure reference (rho0 stride 0) against the closed form."""
+    rng = np.random.default_rng(320 + nq)
+    n = 1 << nq
+    rs = [_rand_rho(rng, nq, n) for _ in range(count)]
+    r0s = [_rand_rho(rng, nq, n) for _ in range(count)]
+    F = L.qcw_rho_fidelity_batch(dev(np.stack(rs)), dev(np.stack(r0s)), nq, count)
+    psi0 = qi.state(6, nq)
+    Fp = L.qcw_rho_fidelity_batch(dev(np.stack(rs)), dev(D.pure(psi0)), nq, count, rho0_stride=0)
+    torch.cuda.synchronize()
+    F, Fp = F.cpu().numpy(), Fp.cpu().numpy()
+    for i in range(count):
+        assert abs(F[i] - D.fidelity_general(rs[i], r0s[i])) <= FID_TOL, i
+        assert abs(Fp[i] - D.observables(rs[i], psi0)["fidelity"]) <= FID_TOL, i
+    # the one-pair call runs the same kernel
+    assert L.qcw_rho_fidelity(dev(rs[3]), dev(r0s[3])) == F[3]
+
+
+def test_eigen_batch_validation(L):
+    nq, n = 3, 8
+    rho = dev(np.stack([np.eye(n) / n] * 4))
+    eig = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(L.QcwError):     # stride below 4^nq
+        L.qcw_rho_eigvals_batch(rho, nq, 4, n * n - 1, eig)
+    # negative count (through the C call: the binding would not allocate for it)
+    assert L.lib().qcw_rho_eigvals_batch(rho.data_ptr(), nq, -1, n * n, eig.data_ptr(), None,
+                                         None) == L.QCW_EINVAL
+    with pytest.raises(L.QcwError):     # nq above 6
+        L.qcw_rho_eigvals_batch(dev(np.zeros(1 << 14)), 7, 1)
+    with pytest.raises(L.QcwError):     # rho stride 0 is only for the reference
+        L.qcw_rho_fidelity_batch(rho, rho, nq, 2, rho_stride=0)
+    # count 0 is a no-op
+    L.qcw_rho_eigvals_batch(rho, nq, 0, n * n, eig)
 
 
 @pytest.mark.parametrize("nq,keep", [(2, [1]), (2, [2]), (3, [1, 3]), (5, [2, 3, 5]), (8, [4]),
