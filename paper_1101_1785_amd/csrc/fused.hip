@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -696,6 +697,39 @@ std::mutex g_plan_mu;
 std::unordered_map<hipStream_t, PlanBuf> g_plan_bufs;
 }  // namespace
 
+// Resident blocks of a pass kernel over the whole device (blocks per CU times
+// CUs), for the persistent kernels' grids.  Computed once per (kernel,
+// device) under a lock: calls may come from several threads at once.
+static int fused_grid(const void *fn, int threads, size_t lds, unsigned *grid) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, unsigned> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QCW_EHIP, "cannot query the device");
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({fn, dev});
+  if (it != cache.end()) {
+    *grid = it->second;
+    return QCW_OK;
+  }
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return fail(QCW_EHIP, "LDS of %zu B per block: %s", lds, hipGetErrorString(e));
+  }
+  int bpc = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, fn, threads, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QCW_EHIP, "fused occupancy query failed");
+  }
+  if (bpc < 1) return fail(QCW_EHIP, "fused kernel with %zu B of LDS does not fit a CU", lds);
+  *grid = (unsigned)(bpc * ncu);
+  cache[{fn, dev}] = *grid;
+  return QCW_OK;
+}
+
 template <int T, int L, int NT>
 static int launch_passes_t(qcw_c64 *psi, int nq, const FusedPass *dp, const FusedGate *dg,
                            int npass, hipStream_t s) {
@@ -707,22 +741,9 @@ static int launch_passes_t(qcw_c64 *psi, int nq, const FusedPass *dp, const Fuse
   constexpr bool persistent = T >= 13;
   const void *fn = persistent ? (const void *)fused_persistent_kernel<T, L, NT>
                               : (const void *)fused_pass_kernel<T, L, NT>;
-  static unsigned grid = 0;  // once per process and template instance
-  if (!grid) {
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return fail(QCW_EHIP, "LDS of %zu B per block: %s", lds, hipGetErrorString(e));
-    }
-    int bpc = 0, dev = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, fn, NT, lds) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(QCW_EHIP, "fused occupancy query failed");
-    }
-    if (bpc < 1) return fail(QCW_EHIP, "fused kernel with %zu B of LDS does not fit a CU", lds);
-    grid = (unsigned)(bpc * ncu);
-  }
+  unsigned grid = 0;
+  int rc = fused_grid(fn, NT, lds, &grid);
+  if (rc) return rc;
   for (int p = 0; p < npass; ++p) {
     TimedLaunch t(QCW_KERNEL_FUSED, s);
     if (persistent) {
@@ -755,21 +776,9 @@ static int launch_ws(qcw_c64 *psi, int nq, const FusedPass *dp, const FusedGate 
   constexpr int T = 12;
   const size_t lds = 2 * (sizeof(double2) << T);
   const uint64_t ntiles = 1ull << (nq - T);
-  static unsigned grid = 0;
-  if (!grid) {
-    const void *fn = (const void *)fused_ws_kernel<L>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return fail(QCW_EHIP, "LDS of %zu B per block: %s", lds, hipGetErrorString(e));
-    int bpc = 0, dev = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, fn, 1024, lds) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(QCW_EHIP, "fused occupancy query failed");
-    }
-    if (bpc < 1) return fail(QCW_EHIP, "warp-specialised fused kernel does not fit a CU");
-    grid = (unsigned)(bpc * ncu);
-  }
+  unsigned grid = 0;
+  int rc = fused_grid((const void *)fused_ws_kernel<L>, 1024, lds, &grid);
+  if (rc) return rc;
   const unsigned blocks = (unsigned)std::min<uint64_t>(grid, ntiles);
   for (int p = 0; p < npass; ++p) {
     TimedLaunch t(QCW_KERNEL_FUSED, s);
@@ -1018,6 +1027,61 @@ int qcw_fused_plan(int nq, const qcw_gate *gates, int ngates, int tile_bits, int
     return fail(QCW_EINVAL, "invalid arguments");
   int n = fused_pass_count(nq, gates, ngates, tile_bits, low_bits, plan, pass_of, order);
   return n < 0 ? fail(QCW_EINVAL, "invalid gate") : n;
+}
+
+
+int qcw_debug_fused_tables(int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
+                           int64_t nmats, int tile_bits, int low_bits, int plan, int pass_cap,
+                           int gate_cap, int32_t *pass_hdr, int32_t *outer_pos,
+                           uint64_t *chunk_off, int32_t *gate_hdr, qcw_c64 *gate_mat,
+                           int *npass, int *ngate) {
+  clear_error();
+  if (tile_bits == 0) tile_bits = kFusedDefaultTile;
+  if (low_bits == 0) low_bits = kFusedDefaultLow;
+  if (nq < 9 || nq > kMaxQubits || ngates < 1 || !gates || !mats || tile_bits < 8 ||
+      tile_bits > 13 || low_bits < 3 || low_bits > 5 || tile_bits - low_bits > kFusedMaxFree ||
+      (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE | QCW_PLAN_3M)) || !pass_hdr || !outer_pos ||
+      !chunk_off || !gate_hdr || !gate_mat || !npass || !ngate)
+    return fail(QCW_EINVAL, "invalid arguments");
+  std::vector<Geom> geo(ngates);
+  for (int i = 0; i < ngates; ++i) {
+    int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
+    if (rc) return rc;
+    const int64_t mm = (int64_t)1 << (2 * gates[i].k);
+    if (gates[i].mat < 0 || gates[i].mat + mm > nmats)
+      return fail(QCW_EINVAL, "gate %d: matrix offset outside mats", i);
+  }
+  std::vector<FusedPass> passes;
+  std::vector<FusedGate> fg;
+  int rc = plan_passes(nq, geo, gates, mats, FusedShape{std::min(tile_bits, nq), low_bits}, plan,
+                       passes, fg);
+  if (rc) return rc;
+  *npass = (int)passes.size();
+  *ngate = (int)fg.size();
+  if ((int)passes.size() > pass_cap || (int)fg.size() > gate_cap)
+    return fail(QCW_EINVAL, "plan has %zu passes and %zu gates (caps %d, %d)", passes.size(),
+                fg.size(), pass_cap, gate_cap);
+  for (size_t p = 0; p < passes.size(); ++p) {
+    const FusedPass &P = passes[p];
+    pass_hdr[4 * p + 0] = P.gate_off;
+    pass_hdr[4 * p + 1] = P.ngates;
+    pass_hdr[4 * p + 2] = P.T;
+    pass_hdr[4 * p + 3] = P.L;
+    for (int j = 0; j < 40; ++j) outer_pos[40 * p + j] = j < P.n_outer ? P.outer_pos[j] : -1;
+    for (int c = 0; c < (1 << kFusedMaxFree); ++c) chunk_off[(1 << kFusedMaxFree) * p + c] = P.chunk_off[c];
+  }
+  for (size_t g = 0; g < fg.size(); ++g) {
+    const FusedGate &G = fg[g];
+    int32_t *h = gate_hdr + 13 * g;
+    h[0] = G.k;
+    h[1] = G.sb0;
+    h[2] = G.sb1;
+    h[3] = G.sb2;
+    h[4] = G.m3;
+    for (int r = 0; r < 8; ++r) h[5 + r] = (int32_t)G.off[r];
+    for (int e = 0; e < 64; ++e) gate_mat[64 * g + e] = qcw_c64{G.u[e].x, G.u[e].y};
+  }
+  return QCW_OK;
 }
 
 }  // extern "C"

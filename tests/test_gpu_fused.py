@@ -250,3 +250,24 @@ def test_fullsize_fused_plan_matches_plain(L):
     assert worst <= tol * 2.0 ** -15.5 * 64
     del a, b
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("nq", [26, 28])
+def test_fullsize_headline_plan_vs_oracle(L, nq):
+    """The benchmark's exact configuration -- all three plan flags, default
+    tiles (12 bits, 4 low bits, 512 threads), a 4*nq-gate random circuit --
+    at sizes where the commute planner's search runs (24 qubits and up),
+    against the full oracle circuit, element by element: normwise within the
+    FP64 circuit tolerance and every amplitude within 1e-12 |psi|."""
+    G = 4 * nq
+    print(f"[gpu] headline plan vs oracle nq={nq} G={G}", flush=True)
+    psi0 = qi.state(21, nq, tag=nq)
+    c = qi.circuit(21, nq, G, tag=nq)
+    g, _ = L.pack_circuit(c)
+    assert L.qcw_fused_pass_count(nq, g, G, 0, 0, COMMUTE | FUSE | M3) < \
+        L.qcw_fused_pass_count(nq, g, G, 0, 0, 0)
+    got = _run(L, psi0, c, True, 0, 0, COMMUTE | FUSE | M3)
+    ref = oracle.circuit(c, psi0)
+    nr = np.linalg.norm(ref)
+    assert np.linalg.norm(got - ref) <= TOL * max(1, G / 64) * nr
+    assert np.max(np.abs(got - ref)) <= TOL * nr
