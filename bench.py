@@ -60,14 +60,16 @@ def _args():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-log2", type=int, default=26,
                    help="contiguous outputs per gate timed on the CPU oracle")
-    p.add_argument("--serve-seconds", type=float, default=10.0,
-                   help="length of the open-loop serving run (the full workload is 60 s)")
+    p.add_argument("--serve-seconds", type=float, default=60.0,
+                   help="length of the open-loop serving run (config 3: 60 s)")
     p.add_argument("--serve-rate", type=float, default=2000.0)
     p.add_argument("--serve-sweep-seconds", type=float, default=2.0,
                    help="seconds per offered rate in the serving rate sweep (0: skip)")
     p.add_argument("--no-compare", action="store_true",
-                   help="skip the untimed comparison solves (plain path, list-order plan), so a "
-                        "kernel trace holds only the timed launches")
+                   help="skip the untimed comparison solves (plain path, list-order plan) and the "
+                        "error checks, so a kernel trace holds only the timed launches")
+    p.add_argument("--oracle-check-nq", type=int, default=28,
+                   help="size of the oracle check of the timed plan (0: skip)")
     p.add_argument("--skip-extra", action="store_true",
                    help="only the headline workload (no batched/serving sections)")
     p.add_argument("--section", default="",
@@ -187,7 +189,7 @@ def bench_batched(torch, L, qi, seed, count, lo, hi, tune_table, reps=50, plain=
     err = max(np.linalg.norm(got[offs[i]:offs[i + 1]] - r) / np.linalg.norm(r)
               for i, r in zip(sub, refs))
     tm = _time_batch(torch, b, reps)
-    launch = min(tm, key=tm.get)
+    launch = "graph"          # the captured hipGraph replay is the batched form's figure
     ms = tm[launch]
     info = b.info(hi)
     # graph replays rotating over independent copies (own states and tables)
@@ -709,6 +711,196 @@ def bench_plain_small(torch, L, qi, nq, seed, reps=2000):
             "us_per_solve": dt / reps * 1e6}
 
 
+def _diff_stats(torch, x, y, chunk=1 << 26):
+    """Relative 2-norm difference, max |x - y| over |y|, and bitwise equality of
+    two device vectors, in chunks (temporaries of 1 GiB)."""
+    num = den = mx = 0.0
+    equal = True
+    for i in range(0, x.numel(), chunk):
+        xs, ys = x[i:i + chunk], y[i:i + chunk]
+        d = xs - ys
+        num += torch.linalg.vector_norm(d).item() ** 2
+        den += torch.linalg.vector_norm(ys).item() ** 2
+        mx = max(mx, d.abs().max().item())
+        equal = equal and torch.equal(xs, ys)
+        del d
+    den = den ** 0.5
+    return {"rel_err_2norm": (num ** 0.5) / den, "max_abs_err_over_norm": mx / den,
+            "bitwise_equal": equal}
+
+
+def compare_paths(torch, L, psi, psi_host, nq, gates, mats, G, a, stream):
+    """After the timed region, from the same input in separate buffers: one
+    solve of the timed plan, one plain solve (one sweep per gate) and one
+    list-order fused solve.  Returns the comparison solves/s and the timed
+    plan's error against the plain path (the list-order passes must equal the
+    plain path bit for bit)."""
+    def once(fn):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return 1.0 / (time.perf_counter() - t1)
+
+    src = torch.from_numpy(psi_host).to("cuda")
+    psi.copy_(src)
+    once(lambda: L.qcw_circuit_fused_ex(psi, nq, gates, G, mats, mats.size, a.tile_bits, 0, 0,
+                                        a.plan, stream))
+    plain = src.clone()
+    plain_rate = once(lambda: L.qcw_circuit(plain, nq, gates, G, mats, mats.size, stream))
+    plan_err = _diff_stats(torch, psi, plain)
+    lo_rate = once(lambda: L.qcw_circuit_fused_ex(src, nq, gates, G, mats, mats.size,
+                                                  a.tile_bits, 0, 0, 0, stream))
+    lo = _diff_stats(torch, src, plain)
+    del src, plain
+    torch.cuda.empty_cache()
+    G64 = max(1.0, G / 64)
+    other = {
+        "plain_one_sweep_per_gate_solves_per_s": plain_rate,
+        "fused_list_order_bit_exact_solves_per_s": lo_rate,
+        "fused_list_order_passes": L.qcw_fused_pass_count(nq, gates, G, a.tile_bits, 0, 0),
+    }
+    checks = {
+        "timed_plan_vs_plain": {**{k: v for k, v in plan_err.items() if k != "bitwise_equal"},
+                                "tolerance_2norm": 1e-12 * G64,
+                                "what": "one solve of the timed plan against one plain solve "
+                                        "(one sweep per gate) of the same input, "
+                                        "the whole 2^nq-amplitude state"},
+        "list_order_equals_plain_bitwise": lo["bitwise_equal"],
+    }
+    return other, checks
+
+
+def oracle_check(torch, L, qi, nq, a, seed=1):
+    """The timed configuration (same plan flags and tiles) on a state the oracle
+    finishes in under a minute on the host: one 4*nq-gate solve against the
+    oracle's circuit, element by element."""
+    import oracle
+    G = 4 * nq
+    print(f"[bench] oracle check of the timed plan at nq={nq}", file=sys.stderr, flush=True)
+    psi0 = qi.state(seed, nq)
+    c = qi.circuit(seed, nq, G)
+    g, m = L.pack_circuit(c)
+    x = torch.from_numpy(psi0).to("cuda")
+    L.qcw_circuit_fused_ex(x, nq, g, G, m, m.size, a.tile_bits, 0, 0, a.plan)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy()
+    del x
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    ref = oracle.circuit(c, psi0)
+    dt = time.perf_counter() - t0
+    nr = np.linalg.norm(ref)
+    return {"nq": nq, "gates": G, "seed": seed,
+            "passes": L.qcw_fused_pass_count(nq, g, G, a.tile_bits, 0, a.plan),
+            "rel_err_2norm": float(np.linalg.norm(got - ref) / nr),
+            "max_abs_err_over_norm": float(np.max(np.abs(got - ref)) / nr),
+            "tolerance_2norm": 1e-12 * max(1.0, G / 64), "tolerance_elementwise": 1e-12,
+            "oracle_s": dt, "oracle_threads": oracle.threads()}
+
+
+def _executed_flops(L, circ, gates, mats, a):
+    """FP64 flops the fused passes execute per launch (average over the plan's
+    passes), from the device tables of the plan: per amplitude 8m - 2 for a
+    gate in the direct form, 6m + 1 in the three-product form."""
+    tb = L.qcw_debug_fused_tables(circ.nq, gates, len(circ), mats, a.tile_bits, 0, a.plan)
+    N = 1 << circ.nq
+    tot = sum(N * ((6 * (1 << g["k"]) + 1) if g["m3"] else (8 * (1 << g["k"]) - 2))
+              for g in tb["gates"])
+    return tot / max(1, len(tb["passes"]))
+
+
+def bench_eigen(torch, L, nq, count=4096, seed=8, reps=5, check=64):
+    """Batched eigenvalues with entropies, and batched fidelities, of `count`
+    density matrices of nq qubits (ranks 1, 2, 3 and full in turn), one
+    persistent launch each (the observables the paper follows per step, §5);
+    errors against numpy's Hermitian solver on a sample."""
+    rng = np.random.default_rng([seed, nq])
+    n = 1 << nq
+    ranks = [1, 2, 3, n]
+    rhos = np.empty((count, n, n), np.complex128)
+    for i in range(count):
+        r = min(ranks[i % 4], n)
+        A = rng.normal(size=(n, r)) + 1j * rng.normal(size=(n, r))
+        R = A @ A.conj().T
+        rhos[i] = R / np.trace(R).real
+    d = torch.from_numpy(rhos.reshape(-1)).to("cuda")
+    eig = torch.empty((count, n), dtype=torch.float64, device="cuda")
+    ent = torch.empty(count, dtype=torch.float64, device="cuda")
+    fid = torch.empty(count, dtype=torch.float64, device="cuda")
+    psi0 = np.zeros(n, complex)
+    psi0[0] = 1
+    ref0 = torch.from_numpy(np.outer(psi0, psi0).reshape(-1)).to("cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_eig = timed(lambda: L.qcw_rho_eigvals_batch(d, nq, count, eig=eig, entropy=ent))
+    ms_fid_pair = timed(lambda: L.qcw_rho_fidelity_batch(d, d, nq, count, out=fid))
+    ms_fid_pure = timed(lambda: L.qcw_rho_fidelity_batch(d, ref0, nq, count, rho0_stride=0,
+                                                          out=fid))
+    ev = eig.cpu().numpy()
+    S = ent.cpu().numpy()
+    F = fid.cpu().numpy()
+    sub = range(0, count, max(1, count // check))
+    err_ev = max(float(np.max(np.abs(ev[i] - np.linalg.eigvalsh(rhos[i])))) for i in sub)
+    err_S = 0.0
+    for i in sub:
+        lam = np.linalg.eigvalsh(rhos[i])
+        lam = lam[lam > 1e-300]
+        err_S = max(err_S, abs(S[i] + float(np.sum(lam * np.log2(lam)))))
+    err_F = max(abs(F[i] - np.sqrt(rhos[i][0, 0].real)) for i in sub)
+    del d, eig, ent, fid
+    torch.cuda.empty_cache()
+    return {"nq": nq, "matrices": count, "ranks": "1, 2, 3, full in turn",
+            "eig_ms": ms_eig, "eig_matrices_per_s": count / (ms_eig * 1e-3),
+            "fidelity_pairs_ms": ms_fid_pair, "fidelity_pure_reference_ms": ms_fid_pure,
+            "fidelity_pure_reference_per_s": count / (ms_fid_pure * 1e-3),
+            "max_abs_err_eigenvalues_vs_lapack": err_ev, "max_abs_err_entropy_bits": err_S,
+            "max_abs_err_fidelity_vs_closed_form": float(err_F), "checked_matrices": len(sub)}
+
+
+def key_figures(extra, checks, cpu):
+    """A compact copy of the figures of every configuration, kept with the
+    workload description so that they survive in short records."""
+    def pick(sec, *keys):
+        d = extra.get(sec) or {}
+        return {k: d[k] for k in keys if k in d} or None
+    k = {
+        "config0_plain_nq3": pick("config0_plain_nq3", "p50_us", "p99_us",
+                                  "back_to_back_solves_per_s", "rel_err_vs_oracle"),
+        "config2_batched_4096_nq3_7": pick("batched_config2", "graph_us", "eager_us",
+                                           "batched_solves_per_s", "plain_solves_per_s",
+                                           "batched_over_plain", "max_rel_err_vs_oracle",
+                                           "fp64_frac"),
+        "config3_served_poisson": pick("serving_config3", "rate_per_s", "seconds", "requests",
+                                       "failed", "p50_ms", "p99_ms", "solves_per_s",
+                                       "peak_active"),
+        "config4_batched_4096_nq9": pick("batched_config4", "graph_us", "eager_us",
+                                         "batched_solves_per_s", "plain_solves_per_s",
+                                         "batched_over_plain", "max_rel_err_vs_oracle",
+                                         "fp64_frac"),
+        "eigen_batch_nq5": pick("eigen_batch_nq5", "eig_matrices_per_s",
+                                "max_abs_err_eigenvalues_vs_lapack"),
+        "channel_nq13": pick("multiverse_nq13", "channel_ms", "channel_fp64_frac",
+                             "channel_gbs_read_write_once"),
+        "timed_plan_vs_plain_rel_err": (checks.get("timed_plan_vs_plain") or {}).get(
+            "rel_err_2norm"),
+        "timed_plan_vs_oracle_rel_err": (checks.get("oracle_check") or {}).get("rel_err_2norm"),
+        "cpu_oracle_solves_per_s": (cpu or {}).get("value"),
+    }
+    return {a: b for a, b in k.items() if b is not None}
+
+
 def counters_run(torch, L, qi):
     """One launch of each kernel family at a known size, for hardware counters."""
     nq = 28
@@ -748,6 +940,10 @@ def extra_sections(torch, L, qi, a):
         "grover_n6": lambda: bench_grover(torch, L, qi, tt),
         "shard_nq32": lambda: bench_shard(torch, L, qi),
         "multiverse_nq12": lambda: bench_multiverse(torch, L, qi, 12, 5),
+        "multiverse_nq13": lambda: bench_multiverse(torch, L, qi, 13, 5, steps=10),
+        "multiverse_nq14": lambda: bench_multiverse(torch, L, qi, 14, 5, steps=5),
+        "eigen_batch_nq5": lambda: bench_eigen(torch, L, 5),
+        "eigen_batch_nq6": lambda: bench_eigen(torch, L, 6),
         "multiverse_nq5": lambda: bench_multiverse(torch, L, qi, 5, 5, steps=200),
         "multiverse_nq5_rotation_noise": lambda: bench_multiverse(torch, L, qi, 5, 6, steps=200,
                                                                   noise="rotation"),
@@ -850,41 +1046,61 @@ def main():
         unit_note = "one gate over the state"
     avg_ms = kms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    # the circuit's algorithmic flops (its gates as listed), spread over the launches
+    # the circuit's algorithmic flops (its gates as listed, 8m - 2 per amplitude
+    # per gate), spread over the launches
     flops_per_launch = _flops_per_solve(circ) / max(npass, 1)
     fp64_tflops = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    # the binding roof: the larger of the two minimum times per launch
+    t_hbm = bytes_per_launch / (HBM_PEAK_GBS * 1e9)
+    t_fp64 = flops_per_launch / (FP64_PEAK_TFLOPS * 1e12)
+    executed = _executed_flops(L, circ, gates, mats, a) if a.path == "fused" else None
     norm = torch.linalg.vector_norm(psi).item()
 
-    # the other paths, for comparison (same state buffer, untimed by the events above)
-    other = {}
+    # the other paths, and the error of the timed plan, outside the timed region
+    other, checks = {}, {"final_norm": norm, "wall_s": wall}
     if a.path == "fused" and not a.no_compare:
-        def once(fn):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            return 1.0 / (time.perf_counter() - t1)
-        other = {
-            "plain_one_sweep_per_gate_solves_per_s":
-                once(lambda: L.qcw_circuit(psi, nq, gates, G, mats, mats.size, stream)),
-            "fused_list_order_bit_exact_solves_per_s":
-                once(lambda: L.qcw_circuit_fused_ex(psi, nq, gates, G, mats, mats.size,
-                                                    a.tile_bits, 0, 0, 0, stream)),
-            "fused_list_order_passes": L.qcw_fused_pass_count(nq, gates, G, a.tile_bits, 0, 0),
-        }
+        print("[bench] comparison solves and error checks", file=sys.stderr, flush=True)
+        other, chk = compare_paths(torch, L, psi, psi_host, nq, gates, mats, G, a, stream)
+        checks.update(chk)
+    del psi
+    torch.cuda.empty_cache()
+    if a.path == "fused" and not a.no_compare and a.oracle_check_nq > 0:
+        checks["oracle_check"] = oracle_check(torch, L, qi, a.oracle_check_nq, a)
 
     cpu = None
     if not a.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(circ, psi_host, a.cpu_sample_log2)
-    del psi, psi_host
-    torch.cuda.empty_cache()
+    del psi_host
 
     extra = {}
     if not a.skip_extra:
         for name, fn in extra_sections(torch, L, qi, a).items():
+            print(f"[bench] section {name}", file=sys.stderr, flush=True)
             extra[name] = fn()
 
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS,
+           "traffic": _traffic("fused" if a.path == "fused" else "sweep", nq),
+           "algorithmic_bytes_per_launch": bytes_per_launch, "min_ms_per_launch": t_hbm * 1e3}
+    fp64 = {"achieved": fp64_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": fp64_tflops / FP64_PEAK_TFLOPS,
+            "algorithmic_flops_per_launch": flops_per_launch, "min_ms_per_launch": t_fp64 * 1e3}
+    if t_fp64 > t_hbm:
+        roof = {"bound": "alu", **fp64, "traffic": hbm["traffic"],
+                "why": "the circuit's FP64 flops per pass need more time at 78.6 TFLOP/s than "
+                       "its 32 B per amplitude at 8 TB/s (FP64 vector peak; the FP64 matrix "
+                       "cores share that throughput)"}
+    else:
+        roof = {"bound": "hbm", **hbm}
+    roofline = {
+        **roof,
+        "hbm": hbm, "fp64": fp64,
+        "kernel": kernel, "unit_of_work": unit_note, "launches": launches,
+        "avg_launch_ms": avg_ms, "per_k": per_k or None,
+        "executed_flops_per_launch": executed,
+    }
+    key = key_figures(extra, checks, cpu)
     out = {
         "metric": METRIC,
         "value": a.steps / (ms_total * 1e-3),
@@ -910,20 +1126,11 @@ def main():
                       or "list order (bit-exact)") if a.path == "fused" else None),
             "passes_per_solve": npass,
             **other,
+            "key_figures": key,
         },
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": _traffic("fused" if a.path == "fused" else "sweep", nq),
-            "kernel": kernel, "unit_of_work": unit_note, "launches": launches,
-            "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-            "per_k": per_k or None,
-            "algorithmic_flops_per_launch": flops_per_launch,
-            "fp64_achieved_tflops": fp64_tflops,
-            "fp64_frac": fp64_tflops / FP64_PEAK_TFLOPS,
-        },
+        "roofline": roofline,
         "cpu_baseline": cpu,
-        "checks": {"final_norm": norm, "wall_s": wall},
+        "checks": checks,
         **extra,
     }
     print(json.dumps(out), flush=True)
