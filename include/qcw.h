@@ -286,6 +286,16 @@ int qcw_batch_create(qcw_batch **out, const qcw_instance *inst, int n,
 int qcw_batch_run(qcw_batch *b, void *stream);
 /* The same work enqueued directly (no graph), e.g. inside a caller's capture. */
 int qcw_batch_run_eager(qcw_batch *b, void *stream);
+/* The batch `reps` times in a row (1 <= reps <= 1024) with one graph launch:
+ * every instance's circuit applied reps times, as reps calls of qcw_batch_run
+ * would, bit for bit, for callers that step the same instances repeatedly
+ * (the multiverse paths of §5 advance step after step).  The graph of reps
+ * executions is captured on first use (on a private stream, which it
+ * synchronises) and kept with the handle.  A graph launch costs the host
+ * tens of microseconds in the HIP runtime, more than one execution of a
+ * small batch takes on the device; one launch per reps executions spreads
+ * that cost. */
+int qcw_batch_run_repeat(qcw_batch *b, int reps, void *stream);
 /* Launch shape: tile-shape variant used for instances of nq qubits, grid
  * blocks and dynamic LDS bytes per block.  Any output pointer may be NULL. */
 int qcw_batch_info(const qcw_batch *b, int nq, int *variant, int *blocks, int *lds_bytes);

@@ -76,6 +76,7 @@ _SIGS = {
     "qcw_batch_create": ([_P, _P, _i32, _P, _i64, _P, _i64, _P, _i64, ctypes.c_char_p, _P], _i32),
     "qcw_batch_run": ([_P, _P], _i32),
     "qcw_batch_run_eager": ([_P, _P], _i32),
+    "qcw_batch_run_repeat": ([_P, _i32, _P], _i32),
     "qcw_batch_info": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_batch_destroy": ([_P], _i32),
     "qcw_batch_variant_name": ([_i32], ctypes.c_char_p),
@@ -390,6 +391,10 @@ def qcw_batch_run_eager(h, stream=None):
     _check(_L.qcw_batch_run_eager(h, _stream(stream)), "qcw_batch_run_eager")
 
 
+def qcw_batch_run_repeat(h, reps, stream=None):
+    _check(_L.qcw_batch_run_repeat(h, int(reps), _stream(stream)), "qcw_batch_run_repeat")
+
+
 def qcw_batch_info(h, nq):
     v, b, l = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
     _check(_L.qcw_batch_info(h, int(nq), ctypes.byref(v), ctypes.byref(b), ctypes.byref(l)),
@@ -444,6 +449,9 @@ class Batch:
 
     def run_eager(self, stream=None):
         qcw_batch_run_eager(self.h, stream)
+
+    def run_repeat(self, reps, stream=None):
+        qcw_batch_run_repeat(self.h, reps, stream)
 
     def info(self, nq):
         return qcw_batch_info(self.h, nq)

@@ -72,7 +72,7 @@ __device__ __forceinline__ void lds_gate(double2 *S, int nq, const BGate &g, con
 }
 
 template <int AMP, bool MAT_LDS>
-__device__ void run_instance(const BInst &in, const BGate *__restrict__ gates,
+__device__ void run_instance(const BItem &in, const BGate *__restrict__ gates,
                              const double2 *__restrict__ mats, double2 *__restrict__ states,
                              double2 *S, double2 *Ul, int lane, int g_begin, int g_end) {
   const int nq = in.nq;
@@ -129,16 +129,16 @@ __device__ void run_instance(const BInst &in, const BGate *__restrict__ gates,
 // One persistent launch over `nitems` work items.  Each wavefront owns
 // `wave_amps` amplitudes of dynamic LDS plus two 64-entry matrix slots.
 __global__ __launch_bounds__(kBatchBlock) void batch_kernel(
-    const BItem *__restrict__ items, int nitems, const BInst *__restrict__ inst,
-    const BGate *__restrict__ gates, const double2 *__restrict__ mats,
-    double2 *__restrict__ states, int *__restrict__ counter, int wave_amps) {
+    const BItem *__restrict__ items, int nitems, const BGate *__restrict__ gates,
+    const double2 *__restrict__ mats, double2 *__restrict__ states, int *__restrict__ counter,
+    int wave_amps) {
   extern __shared__ double2 lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   double2 *S = lds + (size_t)wave * (wave_amps + 128);
   double2 *Ul = S + wave_amps;
   for_each_item(items, nitems, counter, lane, wave, [&](const BItem &item) {
-    const BInst in = inst[item.inst];
+    const BItem &in = item;
     const int g0 = item.g_begin, g1 = item.g_end;
     switch (item.variant) {
       case kVarAmp4Sgpr: run_instance<4, false>(in, gates, mats, states, S, Ul, lane, g0, g1); break;
@@ -169,7 +169,7 @@ int launch_batch(const BatchLaunch &L, hipStream_t s) {
   if (L.n_exact > 0) {
     TimedLaunch t(kKernelBatch, s);
     hipLaunchKernelGGL(batch_kernel, dim3(L.ex.blocks), dim3(L.ex.threads), L.ex.lds_bytes, s,
-                       L.items, L.n_exact, L.inst, L.gates, L.mats, L.states, L.counter,
+                       L.items, L.n_exact, L.gates, L.mats, L.states, L.counter,
                        L.ex.wave_amps);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(QCW_EHIP, "batch launch: %s", hipGetErrorString(e));

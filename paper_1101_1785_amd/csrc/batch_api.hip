@@ -128,9 +128,34 @@ int plan_batch_launch(int max_nq, int n_exact, int n_mfma, BatchLaunch *L) {
   return plan_shape(max_nq, n_mfma, amps * sizeof(double2), true, &L->mf);
 }
 
+// Deals one persistent kernel's items (sorted largest first) to its blocks so
+// that the blocks resident together on a CU mix large and small items.  The
+// dispatcher places blocks on CUs in index order, one round over all CUs at a
+// time, so residency slot j of the CUs holds blocks [j * ncu, (j + 1) * ncu);
+// in every other slot the groups of items are dealt in reverse, which pairs
+// the largest items of one slot with the smallest of the next.  Applies only
+// when every item has its own wave and the items fill whole blocks (the item
+// index of a wave is then its block's index times waves per block plus its
+// wave), so no wave is left without an item in the middle of the list.
+void snake_items(BItem *items, int n, const BatchShape &sh, int ncu) {
+  const int wpb = sh.threads / 64;
+  if (n <= 0 || wpb < 1 || n % wpb || (int64_t)n > (int64_t)sh.blocks * wpb || ncu < 1) return;
+  const int nb = n / wpb;
+  if (nb <= ncu) return;
+  std::vector<BItem> src(items, items + n);
+  for (int i = 0; i < nb; ++i) {
+    const int j = i / ncu, p = i % ncu;
+    const int in_slot = std::min(ncu, nb - j * ncu);
+    const int blk = (j & 1) ? j * ncu + (in_slot - 1 - p) : i;
+    for (int w = 0; w < wpb; ++w) items[blk * wpb + w] = src[i * wpb + w];
+  }
+}
+
 // Largest batch-resident instance: each wave needs (2^nq + 128) * 16 bytes of
 // LDS, 34 KiB at nq = 11.  Larger instances run as plain sweeps in the same graph.
 constexpr int kBatchResidentNq = 11;
+// Most executions one graph of qcw_batch_run_repeat may hold.
+constexpr int kBatchMaxRepeat = 1024;
 
 }  // namespace qcw
 
@@ -139,7 +164,6 @@ using namespace qcw;
 struct qcw_batch {
   int n = 0;
   qcw_c64 *states = nullptr;
-  BInst *inst_d = nullptr;
   BGate *gates_d = nullptr;
   double2 *mats_d = nullptr;
   BItem *items_d = nullptr;
@@ -153,13 +177,18 @@ struct qcw_batch {
   TuneTable tune;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // graphs of several executions in a row (qcw_batch_run_repeat), per count
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> repeat;
 };
 
 static void batch_free(qcw_batch *b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  (void)hipFree(b->inst_d);
+  for (auto &r : b->repeat) {
+    if (r.second.second) (void)hipGraphExecDestroy(r.second.second);
+    if (r.second.first) (void)hipGraphDestroy(r.second.first);
+  }
   (void)hipFree(b->gates_d);
   (void)hipFree(b->mats_d);
   (void)hipFree(b->items_d);
@@ -245,6 +274,7 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
 
   // Work items: LDS-resident instances, most work first.
   std::vector<BItem> items;
+  std::vector<int> item_inst;  // instance of each item
   for (int i = 0; i < n; ++i) {
     const BInst &in = b->inst_h[i];
     if (in.nq > kBatchResidentNq) {
@@ -252,7 +282,10 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
       continue;
     }
     int v = variant_override ? variant_override[in.nq] : b->tune.variant[in.nq];
-    items.push_back({i, v, 0, in.ngates});
+    items.push_back({in.nq, v, 0, in.ngates, in.state_off, in.gate_off,
+                     in.ngates > 0 ? gates[in.gate_off].mat : 0,
+                     in.ngates > 0 ? gates[in.gate_off].k : 0, 0});
+    item_inst.push_back(i);
   }
   // Instances on the matrix-core variant (already exact only to rounding) run
   // their circuits fused into gates of at most three qubits.  Instances that
@@ -260,9 +293,10 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
   std::vector<double2> m2((size_t)nmats);
   for (int64_t i = 0; i < nmats; ++i) m2[i] = make_double2(mats[i].re, mats[i].im);
   std::map<std::pair<int64_t, int>, std::pair<int64_t, int>> fused_at;
-  for (BItem &it : items) {
+  for (size_t ii = 0; ii < items.size(); ++ii) {
+    BItem &it = items[ii];
     if (it.variant != kVarAmp4Mfma) continue;
-    BInst &in = b->inst_h[it.inst];
+    BInst &in = b->inst_h[item_inst[ii]];
     auto key = std::make_pair(in.gate_off, in.ngates);
     auto f = fused_at.find(key);
     if (f == fused_at.end()) {
@@ -283,21 +317,39 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
     }
     in.gate_off = f->second.first;
     in.ngates = f->second.second;
+    it.gate_off = in.gate_off;
     it.g_end = in.ngates;
+  }
+  // the first gate's matrix, for the matrix-core kernel (offsets into m2)
+  for (BItem &it : items) {
+    if (it.variant != kVarAmp4Mfma || it.g_end <= it.g_begin) continue;
+    const BGate &g0 = bg[it.gate_off + it.g_begin];
+    it.mat0 = g0.mat_off;
+    it.k0 = g0.k;
   }
   // Exact-kernel items first, then matrix-core items; most work first in each.
   std::stable_sort(items.begin(), items.end(), [&](const BItem &x, const BItem &y) {
     const bool mx = x.variant == kVarAmp4Mfma, my = y.variant == kVarAmp4Mfma;
     if (mx != my) return my;
-    const BInst &a = b->inst_h[x.inst], &c = b->inst_h[y.inst];
-    return ((int64_t)a.ngates << a.nq) > ((int64_t)c.ngates << c.nq);
+    return ((int64_t)(x.g_end - x.g_begin) << x.nq) > ((int64_t)(y.g_end - y.g_begin) << y.nq);
   });
   b->nitems = (int)items.size();
   int n_exact = 0;
   for (const BItem &it : items) n_exact += it.variant != kVarAmp4Mfma;
 
-  int rc;
-  if ((rc = upload(&b->inst_d, b->inst_h.data(), b->inst_h.size(), "instances"))) return rc;
+  // Grids first, so the items can be dealt to their blocks.
+  int rc = plan_batch_launch(max_nq, n_exact, b->nitems - n_exact, &b->L);
+  if (rc) return rc;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(QCW_EHIP, "cannot query the device");
+    }
+    snake_items(items.data(), n_exact, b->L.ex, ncu);
+    snake_items(items.data() + n_exact, b->nitems - n_exact, b->L.mf, ncu);
+  }
   if ((rc = upload(&b->gates_d, bg.data(), bg.size(), "gates"))) return rc;
   if ((rc = upload(&b->mats_d, m2.data(), m2.size(), "matrices"))) return rc;
   if ((rc = upload(&b->items_d, items.data(), items.size(), "work items"))) return rc;
@@ -307,15 +359,17 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
   b->L.items = b->items_d;
   b->L.nitems = b->nitems;
   b->L.n_exact = n_exact;
-  b->L.inst = b->inst_d;
   b->L.gates = b->gates_d;
   b->L.mats = b->mats_d;
   b->L.states = reinterpret_cast<double2 *>(states);
   b->L.counter = b->counter_d;
-  return plan_batch_launch(max_nq, n_exact, b->nitems - n_exact, &b->L);
+  return QCW_OK;
 }
 
-static int capture(qcw_batch *b, hipStream_t user) {
+// Captures `reps` executions of the batch, one after another, into a graph
+// on `user` (NULL: a private stream) and instantiates it.
+static int capture(qcw_batch *b, hipStream_t user, int reps, hipGraph_t *graph,
+                   hipGraphExec_t *exec) {
   hipStream_t s = user;
   bool own = false;
   if (!s) {
@@ -332,12 +386,12 @@ static int capture(qcw_batch *b, hipStream_t user) {
     (void)hipGetLastError();
     rc = fail(QCW_EHIP, "hipStreamBeginCapture failed");
   } else {
-    rc = enqueue_batch(b, s);
+    for (int r = 0; r < reps && !rc; ++r) rc = enqueue_batch(b, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (!rc && e != hipSuccess) rc = fail(QCW_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    b->graph = g;
-    if (!rc && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+    *graph = g;
+    if (!rc && hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
       (void)hipGetLastError();
       rc = fail(QCW_EHIP, "hipGraphInstantiate failed");
     }
@@ -365,7 +419,7 @@ int qcw_batch_create(qcw_batch **out, const qcw_instance *inst, int n, const qcw
   qcw_batch *b = new qcw_batch();
   int rc = tune_load(tune_table, &b->tune);
   if (!rc) rc = batch_build(b, inst, n, gates, ngates, mats, nmats, states, nstates, nullptr);
-  if (!rc) rc = capture(b, (hipStream_t)stream);
+  if (!rc) rc = capture(b, (hipStream_t)stream, 1, &b->graph, &b->exec);
   if (rc) {
     batch_free(b);
     return rc;
@@ -379,6 +433,30 @@ int qcw_batch_run(qcw_batch *b, void *stream) {
   if (!b || !b->exec) return fail(QCW_EINVAL, "invalid batch handle");
   TimedLaunch t(kKernelBatch, (hipStream_t)stream);
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(QCW_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+  return QCW_OK;
+}
+
+int qcw_batch_run_repeat(qcw_batch *b, int reps, void *stream) {
+  clear_error();
+  if (!b || !b->exec) return fail(QCW_EINVAL, "invalid batch handle");
+  if (reps < 1 || reps > kBatchMaxRepeat)
+    return fail(QCW_EINVAL, "reps=%d outside [1, %d]", reps, kBatchMaxRepeat);
+  if (reps == 1) return qcw_batch_run(b, stream);
+  auto it = b->repeat.find(reps);
+  if (it == b->repeat.end()) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    int rc = capture(b, nullptr, reps, &g, &x);
+    if (rc) {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    it = b->repeat.emplace(reps, std::make_pair(g, x)).first;
+  }
+  TimedLaunch t(kKernelBatch, (hipStream_t)stream);
+  hipError_t e = hipGraphLaunch(it->second.second, (hipStream_t)stream);
   if (e != hipSuccess) return fail(QCW_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
   return QCW_OK;
 }

@@ -1,8 +1,7 @@
 // Gate updates on an LDS-resident block of amplitudes with the FP64 matrix
-// cores, shared by the matrix-core batch kernel (batch_mfma.hip) and the
-// fast fused passes (fused.hip).  A wavefront applies a gate to a range of
-// its groups; the results agree with the plain path to rounding (the
-// instructions' summation order), not bit for bit.
+// cores, for the matrix-core batch kernel (batch_mfma.hip).  A wavefront
+// applies a gate to a range of its groups; the results agree with the plain
+// path to rounding (the instructions' summation order), not bit for bit.
 //
 // The complex m x m product is the real 2m x 2m product
 //   [Re y; Im y] = [[Re U, -Im U], [Im U, Re U]] [Re x; Im x]
@@ -27,8 +26,9 @@ namespace mc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Tiles of 16 groups applied together by one step: their LDS latencies and
-// matrix-core chains overlap.
+// At most this many tiles of 16 groups are applied together by one step:
+// their LDS latencies and matrix-core chains overlap.  A gate with fewer
+// groups (small instances: 2^(nq-k) groups) issues only the tiles it has.
 constexpr int kTiles = 4;
 
 // Gate descriptor header (the first twelve dwords of both BGate and
@@ -127,38 +127,38 @@ __device__ __forceinline__ void gate1(double2 *S, uint32_t jb, uint32_t nj, cons
 // Two-qubit gate, 16 groups per tile: the real 8 x 8 matrix splits into four
 // 4 x 4 blocks acting on (Re x, Im x):
 //   Re y = ReU Re x - ImU Im x,  Im y = ImU Re x + ReU Im x.
-// Lane l holds U[l & 3][l >> 4] and owns amplitude l >> 4 of its group.  FULL:
-// nj is a multiple of 16 kTiles, so no tile needs masking.
-template <bool FULL>
+// Lane l holds U[l & 3][l >> 4] and owns amplitude l >> 4 of its group.  NT
+// tiles per step; FULL: nj is a multiple of 16 NT, so no tile needs masking.
+template <int NT, bool FULL>
 __device__ __forceinline__ void gate2(double2 *S, uint32_t jb, uint32_t nj, const Fields &f,
                                       double2 u, int lane) {
   const uint32_t lane_p =
       insert_zeros<2, uint32_t>((uint32_t)(lane & 15), f.sb0, f.sb1, 0) + member(f, lane >> 4);
   const bool lane_ok = FULL || (uint32_t)(lane & 15) < nj;
-  for (uint32_t t0 = 0; t0 < nj; t0 += 16 * kTiles) {
-    uint32_t p[kTiles];
-    bool ok[kTiles];
-    double2 x[kTiles];
+  for (uint32_t t0 = 0; t0 < nj; t0 += 16 * NT) {
+    uint32_t p[NT];
+    bool ok[NT];
+    double2 x[NT];
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
       ok[t] = FULL || (lane_ok && t0 + 16 * t < nj);
       p[t] = lane_p | insert_zeros<2, uint32_t>(jb + t0 + 16 * t, f.sb0, f.sb1, 0);
       x[t] = make_double2(0.0, 0.0);
       if (ok[t]) x[t] = S[p[t]];
     }
-    double re[kTiles], im[kTiles];
+    double re[NT], im[NT];
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
       re[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, x[t].x, 0.0, 0, 0, 0);
       im[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(u.y, x[t].x, 0.0, 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
       re[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(-u.y, x[t].y, re[t], 0, 0, 0);
       im[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(u.x, x[t].y, im[t], 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t)
+    for (int t = 0; t < NT; ++t)
       if (ok[t]) S[p[t]] = make_double2(re[t], im[t]);
   }
 }
@@ -168,8 +168,8 @@ __device__ __forceinline__ void gate2(double2 *S, uint32_t jb, uint32_t nj, cons
 // are Re, Im of amplitude s = l >> 4 and Re, Im of amplitude 4 + s -- the two
 // amplitudes it also supplies as B.  Lane l holds the A entries of its row
 // l & 15 (fetch_operands): real parts for a Re row, and the signs and parts
-// of the real form for an Im row.
-template <bool FULL>
+// of the real form for an Im row.  NT tiles per step, FULL as for gate2.
+template <int NT, bool FULL>
 __device__ __forceinline__ void gate3(double2 *S, uint32_t jb, uint32_t nj, const Fields &f,
                                       double2 u0, double2 u1, int lane) {
   const int s = lane >> 4;
@@ -179,12 +179,12 @@ __device__ __forceinline__ void gate3(double2 *S, uint32_t jb, uint32_t nj, cons
   const uint32_t m0 = member(f, s), m1 = member(f, 4 + s);
   const uint32_t lane_b = insert_zeros<3, uint32_t>((uint32_t)(lane & 15), f.sb0, f.sb1, f.sb2);
   const bool lane_ok = FULL || (uint32_t)(lane & 15) < nj;
-  for (uint32_t t0 = 0; t0 < nj; t0 += 16 * kTiles) {
-    uint32_t b[kTiles];
-    bool ok[kTiles];
-    double2 x0[kTiles], x1[kTiles];
+  for (uint32_t t0 = 0; t0 < nj; t0 += 16 * NT) {
+    uint32_t b[NT];
+    bool ok[NT];
+    double2 x0[NT], x1[NT];
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
       ok[t] = FULL || (lane_ok && t0 + 16 * t < nj);
       b[t] = lane_b | insert_zeros<3, uint32_t>(jb + t0 + 16 * t, f.sb0, f.sb1, f.sb2);
       x0[t] = make_double2(0.0, 0.0);
@@ -194,20 +194,20 @@ __device__ __forceinline__ void gate3(double2 *S, uint32_t jb, uint32_t nj, cons
         x1[t] = S[b[t] + m1];
       }
     }
-    d4 d[kTiles];
+    d4 d[NT];
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
       d[t] = d4{0.0, 0.0, 0.0, 0.0};
       d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0[t].x, d[t], 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0[t].y, d[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0[t].y, d[t], 0, 0, 0);
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, x1[t].x, d[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, x1[t].x, d[t], 0, 0, 0);
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, x1[t].y, d[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, x1[t].y, d[t], 0, 0, 0);
 #pragma unroll
-    for (int t = 0; t < kTiles; ++t)
+    for (int t = 0; t < NT; ++t)
       if (ok[t]) {
         S[b[t] + m0] = make_double2(d[t][0], d[t][1]);
         S[b[t] + m1] = make_double2(d[t][2], d[t][3]);
@@ -215,16 +215,22 @@ __device__ __forceinline__ void gate3(double2 *S, uint32_t jb, uint32_t nj, cons
   }
 }
 
-// One gate of descriptor f with operands (u0, u1) on groups jb .. jb + nj - 1.
+// One gate of descriptor f with operands (u0, u1) on groups jb .. jb + nj - 1
+// (nj a power of two): as many tiles per step as there are groups, up to
+// kTiles.  Each group's result depends only on its own column, so the tile
+// count changes no result.
 __device__ __forceinline__ void apply(double2 *S, uint32_t jb, uint32_t nj, const Fields &f,
                                       double2 u0, double2 u1, int lane) {
-  const bool full = (nj & (16 * kTiles - 1)) == 0;
   if (f.k == 3) {
-    if (full) gate3<true>(S, jb, nj, f, u0, u1, lane);
-    else gate3<false>(S, jb, nj, f, u0, u1, lane);
+    if (nj >= 16 * kTiles) gate3<kTiles, true>(S, jb, nj, f, u0, u1, lane);
+    else if (nj == 32) gate3<2, true>(S, jb, nj, f, u0, u1, lane);
+    else if (nj == 16) gate3<1, true>(S, jb, nj, f, u0, u1, lane);
+    else gate3<1, false>(S, jb, nj, f, u0, u1, lane);
   } else if (f.k == 2) {
-    if (full) gate2<true>(S, jb, nj, f, u0, lane);
-    else gate2<false>(S, jb, nj, f, u0, lane);
+    if (nj >= 16 * kTiles) gate2<kTiles, true>(S, jb, nj, f, u0, lane);
+    else if (nj == 32) gate2<2, true>(S, jb, nj, f, u0, lane);
+    else if (nj == 16) gate2<1, true>(S, jb, nj, f, u0, lane);
+    else gate2<1, false>(S, jb, nj, f, u0, lane);
   } else {
     gate1(S, jb, nj, f, u0, lane);
   }

@@ -43,12 +43,20 @@ struct alignas(16) BGate {  // gate with its geometry precomputed on the host
 };
 static_assert(sizeof(BGate) == 64, "BGate layout");
 
-struct BItem {
-  int32_t inst;     // instance index
-  int32_t variant;  // BatchVariant
-  int32_t g_begin;  // gate range of this launch
+// A work item carries its instance's fields and the first gate's matrix, so
+// a wave issues its state, descriptor and first operand loads at once.
+struct alignas(16) BItem {
+  int32_t nq;
+  int32_t variant;    // BatchVariant
+  int32_t g_begin;    // gate range of this launch (relative to gate_off)
   int32_t g_end;
+  int64_t state_off;  // in complex elements
+  int64_t gate_off;   // index of the instance's first gate
+  int64_t mat0;       // matrix offset of gate g_begin (0 when the range is empty)
+  int32_t k0;         // its qubit count
+  int32_t pad;
 };
+static_assert(sizeof(BItem) == 48, "BItem layout");
 
 // Grid of one of the two persistent kernels.
 struct BatchShape {
@@ -62,7 +70,6 @@ struct BatchLaunch {
   const BItem *items;  // items [0, n_exact) run in the exact kernel, the rest in
   int nitems;          // the matrix-core kernel (variant kVarAmp4Mfma)
   int n_exact;
-  const BInst *inst;
   const BGate *gates;
   const double2 *mats;
   double2 *states;

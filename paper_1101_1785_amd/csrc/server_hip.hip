@@ -83,8 +83,7 @@ class HipExecutor : public Executor {
     res_cap_ = std::min<uint64_t>(arena_bytes_, (uint64_t)max_slots_ * (16ull << max_nq_));
     blob_cap_ = std::min<uint64_t>(arena_bytes_, kStageBlobBytes);
     const uint64_t ms = (uint64_t)max_slots_;
-    table_cap_ = 2 * round256(ms * sizeof(CopyEnt)) + round256(ms * sizeof(BInst)) +
-                 round256(ms * sizeof(BItem));
+    table_cap_ = 2 * round256(ms * sizeof(CopyEnt)) + round256(ms * sizeof(BItem));
     if (hipMalloc(&arena_, std::max<uint64_t>(arena_bytes_, 256)) != hipSuccess)
       return mem_fail("arena", arena_bytes_);
     if (hipMalloc(&mirror_d_, blob_cap_ + table_cap_) != hipSuccess ||
@@ -149,6 +148,8 @@ class HipExecutor : public Executor {
     SlotInfo &s = slots_[slot];
     s.nq = r.nq;
     s.ngates = r.ngates;
+    s.kmat.resize(r.ngates);
+    for (int g = 0; g < r.ngates; ++g) s.kmat[g] = {bg[g].k, bg[g].mat_off};
     s.state_off = (int64_t)(off / 16);
     s.gate_off = (int64_t)((off + sbytes) / 64);
     if (!staged) {
@@ -168,20 +169,20 @@ class HipExecutor : public Executor {
     if (sticky_) return sticky_fail();
     const int n = (int)items.size();
     if (n < 1 || n > max_slots_) return bail(fail(QCW_EINVAL, "server: tick of %d items", n));
-    // Tables behind the staged requests: [uploads | gathers | instances | items].
+    // Tables behind the staged requests: [uploads | gathers | items].
     const uint64_t t_up = blob_used_;
     const uint64_t t_ga = t_up + round256(ups_.size() * sizeof(CopyEnt));
-    const uint64_t t_in = t_ga + round256((uint64_t)n * sizeof(CopyEnt));
-    const uint64_t t_it = t_in + round256((uint64_t)n * sizeof(BInst));
+    const uint64_t t_it = t_ga + round256((uint64_t)n * sizeof(CopyEnt));
     const uint64_t t_end = t_it + round256((uint64_t)n * sizeof(BItem));
     fill_uploads((CopyEnt *)(stage_h_ + t_up));
-    BInst *inst_h = (BInst *)(stage_h_ + t_in);
     BItem *items_h = (BItem *)(stage_h_ + t_it);
     int max_nq = 1;
     for (int i = 0; i < n; ++i) {
       const SlotInfo &s = slots_[items[i].slot];
-      inst_h[i] = {s.nq, s.ngates, s.state_off, s.gate_off};
-      items_h[i] = {i, tune_.variant[s.nq], items[i].g_begin, items[i].g_end};
+      const bool any = items[i].g_begin < items[i].g_end;
+      items_h[i] = {s.nq, tune_.variant[s.nq], items[i].g_begin, items[i].g_end, s.state_off,
+                    s.gate_off, any ? s.kmat[items[i].g_begin].second : 0,
+                    any ? s.kmat[items[i].g_begin].first : 0, 0};
       max_nq = std::max(max_nq, s.nq);
     }
     // As in the batched form: exact-kernel items first, then matrix-core
@@ -189,8 +190,7 @@ class HipExecutor : public Executor {
     std::stable_sort(items_h, items_h + n, [&](const BItem &a, const BItem &b) {
       const bool ma = a.variant == kVarAmp4Mfma, mb = b.variant == kVarAmp4Mfma;
       if (ma != mb) return mb;
-      return ((int64_t)(a.g_end - a.g_begin) << inst_h[a.inst].nq) >
-             ((int64_t)(b.g_end - b.g_begin) << inst_h[b.inst].nq);
+      return ((int64_t)(a.g_end - a.g_begin) << a.nq) > ((int64_t)(b.g_end - b.g_begin) << b.nq);
     });
     int n_exact = 0;
     for (int i = 0; i < n; ++i) n_exact += items_h[i].variant != kVarAmp4Mfma;
@@ -216,7 +216,6 @@ class HipExecutor : public Executor {
     L.items = (const BItem *)(mir + t_it);
     L.nitems = n;
     L.n_exact = n_exact;
-    L.inst = (const BInst *)(mir + t_in);
     L.gates = (const BGate *)arena_;
     L.mats = (const double2 *)arena_;
     L.states = (double2 *)arena_;
@@ -250,6 +249,7 @@ class HipExecutor : public Executor {
     int nq = 0, ngates = 0;
     int64_t state_off = 0, gate_off = 0;
     uint64_t res_off = 0;  // of the final state in the result buffer
+    std::vector<std::pair<int, int64_t>> kmat;  // each gate's k and arena matrix offset
   };
   struct Upload {
     uint64_t stage_off, arena_off, bytes;

@@ -180,6 +180,34 @@ def test_graph_replays_with_eager_work_between(L):
     b.close()
 
 
+@pytest.mark.parametrize("variant", [None, "amp4_mfma"])
+def test_run_repeat_equals_single_replays(L, tmp_path, variant):
+    """reps executions in one graph launch equal reps single replays, bit for
+    bit, for the exact and the matrix-core shapes, with an oversize instance
+    (plain sweeps) in the same graph; invalid counts are rejected."""
+    inst = qi.batch(16, 60, 3, 9) + [(12, qi.state(16, 12, 9), qi.circuit(16, 12, 8, 9))]
+    tt = None
+    if variant:
+        tt = str(tmp_path / "t.txt")
+        with open(tt, "w") as f:
+            f.write("arch gfx950\n" + "".join(f"nq {q} variant {variant}\n" for q in range(1, 12)))
+    a = torch.from_numpy(_pack_states(inst)).to("cuda")
+    b = a.clone()
+    ba = L.Batch([(nq, c) for nq, _, c in inst], a, tune_table=tt)
+    bb = L.Batch([(nq, c) for nq, _, c in inst], b, tune_table=tt)
+    for reps in (3, 1, 5):
+        ba.run_repeat(reps)
+        for _ in range(reps):
+            bb.run()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), reps
+    for bad in (0, -1, 1025):
+        with pytest.raises(L.QcwError):
+            ba.run_repeat(bad)
+    ba.close()
+    bb.close()
+
+
 def test_oversize_instances_run_as_sweeps(L):
     """Instances above 11 qubits run as plain sweeps inside the same graph."""
     inst = [(12, qi.state(7, 12, 1), qi.circuit(7, 12, 10, 1)),
