@@ -182,6 +182,25 @@ enum {
 int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                          const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
                          int threads, int plan, void *stream);
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): qcw_circuit_fused_ex
+ * with the same arguments, kernels and results (bit for bit), except that the
+ * pass and gate tables of the plan are kept in a static device array of the
+ * library, 4 MiB on each GPU that the library runs on (held until the process
+ * ends), instead of a buffer allocated per stream.  The call allocates no
+ * device memory and frees none.  A plan whose tables exceed 4 MiB is rejected
+ * with QCW_EINVAL (the benchmark's 124-gate plan at 31 qubits takes about
+ * 0.16 MiB; each pass costs 8.3 KiB and each gate after in-pass fusion
+ * 1.6 KiB).  All calls on one GPU share its array, which keeps the last plan:
+ * the same request again reuses it without planning, upload or
+ * synchronisation; a new request plans, uploads on `stream` and synchronises
+ * it once.  Calls that overlap on one GPU (on different streams or threads,
+ * with different requests) race on the array.
+ */
+int qcw_circuit_fused_noalloc(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                              const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
+                              int threads, int plan, void *stream);
 /* Number of passes qcw_circuit_fused_ex makes for this gate list and plan
  * (host only; QCW_PLAN_FUSE and QCW_PLAN_3M do not change it). */
 int qcw_fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits,

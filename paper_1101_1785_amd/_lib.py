@@ -67,6 +67,8 @@ _SIGS = {
     "qcw_circuit": ([_P, _i32, _P, _i32, _P, _i64, _P], _i32),
     "qcw_circuit_fused": ([_P, _i32, _P, _i32, _P, _i64, _i32, _P], _i32),
     "qcw_circuit_fused_ex": ([_P, _i32, _P, _i32, _P, _i64, _i32, _i32, _i32, _i32, _P], _i32),
+    "qcw_circuit_fused_noalloc": ([_P, _i32, _P, _i32, _P, _i64, _i32, _i32, _i32, _i32, _P],
+                                  _i32),
     "qcw_fused_pass_count": ([_i32, _P, _i32, _i32, _i32, _i32], _i32),
     "qcw_fused_plan": ([_i32, _P, _i32, _i32, _i32, _i32, _P, _P], _i32),
     "qcw_debug_pick_device": ([_i32, _i32, _P, _P], _i32),

@@ -880,8 +880,95 @@ static std::vector<char> plan_signature(int nq, int T, int L, int plan, const qc
   return sig;
 }
 
+// ------------------------------------------------------------ no-allocation tables
+// qcw_circuit_fused_noalloc keeps its pass and gate tables in this file-scope
+// device array instead of a buffer allocated per stream: one copy per GPU,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not a device address; the array's address on each GPU comes from
+// hipGetSymbolAddress (scratch_state), and only that address is handed to
+// copies and kernels.  Every call on a GPU shares its copy: each call writes
+// the whole region its kernels read (nothing needs to start at zero), and
+// calls that overlap on one GPU race.
+constexpr size_t kScratchBytes = 4u << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+struct ScratchState {
+  void *ptr = nullptr;    // device address of `scratch` on this GPU
+  std::vector<char> sig;  // request whose plan the array holds (empty: none)
+  size_t pbytes = 0;
+  int npass = 0;
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchState> g_scratch;  // per device
+}  // namespace
+
+// The current GPU's scratch state; its address is looked up on the first call
+// on that GPU (with it current).  The caller holds g_scratch_mu.
+static int scratch_state(ScratchState **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QCW_EHIP, "cannot query the device");
+  }
+  ScratchState &st = g_scratch[dev];
+  if (!st.ptr) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(QCW_EHIP, "device address of the no-allocation buffer: %s", hipGetErrorString(e));
+    }
+    st.ptr = p;
+  }
+  *out = &st;
+  return QCW_OK;
+}
+
+// Places a plan in the current GPU's scratch array (no allocation): reuses it
+// when the array already holds this request's plan, else plans, checks the
+// size and uploads it on stream s (synchronising s, as upload_plan does).
+static int place_plan_in_scratch(int nq, const std::vector<Geom> &geo, const qcw_gate *gates,
+                                 const qcw_c64 *mats, FusedShape sh, int plan,
+                                 std::vector<char> &&sig, hipStream_t s, const FusedPass **dp,
+                                 const FusedGate **dg, int *np) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  ScratchState *st = nullptr;
+  int rc = scratch_state(&st);
+  if (rc) return rc;
+  if (st->sig.empty() || st->sig != sig) {
+    std::vector<FusedPass> passes;
+    std::vector<FusedGate> fg;
+    if ((rc = plan_passes(nq, geo, gates, mats, sh, plan, passes, fg))) return rc;
+    const size_t pbytes = passes.size() * sizeof(FusedPass);
+    const size_t need = pbytes + fg.size() * sizeof(FusedGate);
+    if (need > kScratchBytes)
+      return fail(QCW_EINVAL,
+                  "the plan's tables (%zu passes, %zu gates: %zu B) exceed the %zu B "
+                  "no-allocation buffer; use qcw_circuit_fused_ex",
+                  passes.size(), fg.size(), need, kScratchBytes);
+    st->sig.clear();  // until the new plan has landed
+    std::vector<char> blob(need);
+    memcpy(blob.data(), passes.data(), pbytes);
+    memcpy(blob.data() + pbytes, fg.data(), fg.size() * sizeof(FusedGate));
+    if (hipMemcpyAsync(st->ptr, blob.data(), need, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(QCW_EHIP, "upload of the plan into the no-allocation buffer");
+    }
+    st->sig = std::move(sig);
+    st->pbytes = pbytes;
+    st->npass = (int)passes.size();
+  }
+  *dp = (const FusedPass *)st->ptr;
+  *dg = (const FusedGate *)((char *)st->ptr + st->pbytes);
+  *np = st->npass;
+  return QCW_OK;
+}
+
 int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, int low_bits, int threads, int plan, hipStream_t s) {
+              int tile_bits, int low_bits, int threads, int plan, hipStream_t s,
+              bool in_scratch) {
   std::vector<Geom> geo(ngates);
   for (int i = 0; i < ngates; ++i) {
     int rc = make_geom(nq, gates[i].k, gates[i].q, &geo[i]);
@@ -903,22 +990,28 @@ int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw
   const FusedGate *dg = nullptr;
   int np = 0;
   std::vector<char> sig = plan_signature(nq, T, L, plan, gates, ngates, mats);
-  {
-    std::lock_guard<std::mutex> lk(g_plan_mu);
-    PlanBuf &b = g_plan_bufs[s];
-    if (!b.sig.empty() && b.sig == sig) {
-      dp = (const FusedPass *)b.dev;
-      dg = (const FusedGate *)((char *)b.dev + b.pbytes);
-      np = b.npass;
-    }
-  }
-  if (!dp) {
-    std::vector<FusedPass> passes;
-    std::vector<FusedGate> fg;
-    int rc = plan_passes(nq, geo, gates, mats, FusedShape{T, L}, plan, passes, fg);
+  if (in_scratch) {
+    int rc = place_plan_in_scratch(nq, geo, gates, mats, FusedShape{T, L}, plan, std::move(sig),
+                                   s, &dp, &dg, &np);
     if (rc) return rc;
-    if ((rc = upload_plan(passes, fg, s, std::move(sig), &dp, &dg))) return rc;
-    np = (int)passes.size();
+  } else {
+    {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      PlanBuf &b = g_plan_bufs[s];
+      if (!b.sig.empty() && b.sig == sig) {
+        dp = (const FusedPass *)b.dev;
+        dg = (const FusedGate *)((char *)b.dev + b.pbytes);
+        np = b.npass;
+      }
+    }
+    if (!dp) {
+      std::vector<FusedPass> passes;
+      std::vector<FusedGate> fg;
+      int rc = plan_passes(nq, geo, gates, mats, FusedShape{T, L}, plan, passes, fg);
+      if (rc) return rc;
+      if ((rc = upload_plan(passes, fg, s, std::move(sig), &dp, &dg))) return rc;
+      np = (int)passes.size();
+    }
   }
   switch (T) {
     case 8: return launch_passes_l<8, 256>(L, psi, nq, dp, dg, np, s);
@@ -963,9 +1056,9 @@ using namespace qcw;
 
 extern "C" {
 
-int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
-                         const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
-                         int threads, int plan, void *stream) {
+static int fused_entry(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                       const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
+                       int threads, int plan, void *stream, bool in_scratch) {
   clear_error();
   if (plan & ~(QCW_PLAN_COMMUTE | QCW_PLAN_FUSE | QCW_PLAN_3M))
     return fail(QCW_EINVAL, "plan=%d has bits other than QCW_PLAN_COMMUTE, QCW_PLAN_FUSE and QCW_PLAN_3M", plan);
@@ -995,7 +1088,21 @@ int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates
   int rc = check_device_range(psi, ((uint64_t)1 << nq) * sizeof(qcw_c64), "psi");
   if (rc) return rc;
   return run_fused(psi, nq, gates, ngates, mats, tile_bits, low_bits, threads, plan,
-                   (hipStream_t)stream);
+                   (hipStream_t)stream, in_scratch);
+}
+
+int qcw_circuit_fused_ex(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                         const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
+                         int threads, int plan, void *stream) {
+  return fused_entry(psi, nq, gates, ngates, mats, nmats, tile_bits, low_bits, threads, plan,
+                     stream, false);
+}
+
+int qcw_circuit_fused_noalloc(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
+                              const qcw_c64 *mats, int64_t nmats, int tile_bits, int low_bits,
+                              int threads, int plan, void *stream) {
+  return fused_entry(psi, nq, gates, ngates, mats, nmats, tile_bits, low_bits, threads, plan,
+                     stream, true);
 }
 
 int qcw_circuit_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,

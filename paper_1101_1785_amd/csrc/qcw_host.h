@@ -31,8 +31,11 @@ int launch_sweep(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *ou
                  hipStream_t s);
 int launch_pick(const Geom &g, uint64_t *labels_dev, hipStream_t s);
 // Fused passes (fused.hip).
+// in_scratch: the plan tables go into the library's static per-GPU array
+// (qcw_circuit_fused_noalloc) instead of a per-stream allocation.
 int run_fused(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const qcw_c64 *mats,
-              int tile_bits, int low_bits, int threads, int plan, hipStream_t s);
+              int tile_bits, int low_bits, int threads, int plan, hipStream_t s,
+              bool in_scratch = false);
 // Pass count of a plan; when non-NULL, pass_of[g] receives gate g's pass and
 // order[] the gate indices in execution order.
 int fused_pass_count(int nq, const qcw_gate *gates, int ngates, int tile_bits, int low_bits,

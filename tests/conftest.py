@@ -13,7 +13,9 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # Run GPU tests in file order but keep the slow full-size cases last.
-    slow = [i for i in items if "fullsize" in i.nodeid]
-    rest = [i for i in items if "fullsize" not in i.nodeid]
-    items[:] = rest + slow
+    # Run GPU tests in file order but keep the slow full-size cases late, and
+    # the test_zz_* files after them (they must also pass after everything else).
+    last = [i for i in items if "test_zz_" in i.nodeid]
+    slow = [i for i in items if "fullsize" in i.nodeid and i not in last]
+    rest = [i for i in items if i not in last and i not in slow]
+    items[:] = rest + slow + last
