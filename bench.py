@@ -416,7 +416,7 @@ def bench_serving_sweep(torch, L, qi, tt, seconds, rates=(2000, 8000, 12000, 160
                       "~1/client_submit_us the client, not the server, sets the rate"}
 
 
-def bench_serving_native(L, qi, tt, seconds, rates=(16000, 32000, 64000, 96000),
+def bench_serving_native(L, qi, tt, seconds, rates=(16000, 32000, 64000, 96000, 128000, 192000),
                          clients=2, pool=4096, seed=3, lo=3, hi=9):
     """Config 3 driven by the native open-loop load generator (serve_load, built
     beside the library): requests submitted from `clients` C++ threads at

@@ -69,6 +69,7 @@ ServerCore::ServerCore(const ServerConfig &cfg, std::unique_ptr<Executor> ex)
   slots_.resize(cfg_.max_slots);
   for (int i = cfg_.max_slots - 1; i >= 0; --i) free_slots_.push_back(i);
   thr_ = std::thread([this] { loop(); });
+  waiter_ = std::thread([this] { wait_ticks(); });
 }
 
 ServerCore::~ServerCore() { stop(); }
@@ -79,7 +80,9 @@ void ServerCore::stop() {
     stop_ = true;
   }
   cv_work_.notify_all();
+  cv_tick_.notify_all();
   if (thr_.joinable()) thr_.join();
+  if (waiter_.joinable()) waiter_.join();
   std::lock_guard<std::mutex> lk(mu_);
   // Requests still queued or resident when the loop stops fail.
   for (auto &kv : reqs_)
@@ -229,14 +232,57 @@ void ServerCore::admit_locked() {
   }
 }
 
+namespace {
+constexpr uint64_t kAdmitBatch = 32;
+constexpr std::chrono::microseconds kAdmitDelay(100);
+}  // namespace
+
+// One tick in flight at a time.  While it runs, the scheduler keeps admitting
+// arrivals (packing them for upload: the executor's load), so admission work
+// overlaps the GPU work; when the waiter thread reports the tick done, the
+// scheduler completes its finishing requests (their slots and arena regions
+// are freed only now), plans the next tick over every resident request and
+// launches it.
 void ServerCore::loop() {
-  std::vector<TickItem> items;
+  std::vector<TickItem> next, inflight;
+  bool running = false;
   for (;;) {
-    items.clear();
+    next.clear();
     {
       std::unique_lock<std::mutex> lk(mu_);
-      cv_work_.wait(lk, [&] { return stop_ || !pending_.empty() || active_ > 0; });
-      if (stop_) return;
+      if (!running) {
+        cv_work_.wait(lk, [&] { return stop_ || !pending_.empty() || active_ > 0; });
+      } else {
+        // While the tick runs, arrivals are admitted in batches: when
+        // kAdmitBatch of them have come, or kAdmitDelay after the wait began
+        // if any have (one wake-up per arrival would cost more lock traffic
+        // than the packing it moves off the critical path).
+        cv_work_.wait(lk, [&] {
+          return stop_ || tick_done_ || ctr_.submitted != seen_submitted_;
+        });
+        if (!stop_ && !tick_done_) {
+          const auto deadline = std::chrono::steady_clock::now() + kAdmitDelay;
+          cv_work_.wait_until(lk, deadline, [&] {
+            return stop_ || tick_done_ || ctr_.submitted - seen_submitted_ >= kAdmitBatch;
+          });
+        }
+      }
+      if (stop_) {
+        // the tick in flight must end before the executor may go away
+        cv_work_.wait(lk, [&] { return !running || tick_done_; });
+        return;
+      }
+      if (running && !tick_done_) {
+        seen_submitted_ = ctr_.submitted;
+        admit_locked();
+        continue;
+      }
+      if (running) {
+        complete_locked(inflight, tick_rc_);
+        running = false;
+        tick_done_ = false;
+      }
+      seen_submitted_ = ctr_.submitted;
       admit_locked();
       for (int i = 0; i < (int)slots_.size(); ++i) {
         Slot &s = slots_[i];
@@ -244,36 +290,69 @@ void ServerCore::loop() {
         ServeRequest &q = *reqs_[s.ticket];
         int end = q.ngates;
         if (cfg_.gates_per_tick > 0) end = std::min(q.ngates, s.progress + cfg_.gates_per_tick);
-        items.push_back({i, s.progress, end, end == q.ngates});
+        next.push_back({i, s.progress, end, end == q.ngates});
+        s.progress = end;
       }
     }
-    if (items.empty()) continue;
-    const int rc = ex_->tick(items);
+    if (next.empty()) continue;
+    const int rc = ex_->launch(next);
     std::lock_guard<std::mutex> lk(mu_);
-    ctr_.ticks++;
-    const uint64_t t = now_ns();
-    for (const TickItem &it : items) {
-      Slot &s = slots_[it.slot];
-      ServeRequest &q = *reqs_[s.ticket];
-      q.ticks++;
-      s.progress = it.g_end;
-      if (rc == QCW_OK && !it.finishes) continue;
-      if (rc == QCW_OK) {
-        q.result.resize((size_t)1 << q.nq);
-        q.status = ex_->fetch(it.slot, q.nq, q.result.data());
-      } else {
-        q.status = rc;
-      }
-      q.t_done = t;
-      ctr_.completed++;
-      arena_.free(s.off, s.bytes);
-      s.used = false;
-      free_slots_.push_back(it.slot);
-      ex_->release(it.slot);
-      active_--;
+    if (rc) {
+      complete_locked(next, rc);
+      continue;
     }
-    cv_done_.notify_all();
+    inflight.swap(next);
+    running = true;
+    tick_launched_ = true;
+    cv_tick_.notify_one();
   }
+}
+
+// The waiter: blocks in Executor::finish() for each launched tick, then hands
+// its status to the scheduler.
+void ServerCore::wait_ticks() {
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_tick_.wait(lk, [&] { return tick_launched_ || stop_; });
+      if (!tick_launched_) return;  // stopping with no tick in flight
+      tick_launched_ = false;
+    }
+    const int rc = ex_->finish();
+    std::lock_guard<std::mutex> lk(mu_);
+    tick_rc_ = rc;
+    tick_done_ = true;
+    cv_work_.notify_all();
+  }
+}
+
+// Bookkeeping after a tick (rc: its status): finishing requests get their
+// results (or the error) and release their slots; with an error every request
+// of the tick fails.
+void ServerCore::complete_locked(const std::vector<TickItem> &items, int rc) {
+  ctr_.ticks++;
+  const uint64_t t = now_ns();
+  for (const TickItem &it : items) {
+    Slot &s = slots_[it.slot];
+    if (!s.used) continue;
+    ServeRequest &q = *reqs_[s.ticket];
+    q.ticks++;
+    if (rc == QCW_OK && !it.finishes) continue;
+    if (rc == QCW_OK) {
+      q.result.resize((size_t)1 << q.nq);
+      q.status = ex_->fetch(it.slot, q.nq, q.result.data());
+    } else {
+      q.status = rc;
+    }
+    q.t_done = t;
+    ctr_.completed++;
+    arena_.free(s.off, s.bytes);
+    s = Slot{};
+    free_slots_.push_back(it.slot);
+    ex_->release(it.slot);
+    active_--;
+  }
+  cv_done_.notify_all();
 }
 
 }  // namespace qcw

@@ -52,12 +52,17 @@ class Executor {
     (void)r;
     return QCW_OK;
   }
-  // Copies an admitted request into the arena at `off` (its own region).
+  // Copies an admitted request into the arena at `off` (its own region).  It
+  // may be called while a launched tick runs: the copy must then not disturb
+  // that tick, and it reaches the arena no later than the next launch.
   virtual int load(int slot, uint64_t off, const ServeRequest &r) = 0;
-  // Runs one tick: every listed slot advances over its gate range; the states
-  // of finishing slots are copied out.  Returns when the tick is complete.
-  virtual int tick(const std::vector<TickItem> &items) = 0;
-  // The final state of a slot that finished in the last tick.
+  // Starts one tick: every listed slot advances over its gate range and the
+  // states of finishing slots are copied out.  Returns without waiting; at
+  // most one tick is in flight, and finish() is called before the next launch.
+  virtual int launch(const std::vector<TickItem> &items) = 0;
+  // Waits for the launched tick; its results can then be fetched.
+  virtual int finish() = 0;
+  // The final state of a slot that finished in the last finished tick.
   virtual int fetch(int slot, int nq, qcw_c64 *out) = 0;
   // Releases a slot (its arena region is free again).
   virtual void release(int slot) = 0;
@@ -104,12 +109,14 @@ class ServerCore {
 
  private:
   void loop();
+  void wait_ticks();
   void admit_locked();
+  void complete_locked(const std::vector<TickItem> &items, int rc);
   struct Slot {
     bool used = false;
     uint64_t ticket = 0;
     uint64_t off = 0, bytes = 0;
-    int progress = 0;
+    int progress = 0;  // gates covered by the ticks launched so far
   };
   ServerConfig cfg_;
   std::unique_ptr<Executor> ex_;
@@ -124,7 +131,13 @@ class ServerCore {
   bool stop_ = false;
   int active_ = 0;
   ServerCounters ctr_;
-  std::thread thr_;
+  // The tick in flight: the scheduler launches it and goes on admitting
+  // arrivals; the waiter thread blocks in Executor::finish() and reports.
+  bool tick_launched_ = false, tick_done_ = false;
+  int tick_rc_ = QCW_OK;
+  uint64_t seen_submitted_ = 0;  // submissions the scheduler has looked at
+  std::condition_variable cv_tick_;
+  std::thread thr_, waiter_;
 };
 
 }  // namespace qcw

@@ -6,18 +6,21 @@
 //
 // Host traffic is batched per tick.  Admission packs each request's region,
 // laid out as in the arena, into a pinned staging buffer and returns without
-// touching the GPU.  A tick then appends its small tables (copy lists,
-// instances, work items) behind the staged requests and issues, on one
-// stream: one host-to-device copy of the staging buffer into its device
-// mirror, a copy-list kernel that scatters the staged requests into their
-// arena regions, ONE persistent batch launch (the same kernel as
-// qcw_batch_run) over the resident requests, a copy-list kernel that gathers
-// the states of finishing requests into one contiguous buffer, one
-// device-to-host copy of that buffer into pinned memory, and one wait.
+// touching the GPU.  A tick then appends its small tables (copy lists, work
+// items) behind the staged requests and issues, on one stream: one
+// host-to-device copy of the staging buffer into its device mirror, a
+// copy-list kernel that scatters the staged requests into their arena
+// regions, ONE persistent batch launch (the same kernel as qcw_batch_run) over
+// the resident requests, a copy-list kernel that gathers the states of
+// finishing requests into one contiguous buffer, one device-to-host copy of
+// that buffer into pinned memory, and an event.  The launch returns; the
+// scheduler packs the next tick's requests into a second staging buffer while
+// this one runs, and waits for the event before the next launch.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <memory>
 #include <vector>
 
@@ -59,10 +62,12 @@ class HipExecutor : public Executor {
   ~HipExecutor() override {
     if (stream_) (void)hipStreamSynchronize(stream_);
     (void)hipFree(arena_);
-    (void)hipFree(mirror_d_);
     (void)hipFree(res_d_);
     (void)hipFree(counter_d_);
-    (void)hipHostFree(stage_h_);
+    for (int b = 0; b < 2; ++b) {
+      (void)hipFree(mirror_buf_[b]);
+      (void)hipHostFree(stage_buf_[b]);
+    }
     (void)hipHostFree(result_h_);
     if (done_) (void)hipEventDestroy(done_);
     if (stream_) (void)hipStreamDestroy(stream_);
@@ -86,13 +91,17 @@ class HipExecutor : public Executor {
     table_cap_ = 2 * round256(ms * sizeof(CopyEnt)) + round256(ms * sizeof(BItem));
     if (hipMalloc(&arena_, std::max<uint64_t>(arena_bytes_, 256)) != hipSuccess)
       return mem_fail("arena", arena_bytes_);
-    if (hipMalloc(&mirror_d_, blob_cap_ + table_cap_) != hipSuccess ||
-        hipMalloc(&res_d_, std::max<uint64_t>(res_cap_, 256)) != hipSuccess ||
+    for (int b = 0; b < 2; ++b)
+      if (hipMalloc(&mirror_buf_[b], blob_cap_ + table_cap_) != hipSuccess ||
+          hipHostMalloc(&stage_buf_[b], blob_cap_ + table_cap_) != hipSuccess)
+        return mem_fail("staging buffers", 2 * (blob_cap_ + table_cap_));
+    stage_h_ = stage_buf_[0];
+    mirror_d_ = mirror_buf_[0];
+    if (hipMalloc(&res_d_, std::max<uint64_t>(res_cap_, 256)) != hipSuccess ||
         hipMalloc(&counter_d_, 2 * sizeof(int)) != hipSuccess)
-      return mem_fail("staging and tables", blob_cap_ + table_cap_ + res_cap_);
-    if (hipHostMalloc(&stage_h_, blob_cap_ + table_cap_) != hipSuccess ||
-        hipHostMalloc(&result_h_, std::max<uint64_t>(res_cap_, 256)) != hipSuccess)
-      return mem_fail("pinned host buffers", blob_cap_ + table_cap_ + res_cap_);
+      return mem_fail("result and counters", res_cap_);
+    if (hipHostMalloc(&result_h_, std::max<uint64_t>(res_cap_, 256)) != hipSuccess)
+      return mem_fail("pinned result buffer", res_cap_);
     slots_.resize(max_slots_);
     ups_.reserve(max_slots_);
     return QCW_OK;
@@ -164,7 +173,7 @@ class HipExecutor : public Executor {
     return QCW_OK;
   }
 
-  int tick(const std::vector<TickItem> &items) override {
+  int launch(const std::vector<TickItem> &items) override {
     (void)hipSetDevice(dev_);
     if (sticky_) return sticky_fail();
     const int n = (int)items.size();
@@ -230,11 +239,22 @@ class HipExecutor : public Executor {
                                     stream_) != hipSuccess)
       return bail(hip_fail("result copy"));
     if (hipEventRecord(done_, stream_) != hipSuccess) return bail(hip_fail("event record"));
-    if (hipEventSynchronize(done_) != hipSuccess) return bail(hip_fail("tick"));
+    // Requests admitted while this tick runs are packed into the other staging
+    // buffer; the tick before this one finished with it (finish() precedes
+    // every launch).
+    cur_ ^= 1;
+    stage_h_ = stage_buf_[cur_];
+    mirror_d_ = mirror_buf_[cur_];
     ups_.clear();
     up_max_ = 0;
-    blob_used_ = 0;  // the staging buffer is free again once the tick is done
+    blob_used_ = 0;
     return QCW_OK;
+  }
+
+  int finish() override {
+    (void)hipSetDevice(dev_);
+    if (hipEventSynchronize(done_) != hipSuccess) return bail(hip_fail("tick"));
+    return sticky_ ? sticky_fail() : QCW_OK;
   }
 
   int fetch(int slot, int nq, qcw_c64 *out) override {
@@ -301,7 +321,8 @@ class HipExecutor : public Executor {
   // tick fails.  The staged uploads are dropped, so none can land in arena
   // regions that the scheduler hands out again.
   int sticky_set(int rc) {
-    if (!sticky_) sticky_ = rc;
+    int ok = QCW_OK;
+    sticky_.compare_exchange_strong(ok, rc);
     return rc;
   }
   int bail(int rc) {
@@ -350,10 +371,14 @@ class HipExecutor : public Executor {
   hipEvent_t done_ = nullptr;
   void *arena_ = nullptr;
   uint64_t arena_bytes_ = 0;
-  // Staging: requests packed since the last tick [0, blob_used_), then the
-  // tick's tables; mirror_d_ is its device copy.
-  char *stage_h_ = nullptr;
-  void *mirror_d_ = nullptr;
+  // Staging: requests packed since the last launch [0, blob_used_), then the
+  // tick's tables; mirror_d_ is its device copy.  Two such buffers in turn, so
+  // requests are packed into one while the tick launched from the other runs.
+  char *stage_buf_[2] = {nullptr, nullptr};
+  void *mirror_buf_[2] = {nullptr, nullptr};
+  int cur_ = 0;
+  char *stage_h_ = nullptr;  // = stage_buf_[cur_]
+  void *mirror_d_ = nullptr; // = mirror_buf_[cur_]
   uint64_t blob_cap_ = 0, table_cap_ = 0, blob_used_ = 0, up_max_ = 0;
   std::vector<Upload> ups_;
   // Final states of the last tick's finishing requests.
@@ -361,7 +386,7 @@ class HipExecutor : public Executor {
   qcw_c64 *result_h_ = nullptr;
   uint64_t res_cap_ = 0;
   int *counter_d_ = nullptr;
-  int sticky_ = QCW_OK;
+  std::atomic<int> sticky_{QCW_OK};  // read by the waiter thread in finish()
   std::vector<SlotInfo> slots_;
   PlanCache plans_[kBatchMaxNq + 1];
 };

@@ -47,16 +47,28 @@ class FakeExecutor : public Executor {
     st_[slot] = r.psi0;
     return QCW_OK;
   }
-  int tick(const std::vector<TickItem> &items) override {
-    {
-      std::lock_guard<std::mutex> lk(sh_->mu);
-      sh_->ticks++;
-      sh_->max_tick = std::max(sh_->max_tick, (int)items.size());
-      for (const TickItem &it : items)
-        if (!sh_->resident.count(it.slot) || it.g_begin > it.g_end) sh_->violations++;
+  // A tick may only list resident slots, each continuing exactly where its
+  // previous tick left it; at most one tick is in flight.
+  int launch(const std::vector<TickItem> &items) override {
+    std::lock_guard<std::mutex> lk(sh_->mu);
+    if (inflight_) sh_->violations++;
+    inflight_ = true;
+    sh_->ticks++;
+    sh_->max_tick = std::max(sh_->max_tick, (int)items.size());
+    for (const TickItem &it : items) {
+      if (!sh_->resident.count(it.slot) || it.g_begin > it.g_end) sh_->violations++;
+      auto p = progress_.find(it.slot);
+      if (it.g_begin != (p == progress_.end() ? 0 : p->second)) sh_->violations++;
+      progress_[it.slot] = it.g_end;
     }
+    return QCW_OK;
+  }
+  int finish() override {
     if (sh_->tick_seconds > 0)
       std::this_thread::sleep_for(std::chrono::duration<double>(sh_->tick_seconds));
+    std::lock_guard<std::mutex> lk(sh_->mu);
+    if (!inflight_) sh_->violations++;
+    inflight_ = false;
     return QCW_OK;
   }
   int fetch(int slot, int nq, qcw_c64 *out) override {
@@ -66,11 +78,14 @@ class FakeExecutor : public Executor {
   void release(int slot) override {
     std::lock_guard<std::mutex> lk(sh_->mu);
     sh_->resident.erase(slot);
+    progress_.erase(slot);
   }
 
  private:
   std::shared_ptr<Shared> sh_;
   std::vector<std::vector<qcw_c64>> st_;
+  std::map<int, int> progress_;  // slot -> gates covered by launched ticks
+  bool inflight_ = false;
 };
 
 struct Harness {

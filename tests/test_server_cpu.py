@@ -180,3 +180,28 @@ def test_stop_fails_pending_without_hanging(lib):
     codes = [s.poll(t, 4)[0] for t in ts]
     assert all(c in (OK, EINVAL) for c in codes) and EINVAL in codes
     s.close()
+
+
+def test_admission_overlaps_the_running_tick(lib):
+    """A request that arrives while another request's tick runs is admitted
+    (packed for upload) before that tick finishes, and runs in the tick right
+    after it; gate ranges stay contiguous per slot (the double counts any
+    break as a violation)."""
+    s = FakeServer(lib, max_slots=8, gates_per_tick=3, tick_seconds=0.05)
+    g, m, p = _req(5, 12, 11)
+    rc, ta = s.submit(5, g, m, p)
+    assert rc == OK
+    import time
+    time.sleep(0.02)                 # A's first tick (of four) is running
+    rc, tb = s.submit(5, g, m, p)
+    assert rc == OK
+    ra, _, sa = s.wait(ta, 5)
+    rb, _, sb = s.wait(tb, 5)
+    assert ra == OK and rb == OK
+    # A takes four ticks of 50 ms; B, admitted during A's first, finishes one
+    # tick after A (not two: its first tick is launched right after A's first)
+    assert sb.t_admit_ns < sa.t_admit_ns + 50_000_000
+    assert sa.ticks == 4 and sb.ticks == 4
+    assert sb.t_done_ns - sa.t_done_ns < 75_000_000
+    assert s.violations() == 0
+    s.close()
