@@ -284,7 +284,9 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
     int v = variant_override ? variant_override[in.nq] : b->tune.variant[in.nq];
     items.push_back({in.nq, v, 0, in.ngates, in.state_off, in.gate_off,
                      in.ngates > 0 ? gates[in.gate_off].mat : 0,
-                     in.ngates > 0 ? gates[in.gate_off].k : 0, 0});
+                     in.ngates > 1 ? gates[in.gate_off + 1].mat : 0,
+                     in.ngates > 0 ? gates[in.gate_off].k : 0,
+                     in.ngates > 1 ? gates[in.gate_off + 1].k : 0, {0, 0}});
     item_inst.push_back(i);
   }
   // Instances on the matrix-core variant (already exact only to rounding) run
@@ -320,12 +322,17 @@ static int batch_build(qcw_batch *b, const qcw_instance *inst, int n, const qcw_
     it.gate_off = in.gate_off;
     it.g_end = in.ngates;
   }
-  // the first gate's matrix, for the matrix-core kernel (offsets into m2)
+  // the first two gates' matrices, for the matrix-core kernel (offsets into m2)
   for (BItem &it : items) {
     if (it.variant != kVarAmp4Mfma || it.g_end <= it.g_begin) continue;
     const BGate &g0 = bg[it.gate_off + it.g_begin];
     it.mat0 = g0.mat_off;
     it.k0 = g0.k;
+    if (it.g_end - it.g_begin > 1) {
+      const BGate &g1 = bg[it.gate_off + it.g_begin + 1];
+      it.mat1 = g1.mat_off;
+      it.k1 = g1.k;
+    }
   }
   // Exact-kernel items first, then matrix-core items; most work first in each.
   std::stable_sort(items.begin(), items.end(), [&](const BItem &x, const BItem &y) {

@@ -32,6 +32,21 @@ __device__ __forceinline__ void load_state(double2 *S, const double2 *st, uint32
     S[n0 + 384 + lane] = v6;
     S[n0 + 448 + lane] = v7;
   }
+  if (n0 == 0) {
+    // 2^nq <= 256 (at most four amplitudes per lane): every load issued
+    // before any LDS store, in named registers (an array here went to scratch)
+    const uint32_t a = lane, b = 64 + lane, c = 128 + lane, d = 192 + lane;
+    double2 va = make_double2(0.0, 0.0), vb = va, vc = va, vd = va;
+    if (a < N) va = st[a];
+    if (b < N) vb = st[b];
+    if (c < N) vc = st[c];
+    if (d < N) vd = st[d];
+    if (a < N) S[a] = va;
+    if (b < N) S[b] = vb;
+    if (c < N) S[c] = vc;
+    if (d < N) S[d] = vd;
+    return;
+  }
   for (uint32_t n = n0 + lane; n < N; n += 64) S[n] = st[n];
 }
 

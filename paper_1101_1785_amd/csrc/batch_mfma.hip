@@ -82,8 +82,9 @@ __device__ __forceinline__ void preload_desc(const BItem &in, const BGate *__res
 }
 
 __device__ void run_mfma_preloaded(const BItem &in, const uint32_t (&dv)[4],
-                                   const mc::Operands &first, const double2 *__restrict__ mats,
-                                   double2 *S, int lane, uint32_t N) {
+                                   const mc::Operands &first, const mc::Operands &second,
+                                   const double2 *__restrict__ mats, double2 *S, int lane,
+                                   uint32_t N) {
   const int ng = in.g_end - in.g_begin;
   auto operands = [&](int r) {
     const uint32_t d = pre_desc(dv, r);
@@ -103,7 +104,7 @@ __device__ void run_mfma_preloaded(const BItem &in, const uint32_t (&dv)[4],
     mc::apply(S, 0, N >> f.k, f, u0, u1, lane);
   };
   mc::Operands oa = first;
-  mc::Operands ob = operands(min(1, ng - 1));
+  mc::Operands ob = second;
   int r = 0;
   for (; r + 1 < ng; r += 2) {
     step(r, oa);
@@ -143,13 +144,14 @@ __device__ void run_mfma_instance(const BItem &in, const BGate *__restrict__ gat
   double2 *st = states + in.state_off;
   const int ng = in.g_end - in.g_begin;
   if (ng > 0 && ng <= kPreGates) {
-    // the first gate's operands come straight from the item, beside the
-    // descriptor and state loads
+    // the first two gates' operands come straight from the item, beside the
+    // descriptor and state loads (one gate: the first gate's again)
     const mc::Operands first = mc::fetch_operands(in.k0, mats + in.mat0, lane);
+    const mc::Operands second = ng > 1 ? mc::fetch_operands(in.k1, mats + in.mat1, lane) : first;
     uint32_t dv[4];
     preload_desc(in, gates, lane, dv);
     load_state(S, st, N, lane);
-    run_mfma_preloaded(in, dv, first, mats, S, lane, N);
+    run_mfma_preloaded(in, dv, first, second, mats, S, lane, N);
   } else {
     load_state(S, st, N, lane);
     if (ng > 0) run_mfma_streamed(in, gates, mats, S, lane, N);
@@ -160,7 +162,7 @@ __device__ void run_mfma_instance(const BItem &in, const BGate *__restrict__ gat
 
 // One persistent launch over the matrix-core items.  Each wavefront owns
 // `wave_amps` amplitudes of dynamic LDS (no matrix slots).
-__global__ __launch_bounds__(kBatchBlock) void batch_mfma_kernel(
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) void batch_mfma_kernel(
     const BItem *__restrict__ items, int nitems, const BGate *__restrict__ gates,
     const double2 *__restrict__ mats, double2 *__restrict__ states, int *__restrict__ counter,
     int wave_amps) {

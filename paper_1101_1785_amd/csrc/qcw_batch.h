@@ -43,8 +43,9 @@ struct alignas(16) BGate {  // gate with its geometry precomputed on the host
 };
 static_assert(sizeof(BGate) == 64, "BGate layout");
 
-// A work item carries its instance's fields and the first gate's matrix, so
-// a wave issues its state, descriptor and first operand loads at once.
+// A work item carries its instance's fields and the first two gates'
+// matrices, so a wave issues its state, descriptor and first operand loads
+// at once.
 struct alignas(16) BItem {
   int32_t nq;
   int32_t variant;    // BatchVariant
@@ -52,11 +53,11 @@ struct alignas(16) BItem {
   int32_t g_end;
   int64_t state_off;  // in complex elements
   int64_t gate_off;   // index of the instance's first gate
-  int64_t mat0;       // matrix offset of gate g_begin (0 when the range is empty)
-  int32_t k0;         // its qubit count
-  int32_t pad;
+  int64_t mat0, mat1;  // matrix offsets of gates g_begin and g_begin + 1 (0: no such gate)
+  int32_t k0, k1;      // their qubit counts
+  int32_t pad[2];
 };
-static_assert(sizeof(BItem) == 48, "BItem layout");
+static_assert(sizeof(BItem) == 64, "BItem layout");
 
 // Grid of one of the two persistent kernels.
 struct BatchShape {

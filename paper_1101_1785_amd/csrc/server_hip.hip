@@ -188,10 +188,11 @@ class HipExecutor : public Executor {
     int max_nq = 1;
     for (int i = 0; i < n; ++i) {
       const SlotInfo &s = slots_[items[i].slot];
-      const bool any = items[i].g_begin < items[i].g_end;
-      items_h[i] = {s.nq, tune_.variant[s.nq], items[i].g_begin, items[i].g_end, s.state_off,
-                    s.gate_off, any ? s.kmat[items[i].g_begin].second : 0,
-                    any ? s.kmat[items[i].g_begin].first : 0, 0};
+      const int gb = items[i].g_begin, ge = items[i].g_end;
+      const bool g0 = gb < ge, g1 = gb + 1 < ge;
+      items_h[i] = {s.nq, tune_.variant[s.nq], gb, ge, s.state_off, s.gate_off,
+                    g0 ? s.kmat[gb].second : 0, g1 ? s.kmat[gb + 1].second : 0,
+                    g0 ? s.kmat[gb].first : 0, g1 ? s.kmat[gb + 1].first : 0, {0, 0}};
       max_nq = std::max(max_nq, s.nq);
     }
     // As in the batched form: exact-kernel items first, then matrix-core
