@@ -599,11 +599,19 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="p
     NN = 1 << (2 * nq)
     fl = ch.flops_per_element() * NN
     cavg = cms / max(n, 1)
+    kernel = "gather" if ch.plan()["gather_kernel"] else "tiled"
     ch.close()
     return {"nq": nq, "paths": 2 * n_p, "noise": noise, "steps_per_s": 1e3 / ms, "ms_per_step": ms,
             "channel_ms": cavg, "channel_fp64_tflops": fl / (cavg * 1e-3) / 1e12,
             "channel_fp64_frac": fl / (cavg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
             "channel_gbs_read_write_once": 32 * NN / (cavg * 1e-3) / 1e9,
+            "channel_hbm_frac": 32 * NN / (cavg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            # the binding roof: the longer of the flop time and the byte time
+            "channel_bound": "fp64" if fl / FP64_PEAK_TFLOPS / 1e12 > 32 * NN / HBM_PEAK_GBS / 1e9
+                             else "hbm",
+            "channel_roof_frac": max(fl / FP64_PEAK_TFLOPS / 1e12, 32 * NN / HBM_PEAK_GBS / 1e9)
+                                 / (cavg * 1e-3),
+            "channel_kernel": kernel,
             "channel_flops_per_element": ch_flops if (ch_flops := fl // NN) else None,
             "trace_after": ob["trace"].real, "purity_after": ob["purity"],
             "fidelity_after": ob["fidelity"], **spectral}
@@ -907,8 +915,8 @@ def key_figures(extra, checks, cpu):
                                          "fp64_frac"),
         "eigen_batch_nq5": pick("eigen_batch_nq5", "eig_matrices_per_s",
                                 "max_abs_err_eigenvalues_vs_lapack"),
-        "channel_nq13": pick("multiverse_nq13", "channel_ms", "channel_fp64_frac",
-                             "channel_gbs_read_write_once"),
+        "channel_nq13": pick("multiverse_nq13", "channel_ms", "channel_bound",
+                             "channel_roof_frac", "channel_gbs_read_write_once"),
         "timed_plan_vs_plain_rel_err": (checks.get("timed_plan_vs_plain") or {}).get(
             "rel_err_2norm"),
         "timed_plan_vs_oracle_rel_err": (checks.get("oracle_check") or {}).get("rel_err_2norm"),

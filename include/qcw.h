@@ -379,6 +379,9 @@ int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, int ninst,
  * argument that follows it keep it).  The operators are fixed once drawn
  * (§5, caption of the denE listing), so a channel is created once, copied to
  * the device, and applied at every step.  rho_in and rho_out must not overlap.
+ * Applications of one channel must not run at the same time (on two streams
+ * without an order between them): the tiled kernel keeps its work counters
+ * in the channel.
  *
  * qcw_rho_observables (synchronous) writes to out_host, 4 + 3 nq doubles:
  * Tr rho (re, im); Tr rho^2 as sum |rho_nm|^2 (equal for Hermitian rho); the
@@ -404,15 +407,33 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
 int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out,
                       void *stream);
 int qcw_channel_destroy(qcw_channel *c);
-/* Real FP64 operations per output element of one application, as evaluated.
- * Terms whose operators are all diagonal or anti-diagonal (Pauli operators,
- * phases, the identity) read rho at n^x, m^x for a flip mask x; terms with
- * equal masks share that read: 8 per mask group (one complex multiply-add),
- * plus 2 per one-operator term and 8 per two-operator term for its
- * coefficient.  Any other term costs 8 per complex multiply-add (4 for one
- * operator, 16 for two) plus 4 for its weighted sum.  Plus 2 for p_keep * rho.
- * For roofline accounting. */
+/* Real FP64 operations per output element of one application, as evaluated
+ * by the kernel the channel runs (for roofline accounting).  Terms whose
+ * operators are all diagonal or anti-diagonal (Pauli operators, phases, the
+ * identity) read rho at n^x, m^x for a flip mask x, and terms with equal
+ * masks share that read.
+ * - Tiled kernel (every term of that kind, 7 <= nq <= 15): the coefficients
+ *   of a mask group are summed on the host into tables over the group's
+ *   qubits (segments of at most three qubits), so a group costs one
+ *   multiply-add with its coefficient, 4 when every coefficient is real
+ *   (Pauli channels) and 8 otherwise, plus 1 (real) or 2 per further segment.
+ * - Gather kernel (otherwise): 8 per mask group, plus 2 per one-operator
+ *   term and 8 per two-operator term for its coefficient; any other term
+ *   costs 8 per complex multiply-add (4 for one operator, 16 for two) plus 4
+ *   for its weighted sum.
+ * Plus 2 for p_keep * rho. */
 int64_t qcw_channel_flops_per_element(const qcw_channel *c);
+
+/*
+ * The plan of a channel's tiled kernel, and the choice of kernel (host call,
+ * for tests).  force_gather: 1 runs the gather kernel from now on, 0 the tiled
+ * kernel when there is a plan, negative leaves the choice.  info (13 host
+ * int32): {has tiled plan, kernel in use (0 tiled, 1 gather), tile bits E0,
+ * E1, partner tiles (with the tile itself), partners staged in LDS, partners
+ * read directly, tile itself staged, read sets, mask groups, segments,
+ * segments on E0 or E1, all coefficients real}.  QCW_EINVAL for NULL.
+ */
+int qcw_debug_channel_plan(qcw_channel *c, int force_gather, int32_t *info);
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
 

@@ -89,6 +89,7 @@ _SIGS = {
     "qcw_channel_apply": ([_P, _P, _P, _P], _i32),
     "qcw_channel_destroy": ([_P], _i32),
     "qcw_channel_flops_per_element": ([_P], _i64),
+    "qcw_debug_channel_plan": ([_P, _i32, _P], _i32),
     "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_rho_eigvals": ([_P, _i32, _P, _P], _i32),
     "qcw_rho_eigvals_batch": ([_P, _i32, _i64, _i64, _P, _P, _P], _i32),
@@ -637,6 +638,17 @@ class Channel:
 
     def flops_per_element(self):
         return int(_L.qcw_channel_flops_per_element(self.h))
+
+    _PLAN_KEYS = ("tiled_plan", "gather_kernel", "e0", "e1", "partners", "staged", "direct",
+                  "own_staged", "reads", "groups", "segments", "etouch_segments", "real")
+
+    def plan(self, force_gather=-1):
+        """The tiled kernel's plan (qcw_debug_channel_plan) as a dict;
+        force_gather 1/0 picks the gather/tiled kernel from now on."""
+        info = np.zeros(13, dtype=np.int32)
+        _check(_L.qcw_debug_channel_plan(self.h, int(force_gather), _hptr(info)),
+               "qcw_debug_channel_plan")
+        return dict(zip(self._PLAN_KEYS, (int(x) for x in info)))
 
     def close(self):
         if self.h:

@@ -1,0 +1,63 @@
+// Permutation-type channel terms and the tiled channel kernel (channel_tiled.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+#include <vector>
+
+namespace qcw {
+
+// A term whose operators each have one nonzero entry per row, in distinct
+// columns (Pauli operators, phases, the identity): row r of K reads column
+// r ^ s with s = 0 or 1, so (K rho K^dagger)_{nm} = c(n, m) rho_{n^x, m^x}
+// with x the term's flip mask (the bits of its swapping operators) and
+// c = K[r][r^s] conj(K[c][c^s]) depending only on the bits at the term's qubits.
+struct PermTerm {
+  int32_t nops;
+  int32_t bit0, bit1;
+  int32_t pad;
+  double2 c0[4];  // w K0[r][r^s0] conj(K0[c][c^s0]) at r*2 + c (weight folded in)
+  double2 c1[4];  // K1[r][r^s1] conj(K1[c][c^s1]) at r*2 + c
+};
+
+// Bit b of x (b < 16) moved to bit 2b.
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+constexpr int kTiledMinQubits = 7;   // low 4 bits, two tile bits, at least one more
+constexpr int kTiledMaxQubits = 15;  // row and column bits interleave into bits 0..29
+
+struct TiledChannel;
+
+// Shape of a tiled plan (for tests and reports).
+struct TiledSummary {
+  int e0, e1;          // the two tile bits above bit 3
+  int partners;        // partner tiles per tile, the tile itself included
+  int staged, direct;  // partners staged in LDS, partners read directly
+  int own_staged;      // the tile itself staged in LDS (a flip inside it moves bits 0..3)
+  int reads, groups, segments, etouch_segments;
+  int real;            // every combined coefficient is real (2 FMAs per group and output)
+};
+
+// Plans the tiled form of a channel whose terms are all permutation type,
+// given as (flip mask, term).  Returns QCW_OK with *out == nullptr when the
+// channel does not suit it (nq outside [kTiledMinQubits, kTiledMaxQubits],
+// coefficient tables beyond the LDS budget); an error code only when device
+// memory cannot be had.
+int tiled_channel_create(int nq, double p_keep,
+                         const std::vector<std::pair<uint64_t, PermTerm>> &terms,
+                         TiledChannel **out);
+int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, hipStream_t s);
+void tiled_channel_free(TiledChannel *t);
+// Real FP64 operations per output element, as the tiled kernel evaluates them.
+int64_t tiled_channel_flops(const TiledChannel *t);
+void tiled_channel_summary(const TiledChannel *t, TiledSummary *s);
+
+}  // namespace qcw

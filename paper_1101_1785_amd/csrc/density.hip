@@ -15,6 +15,7 @@
 #include <utility>
 #include <vector>
 
+#include "channel_tiled.h"
 #include "qcw_device.h"
 #include "qcw_host.h"
 
@@ -34,19 +35,6 @@ struct DevTerm {
   double weight;
   double pad;
   double2 k0[4], k1[4];  // 2x2 operators, row-major
-};
-
-// A term whose operators each have one nonzero entry per row, in distinct
-// columns (Pauli operators, phases, the identity): row r of K reads column
-// r ^ s with s = 0 or 1, so (K rho K^dagger)_{nm} = c(n, m) rho_{n^x, m^x}
-// with x the term's flip mask (the bits of its swapping operators) and
-// c = K[r][r^s] conj(K[c][c^s]) depending only on the bits at the term's qubits.
-struct PermTerm {
-  int32_t nops;
-  int32_t bit0, bit1;
-  int32_t pad;
-  double2 c0[4];  // w K0[r][r^s0] conj(K0[c][c^s0]) at r*2 + c (weight folded in)
-  double2 c1[4];  // K1[r][r^s1] conj(K1[c][c^s1]) at r*2 + c
 };
 
 // Terms sharing a flip mask read the same element of rho: one gather per group.
@@ -104,14 +92,6 @@ __device__ __forceinline__ double2 pick4(const double2 (&c)[4], int r, int cc) {
 constexpr int kChanBatch = 8;             // flip-mask groups gathered together
 constexpr int kChanTableMaxQubits = 16;   // the interleaved row/column index fits 32 bits
 
-// Bit b of x (b < 16) moved to bit 2b.
-__device__ __forceinline__ uint32_t spread16(uint32_t x) {
-  x = (x | (x << 8)) & 0x00FF00FFu;
-  x = (x | (x << 4)) & 0x0F0F0F0Fu;
-  x = (x | (x << 2)) & 0x33333333u;
-  x = (x | (x << 1)) & 0x55555555u;
-  return x;
-}
 constexpr int kChanTableMaxTerms = 256;   // permutation terms staged in LDS (34 KiB)
 
 // One output element x = n * 2^nq + m of the channel.  With TAB, ctab holds
@@ -405,7 +385,9 @@ struct qcw_channel {
   double2 *coef_d = nullptr;
   PermGroup *groups_d = nullptr;
   PermTerm *perm_d = nullptr;
-  int64_t flops_per_element = 0;  // real FP64 operations per output element, as evaluated
+  int64_t flops_gather = 0;       // real FP64 operations per output element, gather kernel
+  TiledChannel *tiled = nullptr;  // tiled plan (permutation terms only, 7 <= nq <= 15)
+  int force_gather = 0;           // run the gather kernel even with a tiled plan
 };
 
 namespace {
@@ -414,6 +396,7 @@ void channel_free(qcw_channel *c) {
   (void)hipFree(c->coef_d);
   (void)hipFree(c->groups_d);
   (void)hipFree(c->perm_d);
+  tiled_channel_free(c->tiled);
   delete c;
 }
 }  // namespace
@@ -538,7 +521,7 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
   c->nterms = (int)dt.size();
   c->ngroups = (int)groups.size();
   c->nperm = (int)perm.size();
-  c->flops_per_element = flops;
+  c->flops_gather = flops;
   if (!groups.empty()) {
     if (hipMalloc(&c->groups_d, sizeof(PermGroup) * groups.size()) != hipSuccess ||
         hipMalloc(&c->perm_d, sizeof(PermTerm) * perm.size()) != hipSuccess ||
@@ -567,6 +550,13 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
       return fail(QCW_EHIP, "channel coefficient kernel failed");
     }
   }
+  if (dt.empty()) {
+    const int rc = tiled_channel_create(nq, p_keep, pt, &c->tiled);
+    if (rc) {
+      channel_free(c);
+      return rc;
+    }
+  }
   *out = c;
   return QCW_OK;
 }
@@ -585,6 +575,7 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
   const double2 *in = reinterpret_cast<const double2 *>(rho_in);
   double2 *o = reinterpret_cast<double2 *>(rho_out);
+  if (c->tiled && !c->force_gather) return tiled_channel_apply(c->tiled, in, o, (hipStream_t)stream);
   if (c->nperm > 0 && c->nperm <= kChanTableMaxTerms && c->nq <= kChanTableMaxQubits)
     hipLaunchKernelGGL(channel_kernel<true>, dim3(blocks), dim3(kChanThreads),
                        (sizeof(double2) * 8 + sizeof(int) * 2) * c->nperm, (hipStream_t)stream, in,
@@ -605,7 +596,23 @@ int qcw_channel_destroy(qcw_channel *c) {
   return QCW_OK;
 }
 
-int64_t qcw_channel_flops_per_element(const qcw_channel *c) { return c ? c->flops_per_element : -1; }
+int64_t qcw_channel_flops_per_element(const qcw_channel *c) {
+  if (!c) return -1;
+  return c->tiled && !c->force_gather ? tiled_channel_flops(c->tiled) : c->flops_gather;
+}
+
+int qcw_debug_channel_plan(qcw_channel *c, int force_gather, int32_t *info) {
+  clear_error();
+  if (!c || !info) return fail(QCW_EINVAL, "channel or info is NULL");
+  if (force_gather >= 0) c->force_gather = force_gather ? 1 : 0;
+  TiledSummary sm{};
+  tiled_channel_summary(c->tiled, &sm);
+  const int32_t v[13] = {c->tiled ? 1 : 0, c->tiled && !c->force_gather ? 0 : 1, sm.e0, sm.e1,
+                         sm.partners, sm.staged, sm.direct, sm.own_staged, sm.reads, sm.groups,
+                         sm.segments, sm.etouch_segments, sm.real};
+  memcpy(info, v, sizeof(v));
+  return QCW_OK;
+}
 
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host, double *out_host,
                         void *stream) {

@@ -51,43 +51,156 @@ def _terms(rng, nq, n_p, eps, unitary=True):
     return terms
 
 
-@pytest.mark.parametrize("nq", [2, 5, 7, 9])
-def test_pauli_channel_matches_oracle(L, nq):
-    """Pauli-type hits (each output element gathers the flipped elements): at
-    nq >= 7 the kernel visits elements in its cache-ordered sequence, which
-    must not change any result."""
-    rng = np.random.default_rng(90 + nq)
-    rho0 = _rand_rho(rng, nq)
+def _pauli_terms(rng, nq, n_p=16, eps=0.2):
     P = [qi.X, qi.Y, qi.Z]
     terms = []
     for s, ps in ((1, 0.95), (2, 0.05)):
-        for _ in range(16):
+        for _ in range(n_p):
             qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
-            terms.append((0.2 * ps / 16, {q: P[int(rng.integers(3))] for q in qs}))
-    ch = L.Channel(nq, 0.8, terms)
+            terms.append((eps * ps / n_p, {q: P[int(rng.integers(3))] for q in qs}))
+    return terms
+
+
+def _apply(L, ch, rho0, nq, force_gather=-1):
+    ch.plan(force_gather)
     a, b = dev(rho0), torch.empty(1 << (2 * nq), dtype=torch.complex128, device="cuda")
     ch.apply(a, b)
-    assert np.max(np.abs(host(b, nq) - D.channel(rho0, 0.8, terms))) <= TOL
+    return host(b, nq)
+
+
+@pytest.mark.parametrize("nq", [2, 5, 7, 9])
+@pytest.mark.parametrize("kernel", ["auto", "gather"])
+def test_pauli_channel_matches_oracle(L, nq, kernel):
+    """Pauli-type hits (each output element gathers the flipped elements).
+    From nq = 7 a channel of such terms runs the tiled kernel; the gather
+    kernel (forced here) visits elements in its cache-ordered sequence there.
+    Neither order may change a result."""
+    rng = np.random.default_rng(90 + nq)
+    rho0 = _rand_rho(rng, nq)
+    terms = _pauli_terms(rng, nq)
+    ch = L.Channel(nq, 0.8, terms)
+    out = _apply(L, ch, rho0, nq, 1 if kernel == "gather" else 0)
+    assert ch.plan()["gather_kernel"] == (1 if kernel == "gather" or nq < 7 else 0)
+    assert np.max(np.abs(out - D.channel(rho0, 0.8, terms))) <= TOL
     ch.close()
 
 
-def test_pauli_channel_many_terms_matches_oracle(L):
-    """300 Pauli-type hits: more than the kernel stages in LDS (256), so the
-    channel takes its path that chooses coefficients from scalar registers."""
+@pytest.mark.parametrize("kernel", ["auto", "gather"])
+def test_pauli_channel_many_terms_matches_oracle(L, kernel):
+    """300 Pauli-type hits: more than the gather kernel stages in LDS (256),
+    so that kernel chooses coefficients from scalar registers; the tiled
+    kernel groups them into mask groups of many segments."""
     nq = 7
     rng = np.random.default_rng(97)
     rho0 = _rand_rho(rng, nq)
+    terms = _pauli_terms(rng, nq, n_p=150)
+    ch = L.Channel(nq, 0.8, terms)
+    out = _apply(L, ch, rho0, nq, 1 if kernel == "gather" else 0)
+    assert np.max(np.abs(out - D.channel(rho0, 0.8, terms))) <= TOL
+    ch.close()
+
+
+def _phase(rng):
+    return np.diag([np.exp(1j * rng.uniform(0, 2 * np.pi)), np.exp(1j * rng.uniform(0, 2 * np.pi))])
+
+
+def _flip_phase(rng):
+    return np.array([[0, np.exp(1j * rng.uniform(0, 2 * np.pi))],
+                     [np.exp(1j * rng.uniform(0, 2 * np.pi)), 0]])
+
+
+def _tiled_case(kind, nq, seed):
+    """Permutation-type channels shaped to reach every part of the tiled plan.
+    pauli: the multiverse noise of Eq. rhoE4 (real coefficients); phase: Pauli
+    operators mixed with random phases and phased flips (complex
+    coefficients); zheavy: many Z and ZZ hits (flip-free group of several
+    segments) and flips on bits 0..3 (the tile itself staged); pairs: a flip
+    on one of up to four far qubits with one on bits 0..3 (partners read by several
+    read sets, staged)."""
+    rng = np.random.default_rng(seed)
     P = [qi.X, qi.Y, qi.Z]
     terms = []
-    for s, ps in ((1, 0.95), (2, 0.05)):
-        for _ in range(150):
+    if kind == "pauli":
+        return _pauli_terms(rng, nq)
+    if kind == "phase":
+        ops = [qi.X, qi.Y, qi.Z, D.SX, _phase, _flip_phase]
+        for s in (1, 2) * 12:
             qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
-            terms.append((0.2 * ps / 150, {q: P[int(rng.integers(3))] for q in qs}))
+            op = {}
+            for q in qs:
+                o = ops[int(rng.integers(len(ops)))]
+                op[q] = o(rng) if callable(o) else o
+            terms.append((0.2 / 24, op))
+        return terms
+    if kind == "zheavy":
+        for _ in range(20):
+            qs = [int(x) + 1 for x in rng.choice(nq, 1 + int(rng.integers(2)), replace=False)]
+            terms.append((0.1 / 20, {q: qi.Z for q in qs}))
+        for _ in range(10):   # flips among the four lowest bits (qubits nq-3 .. nq)
+            q = nq - int(rng.integers(4))
+            terms.append((0.1 / 10, {q: P[int(rng.integers(2))]}))
+        return terms
+    if kind == "pairs":   # a flip on one of four far qubits (bits >= 4) with one on bits 0..3
+        far = [int(x) + 1 for x in rng.choice(nq - 4, min(4, nq - 4), replace=False)]
+        for _ in range(24):
+            qa, lo = far[int(rng.integers(len(far)))], nq - int(rng.integers(4))
+            terms.append((0.2 / 24, {qa: P[int(rng.integers(2))], lo: P[int(rng.integers(3))]}))
+        return terms
+    raise ValueError(kind)
+
+
+TILED_CASES = [("pauli", 7, 1), ("pauli", 10, 2), ("phase", 8, 3), ("phase", 9, 4),
+               ("zheavy", 8, 5), ("pairs", 9, 6), ("pairs", 7, 7)]
+
+
+@pytest.mark.parametrize("kind,nq,seed", TILED_CASES)
+def test_tiled_channel_matches_oracle(L, kind, nq, seed):
+    """The tiled channel kernel against the oracle's Kronecker-product channel,
+    elementwise (Eqs. rhoE1, rhoE4)."""
+    rng = np.random.default_rng(1000 + seed)
+    rho0 = _rand_rho(rng, nq)
+    terms = _tiled_case(kind, nq, seed)
     ch = L.Channel(nq, 0.8, terms)
-    a, b = dev(rho0), torch.empty(1 << (2 * nq), dtype=torch.complex128, device="cuda")
-    ch.apply(a, b)
-    assert np.max(np.abs(host(b, nq) - D.channel(rho0, 0.8, terms))) <= TOL
+    assert ch.plan()["tiled_plan"] == 1
+    out = _apply(L, ch, rho0, nq, 0)
+    assert np.max(np.abs(out - D.channel(rho0, 0.8, terms))) <= TOL
     ch.close()
+
+
+def test_tiled_channel_plan_coverage(L):
+    """The cases above reach every part of the tiled kernel: partners staged
+    in LDS and read directly, the tile itself staged, segments on the tile
+    bits, groups of several segments, real and complex coefficients."""
+    seen = {"staged": 0, "direct": 0, "own_staged": 0, "etouch_segments": 0, "multi_seg": 0,
+            "real": set()}
+    for kind, nq, seed in TILED_CASES:
+        ch = L.Channel(nq, 0.8, _tiled_case(kind, nq, seed))
+        p = ch.plan()
+        ch.close()
+        for k in ("staged", "direct", "own_staged", "etouch_segments"):
+            seen[k] += p[k]
+        seen["multi_seg"] += p["segments"] > p["groups"]
+        seen["real"].add(p["real"])
+    assert seen["staged"] and seen["direct"] and seen["own_staged"], seen
+    assert seen["etouch_segments"] and seen["multi_seg"], seen
+    assert seen["real"] == {0, 1}, seen
+
+
+@pytest.mark.parametrize("nq,kind", [(11, "pauli"), (12, "pauli"), (12, "phase")])
+def test_tiled_channel_equals_gather_kernel(L, nq, kind):
+    """Beyond the oracle's reach: the tiled and the gather kernels, two
+    independent evaluations of the same sums, agree elementwise on a random
+    density matrix."""
+    print(f"[gpu] tiled vs gather channel nq={nq} {kind}", flush=True)
+    rng = np.random.default_rng(2000 + nq)
+    rho0 = _rand_rho(rng, nq)
+    terms = _tiled_case(kind, nq, 50 + nq)
+    ch = L.Channel(nq, 0.8, terms)
+    t = _apply(L, ch, rho0, nq, 0)
+    g = _apply(L, ch, rho0, nq, 1)
+    ch.close()
+    assert np.max(np.abs(t - g)) <= TOL
+    assert abs(np.trace(t) - 1) <= 1e-12 and np.max(np.abs(t - t.conj().T)) <= TOL
 
 
 @pytest.mark.parametrize("nq", [1, 2, 3, 5, 7])
