@@ -126,8 +126,11 @@ typedef struct {
 /*
  * A circuit: the gates applied in list order, i.e. the operator product read
  * right to left (CNOT_12 H_1 |00> applies H_1 first; §5).  Plain form: one
- * sweep per gate on `stream`.  gates, mats: host arrays; nmats is the length
- * of mats in qcw_c64 elements (every gate's matrix must lie inside it).
+ * sweep per gate on `stream`; on states of at most 11 qubits the gates run in
+ * one launch (a further launch per 32 gates or 224 matrix entries) with the
+ * state in LDS, each gate the sweep's group update, bit for bit one sweep per
+ * gate.  gates, mats: host arrays, read before the call returns; nmats is the
+ * length of mats in qcw_c64 elements (every gate's matrix must lie inside it).
  */
 int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates,
                 const qcw_c64 *mats, int64_t nmats, void *stream);
@@ -567,7 +570,8 @@ int qcw_server_destroy(qcw_server *s);
  * family, the number of launches and their summed duration in milliseconds
  * since the last reset.  Families: QCW_KERNEL_SWEEP1..3 (one-gate sweeps of
  * k = 1, 2, 3, in either sweep kernel), QCW_KERNEL_BATCH (batch executions),
- * QCW_KERNEL_FUSED (fused passes), QCW_KERNEL_CHANNEL (channel applications).
+ * QCW_KERNEL_FUSED (fused passes), QCW_KERNEL_CHANNEL (channel applications),
+ * QCW_KERNEL_SMALL (launches of qcw_circuit on states of at most 11 qubits).
  * Launches recorded into a hipGraph are not timed individually.
  */
 enum {
@@ -577,6 +581,7 @@ enum {
   QCW_KERNEL_BATCH = 4, /* one batch execution (qcw_batch_run: the graph) */
   QCW_KERNEL_FUSED = 5, /* one fused pass */
   QCW_KERNEL_CHANNEL = 6, /* one channel application */
+  QCW_KERNEL_SMALL = 7,   /* one launch of qcw_circuit on a state of <= 11 qubits */
   QCW_KERNEL_COUNT = 8
 };
 int qcw_timing_enable(int on);

@@ -32,6 +32,7 @@ _i64 = ctypes.c_int64
 
 QCW_OK, QCW_EINVAL, QCW_ENOMEM, QCW_EHIP, QCW_EAGAIN = 0, -1, -2, -3, -4
 QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3, QCW_KERNEL_BATCH = 1, 2, 3, 4
+QCW_KERNEL_SMALL = 7
 QCW_KERNEL_FUSED = 5
 QCW_PLAN_COMMUTE, QCW_PLAN_FUSE, QCW_PLAN_3M = 1, 2, 4
 QCW_KERNEL_CHANNEL = 6

@@ -213,6 +213,8 @@ int qcw_circuit(qcw_c64 *psi, int nq, const qcw_gate *gates, int ngates, const q
   }
   int rc = check_device_range(psi, ((uint64_t)1 << nq) * sizeof(qcw_c64), "psi");
   if (rc) return rc;
+  if (nq <= kSmallMaxQubits)
+    return run_small_circuit(psi, nq, geo.data(), gates, ngates, mats, (hipStream_t)stream);
   for (int i = 0; i < ngates; ++i)
     if ((rc = launch_sweep(geo[i], mats + gates[i].mat, psi, psi, (hipStream_t)stream))) return rc;
   return QCW_OK;

@@ -27,6 +27,13 @@ struct TimedLaunch {
 };
 
 // Launchers (sweep.hip).
+// The plain circuit path for states of at most kSmallMaxQubits qubits: the
+// whole (validated) circuit in one launch with the state in LDS, bit for bit
+// one sweep per gate (small_circuit.hip).
+constexpr int kSmallMaxQubits = 11;
+int run_small_circuit(qcw_c64 *psi, int nq, const Geom *geo, const qcw_gate *gates, int ngates,
+                      const qcw_c64 *mats, hipStream_t s);
+
 int launch_sweep(const Geom &g, const qcw_c64 *U, const qcw_c64 *in, qcw_c64 *out,
                  hipStream_t s);
 int launch_pick(const Geom &g, uint64_t *labels_dev, hipStream_t s);

@@ -231,6 +231,35 @@ def test_pick_device_bit_exact(L):
                 assert np.array_equal(L.qcw_debug_pick_device(nq, t), oracle.pick(nq, t)), (nq, t)
 
 
+@pytest.mark.parametrize("nq,G", [(1, 5), (3, 12), (5, 40), (8, 70), (11, 44)])
+def test_small_state_circuit_equals_sweeps(L, nq, G):
+    """States of at most 11 qubits run the whole circuit in one launch (a
+    further launch per 32 gates or 224 matrix entries: G = 40 and 70 need
+    several) with the state in LDS; the result equals one sweep per gate
+    (qcw_opk on each gate, the path of larger states) bit for bit, and the
+    launches are counted as QCW_KERNEL_SMALL."""
+    c = qi.circuit(5, nq, G, tag=11)
+    psi0 = qi.state(6, nq)
+    a, b = dev(psi0), dev(psi0)
+    L.qcw_timing_reset()
+    L.qcw_timing_enable(True)
+    try:
+        L.circuit(a, c)
+        n_small, _ = L.qcw_timing_read(L.QCW_KERNEL_SMALL)
+    finally:
+        L.qcw_timing_enable(False)
+    for k, t, U in zip(c.ks, c.targets, c.mats):
+        L.qcw_opk(k, t, U, b)
+    assert np.array_equal(host(a), host(b))
+    entries = [1 << (2 * k) for k in c.ks]
+    launches, g, m = 1, 0, 0
+    for e in entries:
+        if g == 32 or m + e > 224:
+            launches, g, m = launches + 1, 0, 0
+        g, m = g + 1, m + e
+    assert n_small == launches
+
+
 def test_timing_counts_launches(L):
     psi = dev(qi.state(0, 12))
     L.qcw_timing_reset()
