@@ -57,6 +57,9 @@ constexpr size_t kTableBytesMax = 32 << 10;   // coefficient tables staged in LD
 
 enum PartnerMode : int32_t { kOwn = 0, kStaged = 1, kDirect = 2 };
 
+constexpr uint32_t kTicketSubs = 8;     // ticket counters per XCD, at most
+constexpr uint32_t kTicketStride = 32;  // words between counters: one 128-byte line each
+
 // One segment: its table entry for an output with interleaved index nm is
 // entry f0 + 4 f1 + 16 f2 of its table (4^k entries for k qubits), f_j =
 // (nm >> sh_j) & 3 for its j-th qubit (for qubit bit b, (nm >> 2b) & 3 =
@@ -79,14 +82,16 @@ struct TRead {
   uint32_t flo17;           // f_lo * 17: the flip of the thread index r * 16 + c
   uint32_t rec;             // first record
   uint32_t count[kKinds];   // groups of each kind
-  uint32_t pad[2];
+  uint32_t kinds;           // bit k set: count[k] > 0
+  uint32_t pad;
 };
 struct TPartner {
-  uint32_t fR;    // flip of the tile base
+  uint64_t fRb;   // byte flip of the tile base: ((f_R << nq) | f_R) * 16
   int32_t mode;
   uint32_t r_first, r_count;
-  uint32_t lflo;  // f_lo of the thread's loads: 0 when staged, the read set's when direct
-  int32_t pad[3];
+  uint32_t lflob; // byte flip of the thread's loads: ((f << nq) | f) * 16 for f = f_lo when
+                  // the partner is read directly, 0 when staged
+  uint32_t pad[2];
 };
 
 struct TArgs {
@@ -94,7 +99,9 @@ struct TArgs {
   double p_keep;
   uint32_t xcd_tiles;       // tiles each XCD works through (all tiles / 8)
   uint32_t xcd_blocks;      // blocks on each XCD (grid / 8)
-  uint32_t *tickets;        // per XCD: next tile [0..7], blocks finished [8..15]
+  uint32_t nsub;            // ticket counters per XCD (each XCD has at least nsub blocks)
+  uint32_t *tickets;        // per XCD x: counters x * kTicketSubs + s; blocks finished 8 * kTicketSubs + x
+                            // (each in its own kTicketStride words)
   int npartners;
   int own_staged, any_staged;
   int tab_entries;
@@ -235,22 +242,30 @@ __global__ __launch_bounds__(kTileThreads) void channel_tiled_kernel(const doubl
   const uint32_t tid = threadIdx.x, r = tid >> 4, c = tid & 15u;
   const uint32_t d1 = 1u << A.e0, d2 = 1u << A.e1;
   const uint32_t dep[4] = {0u, d1, d2, d1 | d2};
+  uint64_t db[4];  // byte offsets of the tile's four blocks from its first
+#pragma unroll
+  for (int b = 0; b < 4; ++b) db[b] = (((uint64_t)dep[b] << nq) | dep[b]) << 4;
   const uint32_t k1 = 3u << (2 * A.e0), k2 = 3u << (2 * A.e1);
   const uint32_t K[4] = {0u, k1, k2, k1 | k2};
   const uint32_t mmask = (1u << A.mb_bits) - 1u;
   const uint32_t t0b = ((r << nq) | c) << 4;  // this thread's byte offset within a tile's rows
   // Block b runs on XCD b mod 8.  Each XCD takes its families (family ==
   // XCD mod 8) in order, and its blocks draw the next tile of that sequence
-  // from the XCD's ticket counter, so the tiles in flight on an XCD stay a
+  // from the XCD's ticket counters, so the tiles in flight on an XCD stay a
   // window of consecutive tiles, mostly one family, whose partners share
   // its L2 (a fixed stride would let blocks drift apart over the launch).
-  // The next tile's ticket is drawn at the start of the current one and
-  // published at the next tile start, so the atomic's latency overlaps a
+  // An XCD has `nsub` counters, each on its own cache line: counter s hands
+  // out the tiles j == s mod nsub to its blocks (atomics on one address
+  // serialise: one counter for all of an XCD's blocks took as long as moving
+  // the tiles).  The next ticket is drawn at the start of the current tile
+  // and published at the next tile start, so the atomic's latency overlaps a
   // tile's work.
   const uint32_t x = blockIdx.x & 7u;
+  const uint32_t sub = (blockIdx.x >> 3) % A.nsub;
+  uint32_t *counter = A.tickets + (x * kTicketSubs + sub) * kTicketStride;
   __shared__ uint32_t s_ticket[2];
   uint32_t next = 0;
-  if (threadIdx.x == 0) next = atomicAdd(&A.tickets[x], 1u);
+  if (threadIdx.x == 0) next = atomicAdd(counter, 1u) * A.nsub + sub;
   for (uint32_t it = 0;; ++it) {
     if (threadIdx.x == 0) s_ticket[it & 1u] = next;
     // Also the tile-start barrier: the previous tile's LDS reads are done
@@ -259,7 +274,7 @@ __global__ __launch_bounds__(kTileThreads) void channel_tiled_kernel(const doubl
     __syncthreads();
     const uint32_t j = s_ticket[it & 1u];
     if (j >= A.xcd_tiles) break;
-    if (threadIdx.x == 0) next = atomicAdd(&A.tickets[x], 1u);
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1u) * A.nsub + sub;
     const uint32_t family = ((j >> A.mb_bits) << 3) | x;
     uint32_t nb = (j & mmask) << 4;  // the member's bits, zeros inserted at E0 and E1
     nb = ((nb >> A.e0) << (A.e0 + 1)) | (nb & (d1 - 1u));
@@ -267,30 +282,33 @@ __global__ __launch_bounds__(kTileThreads) void channel_tiled_kernel(const doubl
     const uint32_t mb = nb ^ (family << 4);
     const uint32_t n0 = nb | r, m0 = mb | c;
     const uint32_t nm0 = (spread16(n0) << 1) | spread16(m0);
-    // Element (b, r', c') of the tile at (nb', mb') is at U(b) + (r' << nq | c')
-    // with U(b) = (nb' | dep(b)) << nq | (mb' ^ dep(b)) wave-uniform: a scalar
+    // Element (b, r', c') of the tile at (nb ^ f, mb ^ f) is at byte
+    // U0 ^ F ^ D(b) + (r' << nq | c') * 16, with U0 = (nb << nq | mb) * 16,
+    // F = (f << nq | f) * 16 and D(b) = (dep(b) << nq | dep(b)) * 16 (the
+    // fields do not overlap, so the flips are XORs): a wave-uniform scalar
     // base and a 32-bit per-thread byte offset.
-    auto at = [&](const double2 *base, uint32_t nbp, uint32_t mbp, int b, uint32_t off_b) {
-      return *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(
-                                                    base + el(nbp | dep[b], mbp ^ dep[b], nq)) +
-                                                off_b);
+    const uint64_t u0 = (((uint64_t)nb << nq) | mb) << 4;
+    auto at = [&](const double2 *base, uint64_t fb, int b, uint32_t off_b) {
+      return *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(base) +
+                                                (u0 ^ fb ^ db[b]) + off_b);
     };
     double2 own[4], acc[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) own[a] = at(rho, nb, mb, a, t0b);
+    for (int a = 0; a < 4; ++a) own[a] = at(rho, 0, a, t0b);
     // Partners 1.. in rounds of kRound: every load of a round is issued before
     // the first of its partners is used, so their latencies overlap (round 1
-    // also with the tile's own work).  Past the last partner a slot loads the
-    // last partner again (from cache), so the loads are straight-line code
-    // and the waits for each slot exact.
+    // also with the tile's own work).  Slots past the last partner load
+    // nothing; only a round that ends early then waits for all of its loads
+    // at once.
     double2 q[kRound][4];
     auto issue = [&](int p1) {
 #pragma unroll
       for (int k = 0; k < kRound; ++k) {
-        const TPartner P = ldc<TPartner>(A.partners, (uint32_t)min(p1 + k, A.npartners - 1) * (uint32_t)sizeof(TPartner));
-        const uint32_t off_b = t0b ^ (((P.lflo << nq) | P.lflo) << 4);
+        if (k > 0 && p1 + k >= A.npartners) break;
+        const TPartner P = ldc<TPartner>(A.partners, (uint32_t)(p1 + k) * (uint32_t)sizeof(TPartner));
+        const uint32_t off_b = t0b ^ P.lflob;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) q[k][b] = at(rho, nb ^ P.fR, mb ^ P.fR, b, off_b);
+        for (int b = 0; b < 4; ++b) q[k][b] = at(rho, P.fRb, b, off_b);
       }
     };
     if (A.npartners > 1) issue(1);
@@ -349,15 +367,16 @@ __global__ __launch_bounds__(kTileThreads) void channel_tiled_kernel(const doubl
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const dbl2v w = {acc[a].x, acc[a].y};
-      __builtin_nontemporal_store(
-          w, reinterpret_cast<dbl2v *>(reinterpret_cast<char *>(out + el(nb | dep[a], mb ^ dep[a], nq)) + t0b));
+      __builtin_nontemporal_store(w, reinterpret_cast<dbl2v *>(reinterpret_cast<char *>(out) +
+                                                               (u0 ^ db[a]) + t0b));
     }
   }
   // The last block of the XCD to finish (every block of it has drawn its
   // last ticket) clears the XCD's counters for the next launch.
-  if (threadIdx.x == 0 && atomicAdd(&A.tickets[8 + x], 1u) == A.xcd_blocks - 1u) {
-    atomicExch(&A.tickets[x], 0u);
-    atomicExch(&A.tickets[8 + x], 0u);
+  uint32_t *done = A.tickets + (8 * kTicketSubs + x) * kTicketStride;
+  if (threadIdx.x == 0 && atomicAdd(done, 1u) == A.xcd_blocks - 1u) {
+    for (uint32_t k = 0; k < A.nsub; ++k) atomicExch(A.tickets + (x * kTicketSubs + k) * kTicketStride, 0u);
+    atomicExch(done, 0u);
   }
 }
 
@@ -490,7 +509,11 @@ int tiled_channel_create(int nq, double p_keep,
   sm.e1 = e1;
   int64_t flops_groups = 0, flops_segs = 0;
   for (const auto &pk : plan) {  // f_R ascending: the tile itself first
-    TPartner P{pk.first, 0, (uint32_t)reads.size(), (uint32_t)pk.second.size(), 0u, {0, 0, 0}};
+    TPartner P;
+    memset(&P, 0, sizeof(P));
+    P.fRb = (((uint64_t)pk.first << nq) | pk.first) << 4;
+    P.r_first = (uint32_t)reads.size();
+    P.r_count = (uint32_t)pk.second.size();
     for (const auto &lk : pk.second) {  // f_lo ascending
       TRead R;
       memset(&R, 0, sizeof(R));
@@ -529,6 +552,7 @@ int tiled_channel_create(int nq, double p_keep,
           recs.push_back(S);
         }
         ++R.count[kind];
+        R.kinds |= 1u << kind;
         flops_segs += (int64_t)sb.size() - 1;
         ++flops_groups;
         ++sm.groups;
@@ -541,7 +565,10 @@ int tiled_channel_create(int nq, double p_keep,
     } else {
       P.mode = P.r_count >= 2 ? kStaged : kDirect;
       (P.mode == kStaged ? sm.staged : sm.direct) += 1;
-      if (P.mode == kDirect) P.lflo = pk.second.begin()->first;
+      if (P.mode == kDirect) {
+        const uint64_t f = pk.second.begin()->first;
+        P.lflob = (uint32_t)(((f << nq) | f) << 4);
+      }
     }
     partners.push_back(P);
   }
@@ -562,7 +589,7 @@ int tiled_channel_create(int nq, double p_keep,
   const size_t o_s = align256(o_r + sizeof(TRead) * reads.size());
   const size_t o_t = align256(o_s + sizeof(TRec) * recs.size());
   const size_t o_k = align256(o_t + tab_bytes);
-  const size_t total = o_k + 256;  // 16 ticket counters, zero
+  const size_t total = o_k + (8 * kTicketSubs + 8) * kTicketStride * sizeof(uint32_t);  // zero
   std::vector<unsigned char> host(total, 0);
   memcpy(host.data() + o_p, partners.data(), sizeof(TPartner) * partners.size());
   if (!reads.empty()) memcpy(host.data() + o_r, reads.data(), sizeof(TRead) * reads.size());
@@ -629,6 +656,8 @@ int tiled_channel_create(int nq, double p_keep,
   const uint64_t want = std::min<uint64_t>((uint64_t)bpc * ncu, (uint64_t)A.xcd_tiles * 8);
   t->grid = (unsigned)std::max<uint64_t>(8, want & ~(uint64_t)7);
   A.xcd_blocks = t->grid / 8;
+  A.nsub = 1;
+  while (A.nsub < kTicketSubs && 2 * A.nsub <= A.xcd_blocks) A.nsub *= 2;
   *out = t;
   return QCW_OK;
 }
