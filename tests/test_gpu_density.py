@@ -186,6 +186,61 @@ def test_tiled_channel_plan_coverage(L):
     assert seen["real"] == {0, 1}, seen
 
 
+def test_tiled_channel_without_terms(L):
+    """A channel of no paths keeps p rho: the tiled kernel's plan is the tile
+    itself with no groups, and every output is p times its input exactly."""
+    nq = 8
+    rng = np.random.default_rng(300)
+    rho0 = _rand_rho(rng, nq)
+    ch = L.Channel(nq, 0.7, [])
+    assert ch.plan()["tiled_plan"] == 1 and ch.plan()["groups"] == 0
+    out = _apply(L, ch, rho0, nq, 0)
+    ch.close()
+    assert np.array_equal(out, 0.7 * rho0)
+
+
+def test_tiled_channel_15_qubits_basis_state(L):
+    """nq = 15, the largest state of the tiled kernel (2^30 elements, 16 GiB
+    each for input and output): on |0..0><0..0| a Pauli hit moves weight w_t
+    to the diagonal element at its flip mask, so the output is p at (0, 0)
+    plus the flip-free hits, w summed per flip mask f at (f, f), and zero
+    elsewhere (the output starts as NaN, so every element must be written)."""
+    nq = 15
+    N = 1 << nq
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 2 * 16 * N * N + (8 << 30):
+        pytest.skip("needs 40 GiB of free device memory")
+    print(f"[gpu] tiled pauli channel nq={nq} on a basis state", flush=True)
+    rng = np.random.default_rng(15)
+    P = {"X": qi.X, "Y": qi.Y, "Z": qi.Z}
+    terms, expect = [], {0: 0.8}
+    for s_, ps in ((1, 0.95), (2, 0.05)):
+        for _ in range(16):
+            qs = [int(x) + 1 for x in rng.choice(nq, s_, replace=False)]
+            names = {q: "XYZ"[int(rng.integers(3))] for q in qs}
+            w = 0.2 * ps / 16
+            terms.append((w, {q: P[n] for q, n in names.items()}))
+            f = sum(1 << (nq - q) for q, n in names.items() if n != "Z")
+            expect[f] = expect.get(f, 0.0) + w
+    ch = L.Channel(nq, 0.8, terms)
+    assert ch.plan()["gather_kernel"] == 0
+    a = torch.zeros(N * N, dtype=torch.complex128, device="cuda")
+    a[0] = 1.0
+    b = torch.full_like(a, float("nan"))
+    ch.apply(a, b)
+    ch.close()
+    del a
+    assert not bool(torch.isnan(b).any())
+    assert int(torch.count_nonzero(b).item()) == len(expect)
+    idx = torch.tensor([f * N + f for f in expect], device="cuda")
+    got = b[idx].cpu().numpy()
+    assert np.allclose(got, list(expect.values()), rtol=0, atol=1e-15)
+    assert abs(complex(b.sum().item()) - 1.0) <= 1e-14
+    del b
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("nq,kind", [(11, "pauli"), (12, "pauli"), (12, "phase")])
 def test_tiled_channel_equals_gather_kernel(L, nq, kind):
     """Beyond the oracle's reach: the tiled and the gather kernels, two
@@ -573,8 +628,9 @@ def test_channel_random_rotation_noise(L, nq):
 
 
 def test_pauli_channel_16_qubits_basis_state(L):
-    """nq = 16: 2^32 elements, more than one launch grid can address, so the
-    kernel's blocks stride over the matrix.  On |0..0><0..0| a Pauli hit
+    """nq = 16 (above the tiled kernel's range, so the gather kernel): 2^32
+    elements, more than one launch grid can address, so the kernel's blocks
+    stride over the matrix.  On |0..0><0..0| a Pauli hit
     moves weight w_t to the diagonal element at its flip mask (X and Y flip
     their qubit, Z does not; |entries| = 1), so the output is p at (0, 0) plus
     the weights of the flip-free hits, w summed per flip mask f at (f, f), and
