@@ -289,7 +289,6 @@ __global__ __launch_bounds__(kChanThreads) void channel_kernel(
 }
 
 // ------------------------------------------------------------------ observables
-constexpr int kObsBlocks = 256;
 constexpr int kObsThreads = 256;
 
 template <int NV>
@@ -308,26 +307,49 @@ __device__ void block_sum(double (&v)[NV], double *red) {
 }
 
 // Partial sums per block: trace (re, im), sum |rho|^2 (= Tr rho^2 for a
-// Hermitian rho), and <psi0|rho|psi0> (re).
+// Hermitian rho), and <psi0|rho|psi0> (re).  Each thread takes kObsPerThread
+// elements per step (grid-strided), all loaded before any is summed, so
+// several loads are in flight per lane; the grid depends only on nq, so the
+// summation order, and the result, is the same on every call.
+constexpr int kObsPerThread = 8;
+constexpr int kObsMaxBlocks = 2048;
+
+static int obs_blocks(int nq) {
+  const uint64_t NN = 1ull << (2 * nq);
+  const uint64_t b = NN / ((uint64_t)kObsThreads * kObsPerThread);
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, kObsMaxBlocks));
+}
+
 __global__ __launch_bounds__(kObsThreads) void obs_partial_kernel(const double2 *__restrict__ rho,
                                                                   int nq,
                                                                   const double2 *__restrict__ psi0,
                                                                   double *__restrict__ partial) {
   __shared__ double red[kObsThreads];
   const uint64_t N = 1ull << nq, NN = N * N;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   double v[4] = {0, 0, 0, 0};
-  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < NN;
-       x += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t n = x >> nq, m = x & (N - 1);
-    const double2 r = rho[x];
-    if (n == m) {
-      v[0] += r.x;
-      v[1] += r.y;
+  for (uint64_t x0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x0 < NN;
+       x0 += stride * kObsPerThread) {
+    double2 r[kObsPerThread];
+#pragma unroll
+    for (int k = 0; k < kObsPerThread; ++k) {
+      const uint64_t x = x0 + k * stride;
+      r[k] = x < NN ? rho[x] : make_double2(0.0, 0.0);
     }
-    v[2] += r.x * r.x + r.y * r.y;
-    if (psi0) {
-      const double2 f = cmul(cmul(cconj(psi0[n]), r), psi0[m]);
-      v[3] += f.x;
+#pragma unroll
+    for (int k = 0; k < kObsPerThread; ++k) {
+      const uint64_t x = x0 + k * stride;
+      if (x >= NN) break;
+      const uint64_t n = x >> nq, m = x & (N - 1);
+      if (n == m) {
+        v[0] += r[k].x;
+        v[1] += r[k].y;
+      }
+      v[2] += r[k].x * r[k].x + r[k].y * r[k].y;
+      if (psi0) {
+        const double2 f = cmul(cmul(cconj(psi0[n]), r[k]), psi0[m]);
+        v[3] += f.x;
+      }
     }
   }
   block_sum<4>(v, red);
@@ -359,16 +381,23 @@ __global__ __launch_bounds__(kObsThreads) void obs_polar_kernel(const double2 *_
   if (threadIdx.x == 0) out[4 + blockIdx.x] = v[0];
 }
 
-__global__ void obs_final_kernel(const double *__restrict__ partial, int nblocks,
-                                 double *__restrict__ out, int has_psi) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The blocks' partial sums, in a fixed order (thread t takes blocks t,
+// t + kObsThreads, ..., then the block's fixed tree), so the result does not
+// depend on timing.  One block of kObsThreads threads.
+__global__ __launch_bounds__(kObsThreads) void obs_final_kernel(const double *__restrict__ partial,
+                                                                int nblocks, double *__restrict__ out,
+                                                                int has_psi) {
+  __shared__ double red[kObsThreads];
   double s[4] = {0, 0, 0, 0};
-  for (int b = 0; b < nblocks; ++b)
+  for (int b = threadIdx.x; b < nblocks; b += kObsThreads)
     for (int i = 0; i < 4; ++i) s[i] += partial[b * 4 + i];
-  out[0] = s[0];
-  out[1] = s[1];
-  out[2] = s[2];
-  out[3] = has_psi ? sqrt(fmax(s[3], 0.0)) : NAN;
+  block_sum<4>(s, red);
+  if (threadIdx.x == 0) {
+    out[0] = s[0];
+    out[1] = s[1];
+    out[2] = s[2];
+    out[3] = has_psi ? sqrt(fmax(s[3], 0.0)) : NAN;
+  }
 }
 
 }  // namespace qcw
@@ -625,21 +654,22 @@ int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host, do
   const int nout = 4 + 3 * nq;
   const size_t N = (size_t)1 << nq;
   double *scratch = nullptr;  // partials, outputs, then psi0
-  const size_t bytes = sizeof(double) * (kObsBlocks * 4 + nout) + (psi0_host ? N * sizeof(qcw_c64) : 0);
+  const int nblocks = obs_blocks(nq);
+  const size_t bytes = sizeof(double) * (nblocks * 4 + nout) + (psi0_host ? N * sizeof(qcw_c64) : 0);
   if (hipMalloc(&scratch, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(QCW_ENOMEM, "observables scratch");
   }
-  double *partial = scratch, *out = scratch + kObsBlocks * 4;
+  double *partial = scratch, *out = scratch + nblocks * 4;
   double2 *psi_d = psi0_host ? reinterpret_cast<double2 *>(out + nout) : nullptr;
   hipError_t e = hipSuccess;
   if (psi0_host) e = hipMemcpyAsync(psi_d, psi0_host, N * sizeof(qcw_c64), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(obs_partial_kernel, dim3(kObsBlocks), dim3(kObsThreads), 0, s,
+    hipLaunchKernelGGL(obs_partial_kernel, dim3(nblocks), dim3(kObsThreads), 0, s,
                        reinterpret_cast<const double2 *>(rho), nq, psi_d, partial);
     hipLaunchKernelGGL(obs_polar_kernel, dim3(3 * nq), dim3(kObsThreads), 0, s,
                        reinterpret_cast<const double2 *>(rho), nq, out);
-    hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(64), 0, s, partial, kObsBlocks, out,
+    hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, partial, nblocks, out,
                        psi0_host ? 1 : 0);
     e = hipGetLastError();
   }
