@@ -370,7 +370,8 @@ int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, int ninst,
  *
  * qcw_rho_conjugate: rho <- U rho U^dagger for a k-qubit algorithm gate (the
  * Omega_A factors of Eq. rhoE4): the one-gate sweep of U on the row targets,
- * then of conj(U) on the column targets.
+ * then of conj(U) on the column targets; from nq = 5 both in one pass over
+ * rho (LDS tiles), with the same result bit for bit.
  *
  * A channel is the ensemble average over noisy paths, Eq. rhoE1:
  *     rho_out = p_keep * rho_in + sum_t weight_t K_t rho_in K_t^dagger,

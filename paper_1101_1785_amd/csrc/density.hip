@@ -21,7 +21,6 @@
 
 namespace qcw {
 
-constexpr int kRhoMaxQubits = 17;  // 2 * 17 = 34 superket qubits
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -448,6 +447,9 @@ int qcw_rho_conjugate(int k, const int *targets, const qcw_c64 *U, qcw_c64 *rho,
   }
   Geom gr, gc;
   if ((rc = make_geom(2 * nq, k, t2, &gr)) || (rc = make_geom(2 * nq, k, t3, &gc))) return rc;
+  // One pass of LDS tiles from 2 * kConjTileBits superket qubits on (bit for
+  // bit the two sweeps below), else a sweep on the rows and one on the columns.
+  if (2 * nq >= kConjTileBits) return launch_conjugate(nq, k, targets, U, rho, (hipStream_t)stream);
   const int mm = 1 << (2 * k);
   qcw_c64 Uc[64];
   for (int i = 0; i < mm; ++i) Uc[i] = {U[i].re, -U[i].im};

@@ -27,6 +27,16 @@ struct TimedLaunch {
 };
 
 // Launchers (sweep.hip).
+// Density matrices (multiverse step): rho of nq <= kRhoMaxQubits qubits is a
+// 2nq-qubit vector.  launch_conjugate applies U rho U^dagger in one pass of
+// 2^kConjTileBits-element LDS tiles (conjugate.hip), bit for bit the sweep of
+// U on the row qubits followed by the sweep of conj(U) on the column qubits;
+// targets validated by the caller, nq >= kConjTileBits / 2.
+constexpr int kRhoMaxQubits = 17;
+constexpr int kConjTileBits = 10;
+int launch_conjugate(int nq, int k, const int *targets, const qcw_c64 *U, qcw_c64 *rho,
+                     hipStream_t s);
+
 // The plain circuit path for states of at most kSmallMaxQubits qubits: the
 // whole (validated) circuit in one launch with the state in LDS, bit for bit
 // one sweep per gate (small_circuit.hip).

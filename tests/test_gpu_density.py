@@ -270,6 +270,30 @@ def test_conjugate_matches_oracle(L, nq):
         assert np.max(np.abs(host(r, nq) - D.conjugate(rho0, U, t))) <= TOL
 
 
+@pytest.mark.parametrize("nq", [5, 6, 8, 11])
+def test_conjugate_equals_two_sweeps(L, nq):
+    """From nq = 5 qcw_rho_conjugate applies U and conj(U) in one pass of LDS
+    tiles; the result equals the sweep of U on the row qubits followed by the
+    sweep of conj(U) on the column qubits (qcw_opk on rho read as a
+    2nq-qubit state) bit for bit, for k = 1, 2, 3, targets in any order and
+    targets among the lowest qubits (whose bits are always tile bits)."""
+    rng = np.random.default_rng(400 + nq)
+    rho0 = _rand_rho(rng, nq)
+    cases = [(1, (nq,)), (1, (1,)), (2, (nq, nq - 1)), (2, (1, nq)), (2, (nq - 1, 2)),
+             (3, (nq - 2, 1, nq)), (3, (2, nq - 1, 3)),
+             (3, tuple(int(x) + 1 for x in rng.choice(nq, 3, replace=False)))]
+    for k, t in cases:
+        U = qi.random_unitary(rng, 1 << k)
+        a = dev(rho0)
+        L.qcw_rho_conjugate(k, t, U, a)
+        b = dev(rho0)
+        L.qcw_opk(k, t, U, b, nq=2 * nq)
+        L.qcw_opk(k, tuple(x + nq for x in t), np.conj(U), b, nq=2 * nq)
+        assert np.array_equal(host(a, nq), host(b, nq)), (k, t)
+        if nq <= 8:
+            assert np.max(np.abs(host(a, nq) - D.conjugate(rho0, U, t))) <= TOL, (k, t)
+
+
 @pytest.mark.parametrize("nq", [1, 2, 4, 6, 8])
 @pytest.mark.parametrize("unitary", [True, False])
 def test_channel_matches_oracle(L, nq, unitary):
