@@ -542,7 +542,7 @@ def bench_shard(torch, L, qi, nq=32):
     return out
 
 
-def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="pauli"):
+def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="pauli", kernel=-1):
     """Multiverse density-matrix steps (Eq. rhoE4): channel of n_p single-hit and
     n_p double-hit paths (weights eps*p_s/n_p, p1=.95, p2=.05, p_keep=1-eps) whose
     hit operators are Pauli operators or (noise="rotation") random rotations
@@ -559,6 +559,7 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="p
             qs = [int(x) + 1 for x in rng.choice(nq, s, replace=False)]
             terms.append((eps * ps / n_p, {q: hit() for q in qs}))
     ch = L.Channel(nq, 1 - eps, terms)
+    ch.plan(kernel)
     psi0 = qi.basis_state(nq, 0)
     a = torch.from_numpy(np.outer(psi0, psi0.conj()).reshape(-1)).to("cuda")
     b2 = torch.empty_like(a)
@@ -599,7 +600,9 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="p
     NN = 1 << (2 * nq)
     fl = ch.flops_per_element() * NN
     cavg = cms / max(n, 1)
-    kernel = "gather" if ch.plan()["gather_kernel"] else "tiled"
+    plan = ch.plan()
+    kernel = ("gather" if plan["gather_kernel"] else
+              "tiled, compiled for the channel" if plan["compiled_kernel"] else "tiled, generic")
     ch.close()
     return {"nq": nq, "paths": 2 * n_p, "noise": noise, "steps_per_s": 1e3 / ms, "ms_per_step": ms,
             "channel_ms": cavg, "channel_fp64_tflops": fl / (cavg * 1e-3) / 1e12,
@@ -611,7 +614,7 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="p
                              else "hbm",
             "channel_roof_frac": max(fl / FP64_PEAK_TFLOPS / 1e12, 32 * NN / HBM_PEAK_GBS / 1e9)
                                  / (cavg * 1e-3),
-            "channel_kernel": kernel,
+            "channel_kernel": kernel, "channel_grid": plan["grid"], "channel_vgprs": plan["vgprs"],
             "channel_flops_per_element": ch_flops if (ch_flops := fl // NN) else None,
             "trace_after": ob["trace"].real, "purity_after": ob["purity"],
             "fidelity_after": ob["fidelity"], **spectral}
@@ -965,6 +968,7 @@ def extra_sections(torch, L, qi, a):
         "shard_nq32": lambda: bench_shard(torch, L, qi),
         "multiverse_nq12": lambda: bench_multiverse(torch, L, qi, 12, 5),
         "multiverse_nq13": lambda: bench_multiverse(torch, L, qi, 13, 5, steps=10),
+        "multiverse_nq13_generic": lambda: bench_multiverse(torch, L, qi, 13, 5, steps=10, kernel=2),
         "multiverse_nq14": lambda: bench_multiverse(torch, L, qi, 14, 5, steps=5),
         "eigen_batch_nq5": lambda: bench_eigen(torch, L, 5),
         "eigen_batch_nq6": lambda: bench_eigen(torch, L, 6),

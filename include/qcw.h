@@ -430,14 +430,40 @@ int64_t qcw_channel_flops_per_element(const qcw_channel *c);
 
 /*
  * The plan of a channel's tiled kernel, and the choice of kernel (host call,
- * for tests).  force_gather: 1 runs the gather kernel from now on, 0 the tiled
- * kernel when there is a plan, negative leaves the choice.  info (13 host
- * int32): {has tiled plan, kernel in use (0 tiled, 1 gather), tile bits E0,
- * E1, partner tiles (with the tile itself), partners staged in LDS, partners
- * read directly, tile itself staged, read sets, mask groups, segments,
- * segments on E0 or E1, all coefficients real}.  QCW_EINVAL for NULL.
+ * for tests).  kernel: from now on, 0 runs the tiled kernel when there is a
+ * plan (the one compiled for this channel at creation when the run-time
+ * compiler gave one, else the generic tiled kernel), 1 the gather kernel,
+ * 2 the generic tiled kernel; negative leaves the choice.  Both tiled kernels
+ * give the same bits.  info (17 host int32): {has tiled plan, kernel in use
+ * (0 tiled, 1 gather), tile bits E0, E1, partner tiles (with the tile
+ * itself), partners staged in LDS, partners read directly, tile itself
+ * staged, read sets, mask groups, segments, segments on E0 or E1, all
+ * coefficients real, the compiled tiled kernel in use, workgroups and VGPRs
+ * per lane of the tiled kernel in use (0 for the gather kernel), version of
+ * the run-time compiler that built the compiled kernel (major * 100 + minor;
+ * 0 when there is none)}.  The run-time compiler is the hipRTC of the ROCm
+ * installation the library was built with, loaded in a link-map namespace of
+ * its own, so that another hipRTC already in the process (a PyTorch wheel
+ * bundles one) is not the one used.  QCW_EINVAL for NULL or a kernel choice
+ * above 2.
  */
-int qcw_debug_channel_plan(qcw_channel *c, int force_gather, int32_t *info);
+int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info);
+
+/*
+ * The source of the tiled kernel that qcw_channel_create would compile for
+ * these terms (host call, no device needed; for tests).  Arguments as for
+ * qcw_channel_create.  *len: the source's length (0 when the channel has no
+ * tiled plan); when buf is not NULL, up to cap - 1 bytes of it and a NUL are
+ * written there.  compile != 0: the source is also compiled for gfx950 with
+ * the run-time compiler and *code_bytes set to the code object's size; a
+ * failed compile returns QCW_EHIP with the compiler's log in the last error.
+ * compiler_version (may be NULL): the run-time compiler's version, major *
+ * 100 + minor, 0 when it cannot be loaded.  QCW_EINVAL for bad terms or NULL
+ * len (or code_bytes when compiling).
+ */
+int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *mats,
+                             int64_t nmats, int compile, char *buf, size_t cap, size_t *len,
+                             size_t *code_bytes, int32_t *compiler_version);
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
 

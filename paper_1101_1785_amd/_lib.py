@@ -91,6 +91,8 @@ _SIGS = {
     "qcw_channel_destroy": ([_P], _i32),
     "qcw_channel_flops_per_element": ([_P], _i64),
     "qcw_debug_channel_plan": ([_P, _i32, _P], _i32),
+    "qcw_debug_channel_source": ([_i32, _P, _i32, _P, _i64, _i32, _P, ctypes.c_size_t, _P, _P, _P],
+                                 _i32),
     "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_rho_eigvals": ([_P, _i32, _P, _P], _i32),
     "qcw_rho_eigvals_batch": ([_P, _i32, _i64, _i64, _P, _P, _P], _i32),
@@ -622,6 +624,23 @@ def pack_terms(terms):
     return tab, M
 
 
+def channel_kernel_source(nq, terms, compile=False):
+    """(source, code_bytes, compiler_version) of the tiled kernel a Channel
+    over these terms compiles at creation (qcw_debug_channel_source; host
+    only).  source is "" when the channel has no tiled plan; code_bytes is
+    None unless compile; compiler_version is major * 100 + minor."""
+    tab, mats = pack_terms(terms)
+    n, cb, ver = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_int32(0)
+    args = (int(nq), _hptr(tab) if len(tab) else None, len(tab), _hptr(mats), mats.size)
+    _check(_L.qcw_debug_channel_source(*args, 0, None, 0, ctypes.byref(n), None, None),
+           "qcw_debug_channel_source")
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(_L.qcw_debug_channel_source(*args, int(bool(compile)), buf, n.value + 1, ctypes.byref(n),
+                                       ctypes.byref(cb), ctypes.byref(ver)),
+           "qcw_debug_channel_source")
+    return buf.value.decode(), (cb.value if compile else None), ver.value
+
+
 class Channel:
     """Ensemble-average channel rho -> p rho + sum w K rho K^dagger on the GPU."""
 
@@ -641,13 +660,16 @@ class Channel:
         return int(_L.qcw_channel_flops_per_element(self.h))
 
     _PLAN_KEYS = ("tiled_plan", "gather_kernel", "e0", "e1", "partners", "staged", "direct",
-                  "own_staged", "reads", "groups", "segments", "etouch_segments", "real")
+                  "own_staged", "reads", "groups", "segments", "etouch_segments", "real",
+                  "compiled_kernel", "grid", "vgprs", "compiler_version")
+    KERNEL_TILED, KERNEL_GATHER, KERNEL_TILED_GENERIC = 0, 1, 2
 
-    def plan(self, force_gather=-1):
-        """The tiled kernel's plan (qcw_debug_channel_plan) as a dict;
-        force_gather 1/0 picks the gather/tiled kernel from now on."""
-        info = np.zeros(13, dtype=np.int32)
-        _check(_L.qcw_debug_channel_plan(self.h, int(force_gather), _hptr(info)),
+    def plan(self, kernel=-1):
+        """The tiled kernel's plan (qcw_debug_channel_plan) as a dict; kernel
+        0/1/2 picks the tiled (compiled when available) / gather / generic
+        tiled kernel from now on."""
+        info = np.zeros(17, dtype=np.int32)
+        _check(_L.qcw_debug_channel_plan(self.h, int(kernel), _hptr(info)),
                "qcw_debug_channel_plan")
         return dict(zip(self._PLAN_KEYS, (int(x) for x in info)))
 

@@ -20,6 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libqcw.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "lib")
 ARCH = "gfx950"
 
 FLAGS = [
@@ -27,8 +28,13 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # matrix-core results in ordinary VGPRs: keeps the batch kernel at 4 waves/SIMD
     "-mllvm", "-amdgpu-mfma-vgpr-form",
+    # no wave-level combining of atomics: the channel kernels' ticket draws
+    # (one lane) are used a tile later, and the combining waits for them at once
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{INCLUDE}", f"-I{CSRC}",
+    # the run-time compiler (hipRTC) of the ROCm installation that builds the library
+    f'-DQCW_ROCM_LIB="{ROCM_LIB}"',
 ]
 
 
@@ -56,7 +62,7 @@ def build(jobs: int = 8) -> str:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-           "-lpthread"]
+           "-ldl", "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     build_loadgen()

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -44,18 +45,33 @@ struct TiledSummary {
   int own_staged;      // the tile itself staged in LDS (a flip inside it moves bits 0..3)
   int reads, groups, segments, etouch_segments;
   int real;            // every combined coefficient is real (2 FMAs per group and output)
+  int specialized;     // a kernel compiled for this plan at run time is available
+  int grid, regs;            // the generic kernel's persistent grid and VGPRs per lane
+  int spec_grid, spec_regs;  // the same for the compiled kernel
 };
 
 // Plans the tiled form of a channel whose terms are all permutation type,
-// given as (flip mask, term).  Returns QCW_OK with *out == nullptr when the
-// channel does not suit it (nq outside [kTiledMinQubits, kTiledMaxQubits],
-// coefficient tables beyond the LDS budget); an error code only when device
-// memory cannot be had.
+// given as (flip mask, term), and compiles the tiled kernel specialised to the
+// plan (the generic kernel, which reads the plan from memory, serves when the
+// run-time compiler is unavailable).  Returns QCW_OK with *out == nullptr
+// when the channel does not suit it (nq outside [kTiledMinQubits,
+// kTiledMaxQubits], coefficient tables beyond the LDS budget); an error code
+// only when device memory cannot be had.
 int tiled_channel_create(int nq, double p_keep,
                          const std::vector<std::pair<uint64_t, PermTerm>> &terms,
                          TiledChannel **out);
-int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, hipStream_t s);
+// generic: run the generic kernel even when a specialised one is compiled.
+int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, hipStream_t s,
+                        bool generic);
 void tiled_channel_free(TiledChannel *t);
+// Source of the kernel specialised to the plan of these terms (host only;
+// empty when the channel does not suit the tiled kernel).
+std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms);
+// Compiles such a source for gfx950 without loading it (no device needed);
+// sets the code object's size.
+int tiled_channel_compile_check(const std::string &src, size_t *code_bytes);
+// Version of the run-time compiler, major * 100 + minor (0: unavailable).
+int tiled_channel_compiler_version();
 // Real FP64 operations per output element, as the tiled kernel evaluates them.
 int64_t tiled_channel_flops(const TiledChannel *t);
 void tiled_channel_summary(const TiledChannel *t, TiledSummary *s);

@@ -32,15 +32,19 @@
 // each XCD works through its own families, so partner reads stay in that
 // XCD's L2.
 #include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <map>
 #include <set>
+#include <string>
 #include <vector>
 
 #include "channel_tiled.h"
 #include "qcw_common.h"
+#include "rtc.h"
 
 #include "qcw.h"
 
@@ -259,22 +263,24 @@ __global__ __launch_bounds__(kTileThreads) void channel_tiled_kernel(const doubl
   // serialise: one counter for all of an XCD's blocks took as long as moving
   // the tiles).  The next ticket is drawn at the start of the current tile
   // and published at the next tile start, so the atomic's latency overlaps a
-  // tile's work.
+  // tile's work.  (The library is built without the compiler's wave-level
+  // atomic combining, which would read the drawn value right after the
+  // atomic and so wait for its round trip there.)
   const uint32_t x = blockIdx.x & 7u;
   const uint32_t sub = (blockIdx.x >> 3) % A.nsub;
   uint32_t *counter = A.tickets + (x * kTicketSubs + sub) * kTicketStride;
   __shared__ uint32_t s_ticket[2];
-  uint32_t next = 0;
-  if (threadIdx.x == 0) next = atomicAdd(counter, 1u) * A.nsub + sub;
+  uint32_t drawn = 0;  // the counter's value; its ticket is drawn * nsub + sub
+  if (threadIdx.x == 0) drawn = atomicAdd(counter, 1u);
   for (uint32_t it = 0;; ++it) {
-    if (threadIdx.x == 0) s_ticket[it & 1u] = next;
+    if (threadIdx.x == 0) s_ticket[it & 1u] = drawn * A.nsub + sub;
     // Also the tile-start barrier: the previous tile's LDS reads are done
     // (first time: tables copied).  The ticket slot alternates, so the next
     // one cannot overwrite one still being read.
     __syncthreads();
     const uint32_t j = s_ticket[it & 1u];
     if (j >= A.xcd_tiles) break;
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1u) * A.nsub + sub;
+    if (threadIdx.x == 0) drawn = atomicAdd(counter, 1u);
     const uint32_t family = ((j >> A.mb_bits) << 3) | x;
     uint32_t nb = (j & mmask) << 4;  // the member's bits, zeros inserted at E0 and E1
     nb = ((nb >> A.e0) << (A.e0 + 1)) | (nb & (d1 - 1u));
@@ -395,6 +401,9 @@ struct TiledChannel {
   unsigned grid = 0;
   int64_t flops = 0;
   TiledSummary sum{};
+  const RtcKernel *spec = nullptr;  // the kernel compiled for this plan
+  unsigned spec_grid = 0;
+  uint32_t spec_xcd_blocks = 0, spec_nsub = 0;
 };
 
 namespace {
@@ -460,13 +469,264 @@ std::vector<double2> segment_table(const SegBuild &s) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Ticket counters per XCD for a grid of xcd_blocks blocks per XCD: a power of
+// two, at most kTicketSubs, each counter serving at least two blocks.
+uint32_t ticket_subs(uint32_t xcd_blocks) {
+  uint32_t n = 1;
+  while (n < kTicketSubs && 2 * n <= xcd_blocks) n *= 2;
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// The kernel specialised to one plan, compiled at run time.  It is the tiled
+// kernel above with the plan's descriptors turned into code: partner flips,
+// read sets, group kinds and segment qubits become constants, so nothing is
+// decoded per group.  A segment's table index is split into the fields of
+// its qubits at bits 0..3 (fixed per thread for the whole launch: hoisted
+// out of the tile loop) and the others (the same for the whole tile, or for
+// one output a on E0/E1: scalar arithmetic).  The thread fields are the
+// low digits of the index (a segment's qubits are in ascending bit order),
+// so the two parts add.  Groups, segments and products run in the generic
+// kernel's order with its operations, so the two kernels agree bit for bit.
+
+struct GenPlan {
+  int nq, e0, e1, mb_bits;
+  uint32_t xcd_tiles;
+  bool real, own_staged, any_staged;
+  size_t tab_entries;
+  const std::vector<TPartner> *partners;
+  const std::vector<TRead> *reads;
+  const std::vector<TRec> *recs;  // entry_b still the table entry index
+};
+
+void add(std::string &s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void add(std::string &s, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  s += buf;
+}
+
+constexpr const char *kSpecName = "qcw_channel_tiled_spec";
+
+std::string tiled_source(const GenPlan &G) {
+  const int nq = G.nq, e0 = G.e0, e1 = G.e1;
+  const std::vector<TPartner> &P = *G.partners;
+  const std::vector<TRead> &R = *G.reads;
+  const std::vector<TRec> &S = *G.recs;
+  std::string s;
+  // the uniform fields the segments need
+  std::set<int> ubits;
+  bool need_e0 = false, need_e1 = false;
+  for (const TRec &rc : S)
+    for (uint32_t j = 0; j < rc.nbits; ++j) {
+      const int b = (int)((j == 0 ? rc.sh0 : j == 1 ? rc.sh1 : rc.sh2) / 2);
+      if (b == e0) need_e0 = true;
+      else if (b == e1) need_e1 = true;
+      else if (b >= 4) ubits.insert(b);
+    }
+  add(s, "typedef unsigned int u32;\ntypedef unsigned long long u64;\n");
+  add(s, "typedef double dbl2v __attribute__((ext_vector_type(2)));\n");
+  add(s, "typedef %s CT;\n", G.real ? "double" : "double2");
+  s += R"(
+__device__ __forceinline__ void madd(double2 &acc, double c, double2 v) {
+  acc.x = __fma_rn(c, v.x, acc.x);
+  acc.y = __fma_rn(c, v.y, acc.y);
+}
+__device__ __forceinline__ void madd(double2 &acc, double2 c, double2 v) {
+  acc.x = __fma_rn(c.x, v.x, acc.x);
+  acc.x = __fma_rn(-c.y, v.y, acc.x);
+  acc.y = __fma_rn(c.x, v.y, acc.y);
+  acc.y = __fma_rn(c.y, v.x, acc.y);
+}
+__device__ __forceinline__ double cadd(double a, double b) { return a + b; }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  a.x += b.x;
+  a.y += b.y;
+  return a;
+}
+)";
+  add(s, "extern \"C\" __global__ __launch_bounds__(%d) void %s(const double2 *__restrict__ rho, "
+         "double2 *__restrict__ out, const CT *__restrict__ tables, u32 *tickets, double p_keep, "
+         "u32 xcd_blocks, u32 nsub) {\n", kTileThreads, kSpecName);
+  if (G.own_staged) add(s, "  __shared__ double2 own_slot[%d];\n", kTileElems);
+  if (G.any_staged) add(s, "  __shared__ double2 part_slot[%d];\n", kTileElems);
+  if (G.tab_entries) {
+    add(s, "  __shared__ CT tab[%zu];\n", G.tab_entries);
+    add(s, "  for (u32 i = threadIdx.x; i < %zuu; i += %du) tab[i] = tables[i];\n", G.tab_entries,
+        kTileThreads);
+  }
+  add(s, "  __shared__ u32 s_ticket[2];\n");
+  add(s, "  const u32 tid = threadIdx.x, r = tid >> 4, c = tid & 15u;\n");
+  add(s, "  const u32 t0b = ((r << %d) | c) << 4;\n", nq);
+  for (int b = 0; b < 4; ++b) add(s, "  const u32 tf%d = (((r >> %d) & 1u) << 1) | ((c >> %d) & 1u);\n", b, b, b);
+  add(s, "  const u32 x = blockIdx.x & 7u, sub = (blockIdx.x >> 3) %% nsub;\n");
+  add(s, "  u32 *counter = tickets + (x * %uu + sub) * %uu;\n", kTicketSubs, kTicketStride);
+  add(s, "  u32 drawn = 0;\n  if (tid == 0) drawn = atomicAdd(counter, 1u);\n");
+  add(s, "  for (u32 it = 0;; ++it) {\n");
+  add(s, "    if (tid == 0) s_ticket[it & 1u] = drawn * nsub + sub;\n    __syncthreads();\n");
+  add(s, "    const u32 j = __builtin_amdgcn_readfirstlane(s_ticket[it & 1u]);\n");
+  add(s, "    if (j >= %uu) break;\n", G.xcd_tiles);
+  add(s, "    if (tid == 0) drawn = atomicAdd(counter, 1u);\n");
+  // The thread's byte offset, made opaque for the tile: otherwise the
+  // compiler hoists rho + t0b out of the loop and forms every address with a
+  // 64-bit vector add, where (per-tile scalar base) + (32-bit vector offset)
+  // needs none.
+  add(s, "    u32 tv = t0b;\n    asm volatile(\"\" : \"+v\"(tv));\n");
+  add(s, "    const u32 family = ((j >> %d) << 3) | x;\n", G.mb_bits);
+  add(s, "    u32 nb = (j & %uu) << 4;\n", (1u << G.mb_bits) - 1u);
+  add(s, "    nb = ((nb >> %d) << %d) | (nb & %uu);\n", e0, e0 + 1, (1u << e0) - 1u);
+  add(s, "    nb = ((nb >> %d) << %d) | (nb & %uu);\n", e1, e1 + 1, (1u << e1) - 1u);
+  add(s, "    const u32 mb = nb ^ (family << 4);\n");
+  add(s, "    const u64 u0 = (((u64)nb << %d) | mb) << 4;\n", nq);
+  for (int b : ubits) add(s, "    const u32 uf%d = (((nb >> %d) & 1u) << 1) | ((mb >> %d) & 1u);\n", b, b, b);
+  if (need_e0) add(s, "    const u32 fa0_0 = (mb >> %d) & 1u, fa0_1 = 2u | (fa0_0 ^ 1u);\n", e0);
+  if (need_e1) add(s, "    const u32 fa1_0 = (mb >> %d) & 1u, fa1_1 = 2u | (fa1_0 ^ 1u);\n", e1);
+  // byte offset of block b of a tile: (dep(b) << nq | dep(b)) * 16
+  uint64_t db[4];
+  for (int b = 0; b < 4; ++b) {
+    const uint64_t d = ((b & 1) ? 1ull << e0 : 0) | ((b & 2) ? 1ull << e1 : 0);
+    db[b] = ((d << nq) | d) << 4;
+  }
+  auto load = [&](const char *dst, uint64_t fb, int b, uint32_t lflob) {
+    add(s, "    const double2 %s = *(const double2 *)((const char *)rho + (u0 ^ %lluull) + (tv ^ %uu));\n",
+        dst, (unsigned long long)(fb ^ db[b]), lflob);
+  };
+  for (int a = 0; a < 4; ++a) {
+    char nm[16];
+    snprintf(nm, sizeof(nm), "own%d", a);
+    load(nm, 0, a, 0);
+  }
+  const int np = (int)P.size();
+  auto issue = [&](int p1) {
+    for (int k = 0; k < kRound && p1 + k < np; ++k)
+      for (int b = 0; b < 4; ++b) {
+        char nm[24];
+        snprintf(nm, sizeof(nm), "q%d_%d", p1 + k, b);
+        load(nm, P[p1 + k].fRb, b, P[p1 + k].lflob);
+      }
+  };
+  if (np > 1) issue(1);
+  if (G.own_staged)
+    for (int a = 0; a < 4; ++a) add(s, "    own_slot[%d + tid] = own%d;\n", a * 256, a);
+  add(s, "    double2 acc0 = make_double2(0.0, 0.0), acc1 = acc0, acc2 = acc0, acc3 = acc0;\n");
+
+  // Table index of segment rc for output a (a < 0: the segment avoids E0/E1).
+  auto index = [&](const TRec &rc, int a) {
+    std::string e;
+    for (uint32_t j = 0; j < rc.nbits; ++j) {
+      const int b = (int)((j == 0 ? rc.sh0 : j == 1 ? rc.sh1 : rc.sh2) / 2);
+      char t[48];
+      if (b < 4) snprintf(t, sizeof(t), "(tf%d << %u)", b, 2 * j);
+      else if (b == e0) snprintf(t, sizeof(t), "(fa0_%d << %u)", a & 1, 2 * j);
+      else if (b == e1) snprintf(t, sizeof(t), "(fa1_%d << %u)", (a >> 1) & 1, 2 * j);
+      else snprintf(t, sizeof(t), "(uf%d << %u)", b, 2 * j);
+      if (!e.empty()) e += " + ";
+      e += t;
+    }
+    char t[48];
+    snprintf(t, sizeof(t), "tab[%uu + ", rc.entry_b);
+    return std::string(t) + e + "]";
+  };
+  auto process = [&](int p) {
+    const TPartner &pt = P[p];
+    add(s, "    {  // partner %d\n", p);
+    if (pt.mode == kStaged) {
+      add(s, "    __syncthreads();\n");
+      for (int b = 0; b < 4; ++b) add(s, "    part_slot[%d + tid] = q%d_%d;\n", b * 256, p, b);
+      add(s, "    __syncthreads();\n");
+    } else if (pt.mode == kOwn && G.own_staged) {
+      add(s, "    __syncthreads();\n");
+    }
+    for (uint32_t ri = pt.r_first; ri < pt.r_first + pt.r_count; ++ri) {
+      const TRead &rd = R[ri];
+      add(s, "    {  // read set f_lo*17 = %u\n", rd.flo17);
+      for (int b = 0; b < 4; ++b) {
+        if (pt.mode == kOwn && rd.flo17 == 0) add(s, "    const double2 v%d = own%d;\n", b, b);
+        else if (pt.mode == kOwn) add(s, "    const double2 v%d = own_slot[%d + (tid ^ %uu)];\n", b, b * 256, rd.flo17);
+        else if (pt.mode == kStaged) add(s, "    const double2 v%d = part_slot[%d + (tid ^ %uu)];\n", b, b * 256, rd.flo17);
+        else add(s, "    const double2 v%d = q%d_%d;\n", b, p, b);
+      }
+      uint32_t ob = rd.rec;
+      for (int kind = 0; kind < kKinds; ++kind) {
+        const int fe = kind >> 1;
+        const bool uni = (kind & 1) == 0;
+        for (uint32_t g = 0; g < rd.count[kind]; ++g) {
+          const TRec &first = S[ob];
+          const uint32_t nseg = 1 + first.extra;
+          add(s, "    {\n");
+          if (uni) {
+            add(s, "      CT cg = %s;\n", index(first, 0).c_str());
+            for (uint32_t e = 1; e < nseg; ++e) add(s, "      cg = cadd(cg, %s);\n", index(S[ob + e], 0).c_str());
+            for (int a = 0; a < 4; ++a) add(s, "      madd(acc%d, cg, v%d);\n", a, a ^ fe);
+          } else {
+            for (int a = 0; a < 4; ++a) add(s, "      CT c%d = %s;\n", a, index(first, a).c_str());
+            for (uint32_t e = 1; e < nseg; ++e) {
+              const TRec &sg = S[ob + e];
+              if (sg.etouch) {
+                for (int a = 0; a < 4; ++a) add(s, "      c%d = cadd(c%d, %s);\n", a, a, index(sg, a).c_str());
+              } else {
+                add(s, "      { const CT t = %s;\n", index(sg, 0).c_str());
+                for (int a = 0; a < 4; ++a) add(s, "        c%d = cadd(c%d, t);\n", a, a);
+                add(s, "      }\n");
+              }
+            }
+            for (int a = 0; a < 4; ++a) add(s, "      madd(acc%d, c%d, v%d);\n", a, a, a ^ fe);
+          }
+          add(s, "    }\n");
+          ob += nseg;
+        }
+      }
+      add(s, "    }\n");
+    }
+    add(s, "    }\n");
+  };
+  process(0);
+  for (int p1 = 1; p1 < np; p1 += kRound) {
+    if (p1 > 1) issue(p1);
+    for (int k = 0; k < kRound && p1 + k < np; ++k) process(p1 + k);
+  }
+  for (int a = 0; a < 4; ++a) {
+    add(s, "    acc%d.x = __fma_rn(p_keep, own%d.x, acc%d.x);\n", a, a, a);
+    add(s, "    acc%d.y = __fma_rn(p_keep, own%d.y, acc%d.y);\n", a, a, a);
+  }
+  for (int a = 0; a < 4; ++a) {
+    add(s, "    { const dbl2v w = {acc%d.x, acc%d.y};\n", a, a);
+    add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (u0 ^ %lluull) + tv)); }\n",
+        (unsigned long long)db[a]);
+  }
+  add(s, "  }\n");
+  add(s, "  u32 *done = tickets + (%uu + x) * %uu;\n", 8 * kTicketSubs, kTicketStride);
+  add(s, "  if (tid == 0 && atomicAdd(done, 1u) == xcd_blocks - 1u) {\n");
+  add(s, "    for (u32 k = 0; k < nsub; ++k) atomicExch(tickets + (x * %uu + k) * %uu, 0u);\n", kTicketSubs,
+      kTicketStride);
+  add(s, "    atomicExch(done, 0u);\n  }\n}\n");
+  return s;
+}
+
 }  // namespace
 
-int tiled_channel_create(int nq, double p_keep,
-                         const std::vector<std::pair<uint64_t, PermTerm>> &terms,
-                         TiledChannel **out) {
-  *out = nullptr;
-  if (nq < kTiledMinQubits || nq > kTiledMaxQubits) return QCW_OK;
+namespace {
+
+// A plan on the host: the descriptor and table bytes the generic kernel
+// reads, their layout, and the source of the kernel specialised to it.
+struct HostPlan {
+  int e0 = 0, e1 = 0;
+  bool real = false;
+  TiledSummary sm{};
+  int npartners = 0;
+  size_t tab_entries = 0, tab_bytes = 0, tab_lds0 = 0;
+  size_t o_p = 0, o_r = 0, o_s = 0, o_t = 0, o_k = 0;
+  std::vector<unsigned char> bytes;  // descriptors, tables, zeroed ticket counters
+  int64_t flops = 0;
+  std::string src;
+};
+
+// False when the channel does not suit the tiled kernel.
+bool plan_host(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms, HostPlan &H) {
+  if (nq < kTiledMinQubits || nq > kTiledMaxQubits) return false;
   const uint32_t N = 1u << nq;
   std::map<uint32_t, std::vector<const PermTerm *>> by_flip;
   for (const auto &pr : terms) by_flip[(uint32_t)pr.first].push_back(&pr.second);
@@ -575,10 +835,24 @@ int tiled_channel_create(int nq, double p_keep,
   bool real = true;
   for (const double2 &v : tab) real = real && v.y == 0.0;
   const size_t tab_bytes = tab.size() * (real ? sizeof(double) : sizeof(double2));
-  if (tab_bytes > kTableBytesMax) return QCW_OK;
+  if (tab_bytes > kTableBytesMax) return false;
   sm.partners = (int)partners.size();
   sm.reads = (int)reads.size();
   sm.real = real ? 1 : 0;
+  GenPlan gp;
+  gp.nq = nq;
+  gp.e0 = e0;
+  gp.e1 = e1;
+  gp.mb_bits = nq - 6;
+  gp.xcd_tiles = 1u << (2 * nq - 13);
+  gp.real = real;
+  gp.own_staged = sm.own_staged != 0;
+  gp.any_staged = sm.staged > 0;
+  gp.tab_entries = tab.size();
+  gp.partners = &partners;
+  gp.reads = &reads;
+  gp.recs = &recs;
+  const std::string spec_src = tiled_source(gp);
   // LDS: the own tile (when staged), the staged partner, then the tables.
   const size_t tab_lds0 = (sm.own_staged ? kTileElems * sizeof(double2) : 0) +
                           (sm.staged ? kTileElems * sizeof(double2) : 0);
@@ -600,35 +874,74 @@ int tiled_channel_create(int nq, double p_keep,
     else
       memcpy(host.data() + o_t + i * sizeof(double2), &tab[i], sizeof(double2));
   }
+  H.e0 = e0;
+  H.e1 = e1;
+  H.real = real;
+  H.sm = sm;
+  H.npartners = (int)partners.size();
+  H.tab_entries = tab.size();
+  H.tab_bytes = tab_bytes;
+  H.tab_lds0 = tab_lds0;
+  H.o_p = o_p;
+  H.o_r = o_r;
+  H.o_s = o_s;
+  H.o_t = o_t;
+  H.o_k = o_k;
+  H.bytes = std::move(host);
+  H.flops = 2 + flops_groups * (real ? 4 : 8) + flops_segs * (real ? 1 : 2);
+  H.src = spec_src;
+  return true;
+}
 
+}  // namespace
+
+std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms) {
+  HostPlan H;
+  return plan_host(nq, terms, H) ? H.src : std::string();
+}
+
+int tiled_channel_compile_check(const std::string &src, size_t *code_bytes) {
+  return rtc_compile(src, kSpecName, code_bytes);
+}
+
+int tiled_channel_compiler_version() { return rtc_compiler_version(); }
+
+int tiled_channel_create(int nq, double p_keep,
+                         const std::vector<std::pair<uint64_t, PermTerm>> &terms,
+                         TiledChannel **out) {
+  *out = nullptr;
+  HostPlan H;
+  if (!plan_host(nq, terms, H)) return QCW_OK;
+  const size_t total = H.bytes.size();
   TiledChannel *t = new TiledChannel();
-  t->real = real;
-  t->sum = sm;
-  t->lds = tab_lds0 + tab_bytes;
-  t->flops = 2 + flops_groups * (real ? 4 : 8) + flops_segs * (real ? 1 : 2);
+  t->real = H.real;
+  t->sum = H.sm;
+  t->lds = H.tab_lds0 + H.tab_bytes;
+  t->flops = H.flops;
   if (hipMalloc(&t->dbuf, total) != hipSuccess ||
-      hipMemcpy(t->dbuf, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(t->dbuf, H.bytes.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
     tiled_channel_free(t);
     return fail(QCW_ENOMEM, "channel plan upload failed");
   }
+  const bool real = H.real;
   unsigned char *d = static_cast<unsigned char *>(t->dbuf);
   TArgs &A = t->args;
   A.nq = nq;
-  A.e0 = e0;
-  A.e1 = e1;
+  A.e0 = H.e0;
+  A.e1 = H.e1;
   A.mb_bits = nq - 6;
   A.p_keep = p_keep;
   A.xcd_tiles = 1u << (2 * nq - 13);
-  A.npartners = (int)partners.size();
-  A.own_staged = sm.own_staged;
-  A.any_staged = sm.staged > 0 ? 1 : 0;
-  A.tab_entries = (int)tab.size();
-  A.partners = reinterpret_cast<const TPartner *>(d + o_p);
-  A.reads = reinterpret_cast<const TRead *>(d + o_r);
-  A.recs = reinterpret_cast<const TRec *>(d + o_s);
-  A.tables = d + o_t;
-  A.tickets = reinterpret_cast<uint32_t *>(d + o_k);
+  A.npartners = H.npartners;
+  A.own_staged = H.sm.own_staged;
+  A.any_staged = H.sm.staged > 0 ? 1 : 0;
+  A.tab_entries = (int)H.tab_entries;
+  A.partners = reinterpret_cast<const TPartner *>(d + H.o_p);
+  A.reads = reinterpret_cast<const TRead *>(d + H.o_r);
+  A.recs = reinterpret_cast<const TRec *>(d + H.o_s);
+  A.tables = d + H.o_t;
+  A.tickets = reinterpret_cast<uint32_t *>(d + H.o_k);
 
   // Persistent grid: resident blocks over the device, a multiple of the 8
   // XCDs so that a block keeps its XCD's families.
@@ -646,8 +959,10 @@ int tiled_channel_create(int nq, double p_keep,
   // too (512 VGPRs per lane and SIMD in granules of 8; a block is one wave
   // per SIMD).
   hipFuncAttributes fa;
-  if (hipFuncGetAttributes(&fa, tiled_fn(real)) == hipSuccess && fa.numRegs > 0)
+  if (hipFuncGetAttributes(&fa, tiled_fn(real)) == hipSuccess && fa.numRegs > 0) {
     bpc = std::min(bpc, std::min(8, 512 / ((fa.numRegs + 7) / 8 * 8)));
+    t->sum.regs = fa.numRegs;
+  }
   (void)hipGetLastError();
   if (bpc < 1) {
     tiled_channel_free(t);
@@ -656,13 +971,48 @@ int tiled_channel_create(int nq, double p_keep,
   const uint64_t want = std::min<uint64_t>((uint64_t)bpc * ncu, (uint64_t)A.xcd_tiles * 8);
   t->grid = (unsigned)std::max<uint64_t>(8, want & ~(uint64_t)7);
   A.xcd_blocks = t->grid / 8;
-  A.nsub = 1;
-  while (A.nsub < kTicketSubs && 2 * A.nsub <= A.xcd_blocks) A.nsub *= 2;
+  A.nsub = ticket_subs(A.xcd_blocks);
+
+  // The kernel compiled for this plan; without it the generic kernel runs.
+  const RtcKernel *k = nullptr;
+  if (rtc_get(H.src, kSpecName, &k) == QCW_OK) {
+    int sbpc = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&sbpc, k->fn, kTileThreads, 0) == hipSuccess &&
+        k->num_regs > 0)
+      sbpc = std::min(sbpc, std::min(8, 512 / ((k->num_regs + 7) / 8 * 8)));
+    (void)hipGetLastError();
+    if (sbpc >= 1) {
+      const uint64_t sw = std::min<uint64_t>((uint64_t)sbpc * ncu, (uint64_t)A.xcd_tiles * 8);
+      t->spec = k;
+      t->spec_grid = (unsigned)std::max<uint64_t>(8, sw & ~(uint64_t)7);
+      t->spec_xcd_blocks = t->spec_grid / 8;
+      t->spec_nsub = ticket_subs(t->spec_xcd_blocks);
+    }
+  }
+  t->sum.specialized = t->spec ? 1 : 0;
+  t->sum.grid = (int)t->grid;
+  t->sum.spec_grid = (int)t->spec_grid;
+  t->sum.spec_regs = k ? k->num_regs : 0;
+  clear_error();
   *out = t;
   return QCW_OK;
 }
 
-int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, hipStream_t s) {
+int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, hipStream_t s,
+                        bool generic) {
+  if (t->spec && !generic) {
+    const double2 *a_in = in;
+    double2 *a_out = out;
+    const void *a_tab = t->args.tables;
+    uint32_t *a_tk = t->args.tickets;
+    double a_p = t->args.p_keep;
+    uint32_t a_xb = t->spec_xcd_blocks, a_ns = t->spec_nsub;
+    void *args[] = {&a_in, &a_out, &a_tab, &a_tk, &a_p, &a_xb, &a_ns};
+    if (hipModuleLaunchKernel(t->spec->fn, t->spec_grid, 1, 1, kTileThreads, 1, 1, 0, s, args, nullptr) !=
+        hipSuccess)
+      return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(hipGetLastError()));
+    return QCW_OK;
+  }
   if (t->real)
     hipLaunchKernelGGL(channel_tiled_kernel<true>, dim3(t->grid), dim3(kTileThreads), t->lds, s, in,
                        out, t->args);

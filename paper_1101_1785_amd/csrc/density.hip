@@ -416,6 +416,7 @@ struct qcw_channel {
   int64_t flops_gather = 0;       // real FP64 operations per output element, gather kernel
   TiledChannel *tiled = nullptr;  // tiled plan (permutation terms only, 7 <= nq <= 15)
   int force_gather = 0;           // run the gather kernel even with a tiled plan
+  int tiled_generic = 0;          // run the generic tiled kernel even with a compiled one
 };
 
 namespace {
@@ -457,15 +458,15 @@ int qcw_rho_conjugate(int k, const int *targets, const qcw_c64 *U, qcw_c64 *rho,
   return launch_sweep(gc, Uc, rho, rho, (hipStream_t)stream);
 }
 
-int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus_term *terms,
-                       int nterms, const qcw_c64 *mats, int64_t nmats) {
-  clear_error();
-  if (!out) return fail(QCW_EINVAL, "out is NULL");
-  *out = nullptr;
+namespace {
+
+// Validates the terms and splits them into permutation-type terms (with
+// their flip masks, sorted by flip mask, one-operator terms first within a
+// mask, otherwise in input order) and general terms.
+int parse_terms(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *mats, int64_t nmats,
+                std::vector<DevTerm> &dt, std::vector<std::pair<uint64_t, PermTerm>> &pt) {
   if (nq < 1 || nq > kRhoMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [1, %d]", nq, kRhoMaxQubits);
   if (nterms < 0 || (nterms > 0 && (!terms || !mats))) return fail(QCW_EINVAL, "bad term list");
-  std::vector<DevTerm> dt;
-  std::vector<std::pair<uint64_t, PermTerm>> pt;  // (flip mask, term)
   for (int i = 0; i < nterms; ++i) {
     const qcw_kraus_term &t = terms[i];
     if (t.nops < 1 || t.nops > 2) return fail(QCW_EINVAL, "term %d: nops=%d outside {1, 2}", i, t.nops);
@@ -527,6 +528,22 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
                      if (a.first != b.first) return a.first < b.first;
                      return a.second.nops < b.second.nops;
                    });
+  return QCW_OK;
+}
+
+}  // namespace
+
+int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus_term *terms,
+                       int nterms, const qcw_c64 *mats, int64_t nmats) {
+  clear_error();
+  if (!out) return fail(QCW_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::vector<DevTerm> dt;
+  std::vector<std::pair<uint64_t, PermTerm>> pt;  // (flip mask, term)
+  {
+    const int rc = parse_terms(nq, terms, nterms, mats, nmats, dt, pt);
+    if (rc) return rc;
+  }
   std::vector<PermGroup> groups;
   std::vector<PermTerm> perm;
   int64_t flops = 2;  // p_keep * rho
@@ -606,7 +623,8 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
   const double2 *in = reinterpret_cast<const double2 *>(rho_in);
   double2 *o = reinterpret_cast<double2 *>(rho_out);
-  if (c->tiled && !c->force_gather) return tiled_channel_apply(c->tiled, in, o, (hipStream_t)stream);
+  if (c->tiled && !c->force_gather)
+    return tiled_channel_apply(c->tiled, in, o, (hipStream_t)stream, c->tiled_generic != 0);
   if (c->nperm > 0 && c->nperm <= kChanTableMaxTerms && c->nq <= kChanTableMaxQubits)
     hipLaunchKernelGGL(channel_kernel<true>, dim3(blocks), dim3(kChanThreads),
                        (sizeof(double2) * 8 + sizeof(int) * 2) * c->nperm, (hipStream_t)stream, in,
@@ -632,16 +650,50 @@ int64_t qcw_channel_flops_per_element(const qcw_channel *c) {
   return c->tiled && !c->force_gather ? tiled_channel_flops(c->tiled) : c->flops_gather;
 }
 
-int qcw_debug_channel_plan(qcw_channel *c, int force_gather, int32_t *info) {
+int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info) {
   clear_error();
   if (!c || !info) return fail(QCW_EINVAL, "channel or info is NULL");
-  if (force_gather >= 0) c->force_gather = force_gather ? 1 : 0;
+  if (kernel > 2) return fail(QCW_EINVAL, "kernel choice %d outside [-1, 2]", kernel);
+  if (kernel >= 0) {
+    c->force_gather = kernel == 1 ? 1 : 0;
+    c->tiled_generic = kernel == 2 ? 1 : 0;
+  }
   TiledSummary sm{};
   tiled_channel_summary(c->tiled, &sm);
-  const int32_t v[13] = {c->tiled ? 1 : 0, c->tiled && !c->force_gather ? 0 : 1, sm.e0, sm.e1,
+  const bool tiled = c->tiled && !c->force_gather;
+  const bool spec = tiled && sm.specialized && !c->tiled_generic;
+  const int32_t v[17] = {c->tiled ? 1 : 0, tiled ? 0 : 1, sm.e0, sm.e1,
                          sm.partners, sm.staged, sm.direct, sm.own_staged, sm.reads, sm.groups,
-                         sm.segments, sm.etouch_segments, sm.real};
+                         sm.segments, sm.etouch_segments, sm.real, spec ? 1 : 0,
+                         tiled ? (spec ? sm.spec_grid : sm.grid) : 0,
+                         tiled ? (spec ? sm.spec_regs : sm.regs) : 0,
+                         sm.specialized ? tiled_channel_compiler_version() : 0};
   memcpy(info, v, sizeof(v));
+  return QCW_OK;
+}
+
+int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *mats,
+                             int64_t nmats, int compile, char *buf, size_t cap, size_t *len,
+                             size_t *code_bytes, int32_t *compiler_version) {
+  clear_error();
+  if (compiler_version) *compiler_version = tiled_channel_compiler_version();
+  if (!len) return fail(QCW_EINVAL, "len is NULL");
+  if (compile && !code_bytes) return fail(QCW_EINVAL, "code_bytes is NULL");
+  std::vector<DevTerm> dt;
+  std::vector<std::pair<uint64_t, PermTerm>> pt;
+  int rc = parse_terms(nq, terms, nterms, mats, nmats, dt, pt);
+  if (rc) return rc;
+  const std::string src = dt.empty() ? tiled_channel_source(nq, pt) : std::string();
+  *len = src.size();
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, src.size());
+    memcpy(buf, src.data(), n);
+    buf[n] = 0;
+  }
+  if (compile) {
+    *code_bytes = 0;
+    if (!src.empty() && (rc = tiled_channel_compile_check(src, code_bytes))) return rc;
+  }
   return QCW_OK;
 }
 
