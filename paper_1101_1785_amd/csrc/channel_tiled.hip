@@ -513,8 +513,10 @@ constexpr const char *kSpecName = "qcw_channel_tiled_spec";
 // Resident blocks per CU for the compiled kernel.  With four, the tiles in
 // flight on an XCD (and the partner tiles they read) outgrow its L2 and the
 // partner reads go back to memory: at nq = 13 the HBM reads per launch were
-// 2.3 times the state, against 1.2 times with three, which also ran faster.
-constexpr int kSpecBlocksPerCU = 3;
+// 2.3 times the state, against 1.2 times with three, which also ran faster
+// (0.53 ms against 0.55; two: 0.58).  At nq = 12 two ran fastest (0.111 ms,
+// three 0.132, four 0.166); at nq = 14 two and three tie.
+int spec_blocks_per_cu(int nq) { return nq <= 12 ? 2 : 3; }
 
 std::string tiled_source(const GenPlan &G) {
   const int nq = G.nq, e0 = G.e0, e1 = G.e1;
@@ -984,7 +986,7 @@ int tiled_channel_create(int nq, double p_keep,
     int sbpc = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&sbpc, k->fn, kTileThreads, 0) == hipSuccess &&
         k->num_regs > 0)
-      sbpc = std::min(sbpc, std::min(kSpecBlocksPerCU, 512 / ((k->num_regs + 7) / 8 * 8)));
+      sbpc = std::min(sbpc, std::min(spec_blocks_per_cu(nq), 512 / ((k->num_regs + 7) / 8 * 8)));
     (void)hipGetLastError();
     if (sbpc >= 1) {
       const uint64_t sw = std::min<uint64_t>((uint64_t)sbpc * ncu, (uint64_t)A.xcd_tiles * 8);
