@@ -54,11 +54,43 @@ struct alignas(16) FusedPass {
 
 typedef double v2d __attribute__((ext_vector_type(2)));
 
+// Wave chunks.  A block of NT threads has NT / 64 waves; the tile bits below
+// wave_tile_bits<T, NT> index within a chunk of the tile, the bits above
+// pick the chunk.  A gate whose targets are all below that bit maps every
+// chunk onto itself: when each wave takes its groups from its own chunk, two
+// such gates in a row need no block barrier between them (a wave's LDS
+// operations complete in order), and neither do the staging of the tile and
+// such a gate, done chunk by chunk as well.
+template <int T, int NT>
+constexpr int wave_tile_bits() {
+  return T - (NT >= 1024 ? 4 : NT >= 512 ? 3 : NT >= 256 ? 2 : NT >= 128 ? 1 : 0);
+}
+
+// Group i of thread tid for a K-qubit gate: strided over the block, or
+// (local) within the thread's wave chunk.  Either way the groups of a gate
+// are dealt out once each, and each is computed as in the sweep.
+template <int K, int NT, int T>
+__device__ __forceinline__ uint32_t group_of(int i, uint32_t tid, bool local) {
+  constexpr int TW = wave_tile_bits<T, NT>();
+  if (TW - K >= 6 && local)
+    return ((tid >> 6) << (TW - K)) | ((uint32_t)i << 6) | (tid & 63u);
+  return (uint32_t)i * NT + tid;
+}
+
+// The gate keeps every wave chunk (all targets below the chunk bits), and
+// its groups fill whole waves (so group_of may deal them per chunk).
+template <int T, int NT>
+__device__ __forceinline__ bool chunk_local(const FusedGate &g) {
+  constexpr int TW = wave_tile_bits<T, NT>();
+  const int top = g.k == 1 ? g.sb0 : g.k == 2 ? g.sb1 : g.sb2;
+  return top < TW && TW - g.k >= 6;
+}
+
 // One gate on a tile of 2^T amplitudes in LDS, NT threads.  Each thread owns
 // 2^(T-K) / NT groups (fixed at compile time) and issues the LDS reads of all
 // of them before any arithmetic, so several reads are in flight per lane.
 template <int K, int NT, int T>
-__device__ __forceinline__ void tile_gate(double2 *S, const FusedGate &g) {
+__device__ __forceinline__ void tile_gate(double2 *S, const FusedGate &g, bool local) {
   constexpr int M = 1 << K;
   constexpr uint32_t NG = 1u << (T - K);
   constexpr int G = NG >= NT ? (int)(NG / NT) : 1;
@@ -67,7 +99,7 @@ __device__ __forceinline__ void tile_gate(double2 *S, const FusedGate &g) {
   uint32_t base[G];
 #pragma unroll
   for (int i = 0; i < G; ++i) {
-    const uint32_t j = i * NT + tid;
+    const uint32_t j = group_of<K, NT, T>(i, tid, local);
     base[i] = insert_zeros<K, uint32_t>(j, g.sb0, g.sb1, g.sb2);
     if (NG >= NT || j < NG) {
 #pragma unroll
@@ -76,7 +108,7 @@ __device__ __forceinline__ void tile_gate(double2 *S, const FusedGate &g) {
   }
 #pragma unroll
   for (int i = 0; i < G; ++i) {
-    const uint32_t j = i * NT + tid;
+    const uint32_t j = group_of<K, NT, T>(i, tid, local);
     if (NG >= NT || j < NG) {
       const uint32_t b = base[i];
       group_matvec_put<M>(x[i], [&](int r, int c) { return g.u[r * M + c]; },
@@ -93,7 +125,7 @@ __device__ __forceinline__ void tile_gate(double2 *S, const FusedGate &g) {
 // the direct product (each term is bounded by a small multiple of |U| |x|, so
 // the error stays within a small factor of it).
 template <int K, int NT, int T>
-__device__ __forceinline__ void tile_gate3m(double2 *S, const FusedGate &g) {
+__device__ __forceinline__ void tile_gate3m(double2 *S, const FusedGate &g, bool local) {
   constexpr int M = 1 << K;
   constexpr uint32_t NG = 1u << (T - K);
   constexpr int G = NG >= NT ? (int)(NG / NT) : 1;
@@ -102,7 +134,7 @@ __device__ __forceinline__ void tile_gate3m(double2 *S, const FusedGate &g) {
   uint32_t base[G];
 #pragma unroll
   for (int i = 0; i < G; ++i) {
-    const uint32_t j = i * NT + tid;
+    const uint32_t j = group_of<K, NT, T>(i, tid, local);
     base[i] = insert_zeros<K, uint32_t>(j, g.sb0, g.sb1, g.sb2);
     if (NG >= NT || j < NG) {
 #pragma unroll
@@ -111,7 +143,7 @@ __device__ __forceinline__ void tile_gate3m(double2 *S, const FusedGate &g) {
   }
 #pragma unroll
   for (int i = 0; i < G; ++i) {
-    const uint32_t j = i * NT + tid;
+    const uint32_t j = group_of<K, NT, T>(i, tid, local);
     if (NG >= NT || j < NG) {
       double sum[M];
 #pragma unroll
@@ -134,18 +166,18 @@ __device__ __forceinline__ void tile_gate3m(double2 *S, const FusedGate &g) {
 
 // One gate of a pass on a tile, in the form its plan chose.
 template <int NT, int T>
-__device__ __forceinline__ void tile_apply(double2 *S, const FusedGate &g) {
+__device__ __forceinline__ void tile_apply(double2 *S, const FusedGate &g, bool local = false) {
   if (g.m3) {
     switch (g.k) {
-      case 1: tile_gate3m<1, NT, T>(S, g); break;
-      case 2: tile_gate3m<2, NT, T>(S, g); break;
-      default: tile_gate3m<3, NT, T>(S, g); break;
+      case 1: tile_gate3m<1, NT, T>(S, g, local); break;
+      case 2: tile_gate3m<2, NT, T>(S, g, local); break;
+      default: tile_gate3m<3, NT, T>(S, g, local); break;
     }
   } else {
     switch (g.k) {
-      case 1: tile_gate<1, NT, T>(S, g); break;
-      case 2: tile_gate<2, NT, T>(S, g); break;
-      default: tile_gate<3, NT, T>(S, g); break;
+      case 1: tile_gate<1, NT, T>(S, g, local); break;
+      case 2: tile_gate<2, NT, T>(S, g, local); break;
+      default: tile_gate<3, NT, T>(S, g, local); break;
     }
   }
 }
@@ -167,27 +199,35 @@ __global__ __launch_bounds__(NT) void fused_pass_kernel(double2 *psi,
     uint64_t b = blockIdx.x;
     for (int j = 0; j < P.n_outer; ++j) tile_base |= ((b >> j) & 1ull) << P.outer_pos[j];
   }
+  // Amplitude q of this thread: element q * 64 + lane of its wave's chunk
+  // (64 consecutive elements per wave and q: whole 16-amplitude chunks of
+  // the state, as before).
+  constexpr int TW = wave_tile_bits<T, NT>();
+  static_assert(PER == 1 << (TW - 6), "a wave chunk is PER elements per lane");
+  const uint32_t chunk0 = (threadIdx.x >> 6) << TW, lane = threadIdx.x & 63u;
   v2d v[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int i = q * NT + threadIdx.x;
+    const uint32_t i = chunk0 | ((uint32_t)q << 6) | lane;
     const uint64_t lab = tile_base + P.chunk_off[i >> L] + (uint32_t)(i & ((1 << L) - 1));
     v[q] = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(psi + lab));
   }
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int i = q * NT + threadIdx.x;
-    S[i] = make_double2(v[q].x, v[q].y);
-  }
-  __syncthreads();
+  for (int q = 0; q < PER; ++q) S[chunk0 | ((uint32_t)q << 6) | lane] = make_double2(v[q].x, v[q].y);
+  // A block barrier separates two steps unless both keep every wave in its
+  // chunk (the staging and the store do).
+  bool prev_local = true;
   for (int gi = 0; gi < P.ngates; ++gi) {
     const FusedGate &g = gates[P.gate_off + gi];
-    tile_apply<NT, T>(S, g);
-    __syncthreads();
+    const bool local = chunk_local<T, NT>(g);
+    if (!(local && prev_local)) __syncthreads();
+    tile_apply<NT, T>(S, g, local);
+    prev_local = local;
   }
+  if (!prev_local) __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int i = q * NT + threadIdx.x;
+    const uint32_t i = chunk0 | ((uint32_t)q << 6) | lane;
     const uint64_t lab = tile_base + P.chunk_off[i >> L] + (uint32_t)(i & ((1 << L) - 1));
     const double2 a = S[i];
     v2d w = {a.x, a.y};
