@@ -387,6 +387,16 @@ int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, int ninst,
  * without an order between them): the tiled kernel keeps its work counters
  * in the channel.
  *
+ * qcw_channel_create is synchronous and uses the current device, on which
+ * the channel must then be applied.  For a channel whose terms are all
+ * diagonal or anti-diagonal operators and 7 <= nq <= 15, it plans the tiled
+ * kernel and compiles that kernel for the plan at run time (hipRTC of the
+ * ROCm installation the library was built with).  The first channel of a
+ * given structure (qubits and operator pattern; the coefficients and p_keep
+ * do not count) takes about a second; later ones reuse the code object,
+ * which stays loaded until the process ends.  Without a run-time compiler the
+ * channel runs the generic tiled kernel, with the same results.
+ *
  * qcw_rho_observables (synchronous) writes to out_host, 4 + 3 nq doubles:
  * Tr rho (re, im); Tr rho^2 as sum |rho_nm|^2 (equal for Hermitian rho); the
  * fidelity Tr sqrt(sqrt(rho0) rho sqrt(rho0)) = sqrt(<psi0|rho|psi0>) against
