@@ -420,6 +420,21 @@ int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus
                        int nterms, const qcw_c64 *mats, int64_t nmats);
 int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out,
                       void *stream);
+/*
+ * One multiverse step of Eq. rhoE4 in one call:
+ *     rho_out = U [channel(rho_in)] U^dagger
+ * for a k-qubit algorithm gate U on the targets (conventions of qcw_opk).
+ * When U is a permutation matrix (entries exactly 0 and 1: X, CNOT, SWAP,
+ * Toffoli, ...) and the channel runs its compiled tiled kernel, the
+ * conjugation is folded into that kernel: output (n, m) is stored at
+ * (pi(n), pi(m)), one pass over rho instead of two.  The kernel for each such
+ * gate is compiled on its first use (about a second, synchronous).
+ * Otherwise it is qcw_channel_apply followed by qcw_rho_conjugate on rho_out.
+ * Either way the result is the same, bit for bit up to the sign of zeros.
+ * rho_in and rho_out must not overlap.
+ */
+int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out, int k,
+                           const int *targets, const qcw_c64 *U, void *stream);
 int qcw_channel_destroy(qcw_channel *c);
 /* Real FP64 operations per output element of one application, as evaluated
  * by the kernel the channel runs (for roofline accounting).  Terms whose
@@ -462,9 +477,11 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info);
 /*
  * The source of the tiled kernel that qcw_channel_create would compile for
  * these terms (host call, no device needed; for tests).  Arguments as for
- * qcw_channel_create.  *len: the source's length (0 when the channel has no
- * tiled plan); when buf is not NULL, up to cap - 1 bytes of it and a NUL are
- * written there.  compile != 0: the source is also compiled for gfx950 with
+ * qcw_channel_create; gate_k != 0 asks instead for the kernel that
+ * qcw_channel_apply_gate compiles for the gate (gate_k, gate_targets, gate_U),
+ * which has none (length 0) unless the gate is a permutation matrix.  *len:
+ * the source's length (0 when the channel has no tiled plan); when buf is
+ * not NULL, up to cap - 1 bytes of it and a NUL are written there.  compile != 0: the source is also compiled for gfx950 with
  * the run-time compiler and *code_bytes set to the code object's size; a
  * failed compile returns QCW_EHIP with the compiler's log in the last error.
  * compiler_version (may be NULL): the run-time compiler's version, major *
@@ -472,7 +489,8 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info);
  * len (or code_bytes when compiling).
  */
 int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *mats,
-                             int64_t nmats, int compile, char *buf, size_t cap, size_t *len,
+                             int64_t nmats, int gate_k, const int *gate_targets,
+                             const qcw_c64 *gate_U, int compile, char *buf, size_t cap, size_t *len,
                              size_t *code_bytes, int32_t *compiler_version);
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
@@ -607,8 +625,10 @@ int qcw_server_destroy(qcw_server *s);
  * family, the number of launches and their summed duration in milliseconds
  * since the last reset.  Families: QCW_KERNEL_SWEEP1..3 (one-gate sweeps of
  * k = 1, 2, 3, in either sweep kernel), QCW_KERNEL_BATCH (batch executions),
- * QCW_KERNEL_FUSED (fused passes), QCW_KERNEL_CHANNEL (channel applications),
- * QCW_KERNEL_SMALL (launches of qcw_circuit on states of at most 11 qubits).
+ * QCW_KERNEL_FUSED (fused passes), QCW_KERNEL_CHANNEL (channel applications,
+ * with or without a folded permutation gate), QCW_KERNEL_SMALL (launches of
+ * qcw_circuit on states of at most 11 qubits), QCW_KERNEL_CONJ (one-pass
+ * conjugations of qcw_rho_conjugate).
  * Launches recorded into a hipGraph are not timed individually.
  */
 enum {
@@ -619,7 +639,8 @@ enum {
   QCW_KERNEL_FUSED = 5, /* one fused pass */
   QCW_KERNEL_CHANNEL = 6, /* one channel application */
   QCW_KERNEL_SMALL = 7,   /* one launch of qcw_circuit on a state of <= 11 qubits */
-  QCW_KERNEL_COUNT = 8
+  QCW_KERNEL_CONJ = 8,    /* one one-pass conjugation rho <- U rho U^dagger */
+  QCW_KERNEL_COUNT = 9
 };
 int qcw_timing_enable(int on);
 int qcw_timing_reset(void);

@@ -33,6 +33,7 @@ _i64 = ctypes.c_int64
 QCW_OK, QCW_EINVAL, QCW_ENOMEM, QCW_EHIP, QCW_EAGAIN = 0, -1, -2, -3, -4
 QCW_KERNEL_SWEEP1, QCW_KERNEL_SWEEP2, QCW_KERNEL_SWEEP3, QCW_KERNEL_BATCH = 1, 2, 3, 4
 QCW_KERNEL_SMALL = 7
+QCW_KERNEL_CONJ = 8
 QCW_KERNEL_FUSED = 5
 QCW_PLAN_COMMUTE, QCW_PLAN_FUSE, QCW_PLAN_3M = 1, 2, 4
 QCW_KERNEL_CHANNEL = 6
@@ -91,8 +92,9 @@ _SIGS = {
     "qcw_channel_destroy": ([_P], _i32),
     "qcw_channel_flops_per_element": ([_P], _i64),
     "qcw_debug_channel_plan": ([_P, _i32, _P], _i32),
-    "qcw_debug_channel_source": ([_i32, _P, _i32, _P, _i64, _i32, _P, ctypes.c_size_t, _P, _P, _P],
-                                 _i32),
+    "qcw_debug_channel_source": ([_i32, _P, _i32, _P, _i64, _i32, _P, _P, _i32, _P, ctypes.c_size_t,
+                                  _P, _P, _P], _i32),
+    "qcw_channel_apply_gate": ([_P, _P, _P, _i32, _P, _P, _P], _i32),
     "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_rho_eigvals": ([_P, _i32, _P, _P], _i32),
     "qcw_rho_eigvals_batch": ([_P, _i32, _i64, _i64, _P, _P, _P], _i32),
@@ -624,14 +626,21 @@ def pack_terms(terms):
     return tab, M
 
 
-def channel_kernel_source(nq, terms, compile=False):
+def channel_kernel_source(nq, terms, compile=False, gate=None):
     """(source, code_bytes, compiler_version) of the tiled kernel a Channel
     over these terms compiles at creation (qcw_debug_channel_source; host
-    only).  source is "" when the channel has no tiled plan; code_bytes is
-    None unless compile; compiler_version is major * 100 + minor."""
+    only), or with gate = (U, targets) the one apply_gate compiles for that
+    gate ("" unless U is a permutation matrix).  source is "" when the
+    channel has no tiled plan; code_bytes is None unless compile;
+    compiler_version is major * 100 + minor."""
     tab, mats = pack_terms(terms)
     n, cb, ver = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_int32(0)
-    args = (int(nq), _hptr(tab) if len(tab) else None, len(tab), _hptr(mats), mats.size)
+    gk, gt, gu = 0, None, None
+    if gate is not None:
+        gk = len(gate[1])
+        gt, gu = _targets(gate[1]), _mat(gate[0], gk)
+    args = (int(nq), _hptr(tab) if len(tab) else None, len(tab), _hptr(mats), mats.size, gk,
+            _hptr(gt) if gt is not None else None, _hptr(gu) if gu is not None else None)
     _check(_L.qcw_debug_channel_source(*args, 0, None, 0, ctypes.byref(n), None, None),
            "qcw_debug_channel_source")
     buf = ctypes.create_string_buffer(n.value + 1)
@@ -655,6 +664,15 @@ class Channel:
     def apply(self, rho_in, rho_out, stream=None):
         _check(_L.qcw_channel_apply(self.h, _dptr(rho_in), _dptr(rho_out), _stream(stream)),
                "qcw_channel_apply")
+
+    def apply_gate(self, rho_in, rho_out, U, targets, stream=None):
+        """rho_out = U channel(rho_in) U^dagger (qcw_channel_apply_gate): one
+        pass when U is a permutation matrix and the compiled tiled kernel runs."""
+        k = len(targets)
+        t = _targets(targets)
+        U = _mat(U, k)
+        _check(_L.qcw_channel_apply_gate(self.h, _dptr(rho_in), _dptr(rho_out), k, _hptr(t),
+                                         _hptr(U), _stream(stream)), "qcw_channel_apply_gate")
 
     def flops_per_element(self):
         return int(_L.qcw_channel_flops_per_element(self.h))

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -37,6 +39,16 @@ constexpr int kTiledMaxQubits = 15;  // row and column bits interleave into bits
 
 struct TiledChannel;
 
+// A permutation gate (a k-qubit unitary that is a permutation matrix) on the
+// state bits bits[0..k-1] (argument order: bits[0] is the most significant
+// bit of the local index l).  table[l] = pi(l): U |l> = |pi(l)>.  The
+// conjugation rho -> U rho U^dagger moves element (n, m) to (pi(n), pi(m)).
+struct OutPerm {
+  int k;
+  int bits[3];
+  uint8_t table[8];
+};
+
 // Shape of a tiled plan (for tests and reports).
 struct TiledSummary {
   int e0, e1;          // the two tile bits above bit 3
@@ -64,9 +76,19 @@ int tiled_channel_create(int nq, double p_keep,
 int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, hipStream_t s,
                         bool generic);
 void tiled_channel_free(TiledChannel *t);
-// Source of the kernel specialised to the plan of these terms (host only;
-// empty when the channel does not suit the tiled kernel).
-std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms);
+// Source of the kernel specialised to the plan of these terms, storing its
+// outputs at their places after the permutation gate `perm` when it is not
+// NULL (host only; empty when the channel does not suit the tiled kernel).
+std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms,
+                                 const OutPerm *perm = nullptr);
+// The channel followed by conjugation with a permutation gate, in one pass:
+// the compiled kernel stores output (n, m) at (pi(n), pi(m)).  The kernel for
+// each gate is compiled on first use.  QCW_EAGAIN when no compiled kernel is
+// available (the caller then applies the channel and the gate separately).
+int tiled_channel_apply_perm(const TiledChannel *t, const OutPerm &perm, const double2 *in,
+                             double2 *out, hipStream_t s);
+// Whether tiled_channel_apply_perm would run (compiling the kernel if needed).
+bool tiled_channel_perm_ready(const TiledChannel *t, const OutPerm &perm);
 // Compiles such a source for gfx950 without loading it (no device needed);
 // sets the code object's size.
 int tiled_channel_compile_check(const std::string &src, size_t *code_bytes);

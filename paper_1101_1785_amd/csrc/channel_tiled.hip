@@ -386,6 +386,17 @@ __global__ __launch_bounds__(kTileThreads) void channel_tiled_kernel(const doubl
   }
 }
 
+// Inputs of the source generator (tiled_source, below).
+struct GenPlan {
+  int nq, e0, e1, mb_bits;
+  uint32_t xcd_tiles;
+  bool real, own_staged, any_staged;
+  size_t tab_entries;
+  const std::vector<TPartner> *partners;
+  const std::vector<TRead> *reads;
+  const std::vector<TRec> *recs;  // entry_b still the table entry index
+};
+
 const void *tiled_fn(bool real) {
   return real ? reinterpret_cast<const void *>(&channel_tiled_kernel<true>)
               : reinterpret_cast<const void *>(&channel_tiled_kernel<false>);
@@ -404,6 +415,19 @@ struct TiledChannel {
   const RtcKernel *spec = nullptr;  // the kernel compiled for this plan
   unsigned spec_grid = 0;
   uint32_t spec_xcd_blocks = 0, spec_nsub = 0;
+  // generator inputs, for the kernels with permuted stores
+  GenPlan gen{};
+  std::vector<TPartner> g_partners;
+  std::vector<TRead> g_reads;
+  std::vector<TRec> g_recs;
+  int ncu = 0;
+  struct Launch {
+    const RtcKernel *k = nullptr;
+    unsigned grid = 0;
+    uint32_t xcd_blocks = 0, nsub = 0;
+  };
+  mutable std::mutex perm_mu;
+  mutable std::map<std::vector<int>, Launch> perm_kernels;  // by gate (k, bits, table)
 };
 
 namespace {
@@ -489,15 +513,6 @@ uint32_t ticket_subs(uint32_t xcd_blocks) {
 // so the two parts add.  Groups, segments and products run in the generic
 // kernel's order with its operations, so the two kernels agree bit for bit.
 
-struct GenPlan {
-  int nq, e0, e1, mb_bits;
-  uint32_t xcd_tiles;
-  bool real, own_staged, any_staged;
-  size_t tab_entries;
-  const std::vector<TPartner> *partners;
-  const std::vector<TRead> *reads;
-  const std::vector<TRec> *recs;  // entry_b still the table entry index
-};
 
 void add(std::string &s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void add(std::string &s, const char *fmt, ...) {
@@ -518,7 +533,7 @@ constexpr const char *kSpecName = "qcw_channel_tiled_spec";
 // three 0.132, four 0.166); at nq = 14 two and three tie.
 int spec_blocks_per_cu(int nq) { return nq <= 12 ? 2 : 3; }
 
-std::string tiled_source(const GenPlan &G) {
+std::string tiled_source(const GenPlan &G, const OutPerm *perm) {
   const int nq = G.nq, e0 = G.e0, e1 = G.e1;
   const std::vector<TPartner> &P = *G.partners;
   const std::vector<TRead> &R = *G.reads;
@@ -555,6 +570,17 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return a;
 }
 )";
+  if (perm) {
+    // pi on a row or column index: the gate's local index l from its bits,
+    // pi(l) from a packed table of 3-bit entries, the changed bits flipped.
+    uint32_t pack = 0;
+    for (int l = 0; l < (1 << perm->k); ++l) pack |= (uint32_t)perm->table[l] << (3 * l);
+    add(s, "__device__ __forceinline__ u32 gate_perm(u32 n) {\n  const u32 l = 0u");
+    for (int j = 0; j < perm->k; ++j) add(s, " | (((n >> %d) & 1u) << %d)", perm->bits[j], perm->k - 1 - j);
+    add(s, ";\n  const u32 d = l ^ ((%uu >> (3u * l)) & 7u);\n  return n", pack);
+    for (int j = 0; j < perm->k; ++j) add(s, " ^ (((d >> %d) & 1u) << %d)", perm->k - 1 - j, perm->bits[j]);
+    add(s, ";\n}\n");
+  }
   add(s, "extern \"C\" __global__ __launch_bounds__(%d) void %s(const double2 *__restrict__ rho, "
          "double2 *__restrict__ out, const CT *__restrict__ tables, u32 *tickets, double p_keep, "
          "u32 xcd_blocks, u32 nsub) {\n", kTileThreads, kSpecName);
@@ -701,8 +727,16 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   }
   for (int a = 0; a < 4; ++a) {
     add(s, "    { const dbl2v w = {acc%d.x, acc%d.y};\n", a, a);
-    add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (u0 ^ %lluull) + tv)); }\n",
-        (unsigned long long)db[a]);
+    if (perm) {
+      // output (n, m) of this thread goes to (pi(n), pi(m))
+      const uint32_t d = ((a & 1) ? 1u << e0 : 0u) | ((a & 2) ? 1u << e1 : 0u);
+      add(s, "      const u32 n2 = gate_perm(nb | %uu | r), m2 = gate_perm((mb ^ %uu) | c);\n", d, d);
+      add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + ((((u64)n2 << %d) | m2) << 4))); }\n",
+          nq);
+    } else {
+      add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (u0 ^ %lluull) + tv)); }\n",
+          (unsigned long long)db[a]);
+    }
   }
   add(s, "  }\n");
   add(s, "  u32 *done = tickets + (%uu + x) * %uu;\n", 8 * kTicketSubs, kTicketStride);
@@ -729,6 +763,11 @@ struct HostPlan {
   std::vector<unsigned char> bytes;  // descriptors, tables, zeroed ticket counters
   int64_t flops = 0;
   std::string src;
+  // generator inputs (gen's vector pointers are set by whoever keeps them)
+  GenPlan gen{};
+  std::vector<TPartner> partners;
+  std::vector<TRead> reads;
+  std::vector<TRec> recs;  // entry_b: table entry index
 };
 
 // False when the channel does not suit the tiled kernel.
@@ -859,7 +898,11 @@ bool plan_host(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms, 
   gp.partners = &partners;
   gp.reads = &reads;
   gp.recs = &recs;
-  const std::string spec_src = tiled_source(gp);
+  const std::string spec_src = tiled_source(gp, nullptr);
+  H.gen = gp;
+  H.partners = partners;
+  H.reads = reads;
+  H.recs = recs;
   // LDS: the own tile (when staged), the staged partner, then the tables.
   const size_t tab_lds0 = (sm.own_staged ? kTileElems * sizeof(double2) : 0) +
                           (sm.staged ? kTileElems * sizeof(double2) : 0);
@@ -902,9 +945,15 @@ bool plan_host(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms, 
 
 }  // namespace
 
-std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms) {
+std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms,
+                                 const OutPerm *perm) {
   HostPlan H;
-  return plan_host(nq, terms, H) ? H.src : std::string();
+  if (!plan_host(nq, terms, H)) return std::string();
+  if (!perm) return H.src;
+  H.gen.partners = &H.partners;
+  H.gen.reads = &H.reads;
+  H.gen.recs = &H.recs;
+  return tiled_source(H.gen, perm);
 }
 
 int tiled_channel_compile_check(const std::string &src, size_t *code_bytes) {
@@ -912,6 +961,74 @@ int tiled_channel_compile_check(const std::string &src, size_t *code_bytes) {
 }
 
 int tiled_channel_compiler_version() { return rtc_compiler_version(); }
+
+namespace {
+
+// Persistent grid of a compiled kernel: resident blocks (capped per CU, see
+// spec_blocks_per_cu) over the device, a multiple of the 8 XCDs.
+bool spec_launch(const TiledChannel *t, const RtcKernel *k, TiledChannel::Launch *ls) {
+  int bpc = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k->fn, kTileThreads, 0) != hipSuccess ||
+      k->num_regs <= 0) {
+    (void)hipGetLastError();
+    return false;
+  }
+  bpc = std::min(bpc, std::min(spec_blocks_per_cu(t->args.nq), 512 / ((k->num_regs + 7) / 8 * 8)));
+  if (bpc < 1) return false;
+  const uint64_t want = std::min<uint64_t>((uint64_t)bpc * t->ncu, (uint64_t)t->args.xcd_tiles * 8);
+  ls->k = k;
+  ls->grid = (unsigned)std::max<uint64_t>(8, want & ~(uint64_t)7);
+  ls->xcd_blocks = ls->grid / 8;
+  ls->nsub = ticket_subs(ls->xcd_blocks);
+  return true;
+}
+
+int launch_spec(const TiledChannel *t, const TiledChannel::Launch &ls, const double2 *in, double2 *out,
+                hipStream_t s) {
+  const double2 *a_in = in;
+  double2 *a_out = out;
+  const void *a_tab = t->args.tables;
+  uint32_t *a_tk = t->args.tickets;
+  double a_p = t->args.p_keep;
+  uint32_t a_xb = ls.xcd_blocks, a_ns = ls.nsub;
+  void *args[] = {&a_in, &a_out, &a_tab, &a_tk, &a_p, &a_xb, &a_ns};
+  if (hipModuleLaunchKernel(ls.k->fn, ls.grid, 1, 1, kTileThreads, 1, 1, 0, s, args, nullptr) !=
+      hipSuccess)
+    return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(hipGetLastError()));
+  return QCW_OK;
+}
+
+// The compiled kernel with permuted stores for this gate (compiled on first
+// use), or nullptr.
+const TiledChannel::Launch *perm_launch(const TiledChannel *t, const OutPerm &p) {
+  if (!t->spec) return nullptr;
+  std::vector<int> key = {p.k};
+  for (int j = 0; j < p.k; ++j) key.push_back(p.bits[j]);
+  for (int l = 0; l < (1 << p.k); ++l) key.push_back(p.table[l]);
+  std::lock_guard<std::mutex> lk(t->perm_mu);
+  auto it = t->perm_kernels.find(key);
+  if (it != t->perm_kernels.end()) return it->second.k ? &it->second : nullptr;
+  TiledChannel::Launch ls;
+  const RtcKernel *k = nullptr;
+  if (rtc_get(tiled_source(t->gen, &p), kSpecName, &k) != QCW_OK || !spec_launch(t, k, &ls)) ls = {};
+  clear_error();
+  auto &e = t->perm_kernels[key];
+  e = ls;
+  return e.k ? &e : nullptr;
+}
+
+}  // namespace
+
+bool tiled_channel_perm_ready(const TiledChannel *t, const OutPerm &perm) {
+  return t && perm_launch(t, perm) != nullptr;
+}
+
+int tiled_channel_apply_perm(const TiledChannel *t, const OutPerm &perm, const double2 *in,
+                             double2 *out, hipStream_t s) {
+  const TiledChannel::Launch *ls = t ? perm_launch(t, perm) : nullptr;
+  if (!ls) return QCW_EAGAIN;
+  return launch_spec(t, *ls, in, out, s);
+}
 
 int tiled_channel_create(int nq, double p_keep,
                          const std::vector<std::pair<uint64_t, PermTerm>> &terms,
@@ -981,20 +1098,21 @@ int tiled_channel_create(int nq, double p_keep,
   A.nsub = ticket_subs(A.xcd_blocks);
 
   // The kernel compiled for this plan; without it the generic kernel runs.
+  t->g_partners = std::move(H.partners);
+  t->g_reads = std::move(H.reads);
+  t->g_recs = std::move(H.recs);
+  t->gen = H.gen;
+  t->gen.partners = &t->g_partners;
+  t->gen.reads = &t->g_reads;
+  t->gen.recs = &t->g_recs;
+  t->ncu = ncu;
   const RtcKernel *k = nullptr;
-  if (rtc_get(H.src, kSpecName, &k) == QCW_OK) {
-    int sbpc = 0;
-    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&sbpc, k->fn, kTileThreads, 0) == hipSuccess &&
-        k->num_regs > 0)
-      sbpc = std::min(sbpc, std::min(spec_blocks_per_cu(nq), 512 / ((k->num_regs + 7) / 8 * 8)));
-    (void)hipGetLastError();
-    if (sbpc >= 1) {
-      const uint64_t sw = std::min<uint64_t>((uint64_t)sbpc * ncu, (uint64_t)A.xcd_tiles * 8);
-      t->spec = k;
-      t->spec_grid = (unsigned)std::max<uint64_t>(8, sw & ~(uint64_t)7);
-      t->spec_xcd_blocks = t->spec_grid / 8;
-      t->spec_nsub = ticket_subs(t->spec_xcd_blocks);
-    }
+  TiledChannel::Launch ls;
+  if (rtc_get(H.src, kSpecName, &k) == QCW_OK && spec_launch(t, k, &ls)) {
+    t->spec = k;
+    t->spec_grid = ls.grid;
+    t->spec_xcd_blocks = ls.xcd_blocks;
+    t->spec_nsub = ls.nsub;
   }
   t->sum.specialized = t->spec ? 1 : 0;
   t->sum.grid = (int)t->grid;
@@ -1008,17 +1126,12 @@ int tiled_channel_create(int nq, double p_keep,
 int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, hipStream_t s,
                         bool generic) {
   if (t->spec && !generic) {
-    const double2 *a_in = in;
-    double2 *a_out = out;
-    const void *a_tab = t->args.tables;
-    uint32_t *a_tk = t->args.tickets;
-    double a_p = t->args.p_keep;
-    uint32_t a_xb = t->spec_xcd_blocks, a_ns = t->spec_nsub;
-    void *args[] = {&a_in, &a_out, &a_tab, &a_tk, &a_p, &a_xb, &a_ns};
-    if (hipModuleLaunchKernel(t->spec->fn, t->spec_grid, 1, 1, kTileThreads, 1, 1, 0, s, args, nullptr) !=
-        hipSuccess)
-      return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(hipGetLastError()));
-    return QCW_OK;
+    TiledChannel::Launch ls;
+    ls.k = t->spec;
+    ls.grid = t->spec_grid;
+    ls.xcd_blocks = t->spec_xcd_blocks;
+    ls.nsub = t->spec_nsub;
+    return launch_spec(t, ls, in, out, s);
   }
   if (t->real)
     hipLaunchKernelGGL(channel_tiled_kernel<true>, dim3(t->grid), dim3(kTileThreads), t->lds, s, in,

@@ -132,6 +132,7 @@ int launch_k(int nq, const int *targets, const qcw_c64 *U, qcw_c64 *rho, hipStre
   }
   const uint64_t blocks = 1ull << (nb - kConjTileBits);
   if (blocks > 0x7fffffffull) return fail(QCW_EINVAL, "rho too large for one launch");
+  TimedLaunch t(QCW_KERNEL_CONJ, s);
   hipLaunchKernelGGL(conj_tile_kernel<K>, dim3((unsigned)blocks), dim3(kConjThreads), 0, s,
                      reinterpret_cast<double2 *>(rho), a);
   const hipError_t e = hipGetLastError();

@@ -531,6 +531,32 @@ int parse_terms(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *
   return QCW_OK;
 }
 
+// U as a permutation of the gate's local basis (entries exactly 1 and 0):
+// U |l> = |table[l]>.
+bool gate_permutation(int k, const Geom &g, const qcw_c64 *U, OutPerm *p) {
+  const int m = 1 << k;
+  p->k = k;
+  for (int j = 0; j < 3; ++j) p->bits[j] = j < k ? g.bit[j] : 0;
+  bool used[8] = {};
+  for (int col = 0; col < m; ++col) {
+    int row = -1;
+    for (int r = 0; r < m; ++r) {
+      const qcw_c64 v = U[r * m + col];
+      if (v.re == 1.0 && v.im == 0.0) {
+        if (row >= 0) return false;
+        row = r;
+      } else if (v.re != 0.0 || v.im != 0.0) {
+        return false;
+      }
+    }
+    if (row < 0 || used[row]) return false;
+    used[row] = true;
+    p->table[col] = (uint8_t)row;
+  }
+  for (int l = m; l < 8; ++l) p->table[l] = 0;
+  return true;
+}
+
 }  // namespace
 
 int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus_term *terms,
@@ -639,6 +665,30 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
   return QCW_OK;
 }
 
+int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out, int k,
+                           const int *targets, const qcw_c64 *U, void *stream) {
+  clear_error();
+  if (!c) return fail(QCW_EINVAL, "channel is NULL");
+  if (!U) return fail(QCW_EINVAL, "U is NULL");
+  Geom g;
+  int rc = make_geom(c->nq, k, targets, &g);
+  if (rc) return rc;
+  OutPerm p;
+  if (c->tiled && !c->force_gather && !c->tiled_generic && gate_permutation(k, g, U, &p) &&
+      tiled_channel_perm_ready(c->tiled, p)) {
+    const uint64_t bytes = (1ull << (2 * c->nq)) * sizeof(qcw_c64);
+    const uint64_t a = (uint64_t)(uintptr_t)rho_in, b = (uint64_t)(uintptr_t)rho_out;
+    if (a < b + bytes && b < a + bytes) return fail(QCW_EINVAL, "rho_in and rho_out overlap");
+    if ((rc = check_device_range(rho_in, bytes, "rho_in")) || (rc = check_device_range(rho_out, bytes, "rho_out")))
+      return rc;
+    TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
+    return tiled_channel_apply_perm(c->tiled, p, reinterpret_cast<const double2 *>(rho_in),
+                                    reinterpret_cast<double2 *>(rho_out), (hipStream_t)stream);
+  }
+  if ((rc = qcw_channel_apply(c, rho_in, rho_out, stream))) return rc;
+  return qcw_rho_conjugate(k, targets, U, rho_out, c->nq, stream);
+}
+
 int qcw_channel_destroy(qcw_channel *c) {
   clear_error();
   if (c) channel_free(c);
@@ -673,7 +723,8 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info) {
 }
 
 int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *mats,
-                             int64_t nmats, int compile, char *buf, size_t cap, size_t *len,
+                             int64_t nmats, int gate_k, const int *gate_targets,
+                             const qcw_c64 *gate_U, int compile, char *buf, size_t cap, size_t *len,
                              size_t *code_bytes, int32_t *compiler_version) {
   clear_error();
   if (compiler_version) *compiler_version = tiled_channel_compiler_version();
@@ -683,7 +734,22 @@ int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, co
   std::vector<std::pair<uint64_t, PermTerm>> pt;
   int rc = parse_terms(nq, terms, nterms, mats, nmats, dt, pt);
   if (rc) return rc;
-  const std::string src = dt.empty() ? tiled_channel_source(nq, pt) : std::string();
+  OutPerm perm;
+  bool with_gate = false;
+  if (gate_k != 0) {
+    Geom g;
+    if ((rc = make_geom(nq, gate_k, gate_targets, &g))) return rc;
+    if (!gate_U) return fail(QCW_EINVAL, "gate_U is NULL");
+    with_gate = gate_permutation(gate_k, g, gate_U, &perm);
+  }
+  *len = 0;
+  if (gate_k != 0 && !with_gate) {  // not a permutation gate: no kernel of its own
+    if (buf && cap > 0) buf[0] = 0;
+    if (compile) *code_bytes = 0;
+    return QCW_OK;
+  }
+  const std::string src =
+      dt.empty() ? tiled_channel_source(nq, pt, with_gate ? &perm : nullptr) : std::string();
   *len = src.size();
   if (buf && cap > 0) {
     const size_t n = std::min(cap - 1, src.size());

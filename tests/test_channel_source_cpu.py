@@ -81,3 +81,21 @@ def test_bad_terms_rejected(L):
         L.channel_kernel_source(0, [])
     with pytest.raises(RuntimeError):
         L.channel_kernel_source(9, [(0.1, {10: qi.X})])
+
+
+def test_permutation_gate_gets_a_kernel_of_its_own(L):
+    """qcw_channel_apply_gate folds a permutation gate into the compiled
+    kernel's stores: its source differs from the plain one only there, names
+    the gate's bits, and compiles; a gate that is not a permutation matrix
+    (H) has no kernel of its own."""
+    nq = 10
+    terms = _pauli(np.random.default_rng(9), nq)
+    plain = L.channel_kernel_source(nq, terms)[0]
+    src, code, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(qi.CNOT, (1, nq)))
+    assert "gate_perm" in src and "gate_perm" not in plain and code > 1000
+    # CNOT(1, nq): local index 2 q1 + q_nq on bits nq - 1 and 0; pi = (0, 1, 3, 2)
+    assert "(((n >> 9) & 1u) << 1) | (((n >> 0) & 1u) << 0)" in src
+    assert f"{0 | 1 << 3 | 3 << 6 | 2 << 9}u" in src
+    assert L.channel_kernel_source(nq, terms, gate=(qi.H, (1,)))[0] == ""
+    toff, code3, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(qi.TOFFOLI, (1, 2, 3)))
+    assert "gate_perm" in toff and code3 > 1000

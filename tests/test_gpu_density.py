@@ -195,6 +195,89 @@ def test_compiled_tiled_kernel_equals_generic(L, kind, nq, seed):
     assert torch.equal(torch.view_as_real(b1), torch.view_as_real(b2))
 
 
+def _step_gates(nq):
+    """Algorithm gates for the one-call step: permutation matrices with
+    targets among the tile's thread bits (the last qubits), its E bits or
+    the rest, and two that are not permutations (the two-kernel path)."""
+    S = np.diag([1.0, 1j])
+    return [(qi.CNOT, (1, 2)), (qi.CNOT, (nq, 1)), (qi.CNOT, (nq - 1, nq)), (qi.CNOT, (3, nq - 2)),
+            (qi.X, (nq // 2,)), (qi.SWAP, (2, nq)), (qi.TOFFOLI, (nq, 1, nq - 3)),
+            (qi.H, (1,)), (S, (nq - 1,))]
+
+
+@pytest.mark.parametrize("kind,nq,seed", [("pauli", 9, 1), ("phase", 8, 3), ("zheavy", 8, 5),
+                                          ("pairs", 9, 6), ("pauli", 12, 8)])
+def test_channel_apply_gate_equals_channel_then_conjugation(L, kind, nq, seed):
+    """One multiverse step in one call (qcw_channel_apply_gate): for a
+    permutation gate the compiled kernel stores output (n, m) at
+    (pi(n), pi(m)), so the step is one pass; it must equal the channel
+    followed by qcw_rho_conjugate exactly (values equal; only zeros may
+    differ in sign).  The timing counters show which path ran."""
+    print(f"[gpu] channel + gate in one call {kind} nq={nq}", flush=True)
+    rng = np.random.default_rng(3000 + seed)
+    terms = _pauli_terms(rng, nq) if kind == "pauli" else _tiled_case(kind, nq, seed)
+    ch = L.Channel(nq, 0.8, terms)
+    assert ch.plan()["compiled_kernel"] == 1
+    NN = 1 << (2 * nq)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    a = torch.complex(torch.randn(NN, dtype=torch.float64, device="cuda", generator=g),
+                      torch.randn(NN, dtype=torch.float64, device="cuda", generator=g))
+    for U, t in _step_gates(nq):
+        perm = bool(np.all((U == 0) | (U == 1)))
+        b1 = torch.full_like(a, float("nan"))
+        b2 = torch.full_like(a, float("nan"))
+        torch.cuda.synchronize()
+        L.qcw_timing_reset()
+        L.qcw_timing_enable(True)
+        ch.apply_gate(a, b1, U, t)
+        n_ch, _ = L.qcw_timing_read(L.QCW_KERNEL_CHANNEL)
+        n_cj, _ = L.qcw_timing_read(L.QCW_KERNEL_CONJ)
+        L.qcw_timing_enable(False)
+        assert (n_ch, n_cj) == ((1, 0) if perm else (1, 1)), (t, n_ch, n_cj)
+        ch.apply(a, b2)
+        L.qcw_rho_conjugate(len(t), t, U, b2)
+        torch.cuda.synchronize()
+        assert not bool(torch.isnan(b1).any()), t
+        assert torch.equal(b1, b2), t
+    ch.close()
+
+
+def test_channel_apply_gate_other_kernels(L):
+    """Without the compiled tiled kernel (the gather kernel, the generic
+    tiled kernel, or nq below the tiled range) the call is the channel then
+    the conjugation, with the same result."""
+    for nq, choice in ((6, -1), (8, 1), (8, 2)):
+        rng = np.random.default_rng(40 + nq + choice)
+        terms = _pauli_terms(rng, nq)
+        ch = L.Channel(nq, 0.8, terms)
+        ch.plan(choice)
+        rho0 = _rand_rho(rng, nq)
+        for U, t in ((qi.CNOT, (1, nq)), (qi.H, (2,))):
+            a = dev(rho0)
+            b1 = torch.empty_like(a)
+            b2 = torch.empty_like(a)
+            ch.apply_gate(a, b1, U, t)
+            ch.apply(a, b2)
+            L.qcw_rho_conjugate(len(t), t, U, b2)
+            assert torch.equal(b1, b2)
+            want = D.conjugate(D.channel(rho0, 0.8, terms), U, t)
+            assert np.max(np.abs(host(b1, nq) - want)) <= TOL
+        ch.close()
+
+
+def test_channel_apply_gate_rejects_bad_input(L):
+    ch = L.Channel(8, 0.8, _pauli_terms(np.random.default_rng(1), 8))
+    a = torch.zeros(1 << 16, dtype=torch.complex128, device="cuda")
+    b = torch.zeros_like(a)
+    with pytest.raises(RuntimeError):
+        ch.apply_gate(a, b, qi.CNOT, (1, 1))       # repeated target
+    with pytest.raises(RuntimeError):
+        ch.apply_gate(a, b, qi.CNOT, (1, 9))       # target outside [1, nq]
+    with pytest.raises(RuntimeError):
+        ch.apply_gate(a, a, qi.CNOT, (1, 2))       # rho_in == rho_out
+    ch.close()
+
+
 def test_tiled_channel_plan_coverage(L):
     """The cases above reach every part of the tiled kernel: partners staged
     in LDS and read directly, the tile itself staged, segments on the tile
