@@ -731,8 +731,11 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
       // output (n, m) of this thread goes to (pi(n), pi(m))
       const uint32_t d = ((a & 1) ? 1u << e0 : 0u) | ((a & 2) ? 1u << e1 : 0u);
       add(s, "      const u32 n2 = gate_perm(nb | %uu | r), m2 = gate_perm((mb ^ %uu) | c);\n", d, d);
-      add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + ((((u64)n2 << %d) | m2) << 4))); }\n",
-          nq);
+      if (2 * nq + 4 <= 32)  // the byte offset fits 32 bits: scalar base plus a 32-bit offset
+        add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (((n2 << %d) | m2) << 4))); }\n", nq);
+      else
+        add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + ((((u64)n2 << %d) | m2) << 4))); }\n",
+            nq);
     } else {
       add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (u0 ^ %lluull) + tv)); }\n",
           (unsigned long long)db[a]);
