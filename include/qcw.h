@@ -424,9 +424,10 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
  * One multiverse step of Eq. rhoE4 in one call:
  *     rho_out = U [channel(rho_in)] U^dagger
  * for a k-qubit algorithm gate U on the targets (conventions of qcw_opk).
- * When U is a permutation matrix (entries exactly 0 and 1: X, CNOT, SWAP,
- * Toffoli, ...) and the channel runs its compiled tiled kernel, the
- * conjugation is folded into that kernel: output (n, m) is stored at
+ * When U is monomial, U |l> = u_l |pi(l)> (one nonzero entry in each row
+ * and column: X, CNOT, SWAP, Toffoli, Z, S, T, Y, CZ, ...), and the channel
+ * runs its compiled tiled kernel, the conjugation is folded into that
+ * kernel: output (n, m), times u_l(n) conj(u_l(m)), is stored at
  * (pi(n), pi(m)), one pass over rho instead of two.  The kernel for each such
  * gate is compiled on its first use (about a second, synchronous).
  * Otherwise it is qcw_channel_apply followed by qcw_rho_conjugate on rho_out.
@@ -479,7 +480,7 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info);
  * these terms (host call, no device needed; for tests).  Arguments as for
  * qcw_channel_create; gate_k != 0 asks instead for the kernel that
  * qcw_channel_apply_gate compiles for the gate (gate_k, gate_targets, gate_U),
- * which has none (length 0) unless the gate is a permutation matrix.  *len:
+ * which has none (length 0) unless the gate is monomial.  *len:
  * the source's length (0 when the channel has no tiled plan); when buf is
  * not NULL, up to cap - 1 bytes of it and a NUL are written there.  compile != 0: the source is also compiled for gfx950 with
  * the run-time compiler and *code_bytes set to the code object's size; a

@@ -39,14 +39,18 @@ constexpr int kTiledMaxQubits = 15;  // row and column bits interleave into bits
 
 struct TiledChannel;
 
-// A permutation gate (a k-qubit unitary that is a permutation matrix) on the
+// A monomial gate (one nonzero entry in each row and column: permutations
+// such as X, CNOT, SWAP, Toffoli, times phases, such as Z, S, T, Y, CZ) on the
 // state bits bits[0..k-1] (argument order: bits[0] is the most significant
-// bit of the local index l).  table[l] = pi(l): U |l> = |pi(l)>.  The
-// conjugation rho -> U rho U^dagger moves element (n, m) to (pi(n), pi(m)).
+// bit of the local index l): U |l> = u_l |pi(l)>, table[l] = pi(l).  The
+// conjugation rho -> U rho U^dagger moves element (n, m) to (pi(n), pi(m))
+// and multiplies it by u_l(n) conj(u_l(m)).
 struct OutPerm {
   int k;
   int bits[3];
   uint8_t table[8];
+  double ur[8], ui[8];  // u_l
+  int unit;             // every u_l is exactly 1: a plain permutation
 };
 
 // Shape of a tiled plan (for tests and reports).
@@ -81,8 +85,9 @@ void tiled_channel_free(TiledChannel *t);
 // NULL (host only; empty when the channel does not suit the tiled kernel).
 std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms,
                                  const OutPerm *perm = nullptr);
-// The channel followed by conjugation with a permutation gate, in one pass:
-// the compiled kernel stores output (n, m) at (pi(n), pi(m)).  The kernel for
+// The channel followed by conjugation with a monomial gate, in one pass:
+// the compiled kernel stores output (n, m), times u_l(n) conj(u_l(m)), at
+// (pi(n), pi(m)).  The kernel for
 // each gate is compiled on first use.  QCW_EAGAIN when no compiled kernel is
 // available (the caller then applies the channel and the gate separately).
 int tiled_channel_apply_perm(const TiledChannel *t, const OutPerm &perm, const double2 *in,

@@ -575,11 +575,33 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
     // pi(l) from a packed table of 3-bit entries, the changed bits flipped.
     uint32_t pack = 0;
     for (int l = 0; l < (1 << perm->k); ++l) pack |= (uint32_t)perm->table[l] << (3 * l);
-    add(s, "__device__ __forceinline__ u32 gate_perm(u32 n) {\n  const u32 l = 0u");
+    add(s, "__device__ __forceinline__ u32 gate_l(u32 n) {\n  return 0u");
     for (int j = 0; j < perm->k; ++j) add(s, " | (((n >> %d) & 1u) << %d)", perm->bits[j], perm->k - 1 - j);
-    add(s, ";\n  const u32 d = l ^ ((%uu >> (3u * l)) & 7u);\n  return n", pack);
+    add(s, ";\n}\n");
+    add(s, "__device__ __forceinline__ u32 gate_perm(u32 n) {\n");
+    add(s, "  const u32 l = gate_l(n), d = l ^ ((%uu >> (3u * l)) & 7u);\n  return n", pack);
     for (int j = 0; j < perm->k; ++j) add(s, " ^ (((d >> %d) & 1u) << %d)", perm->k - 1 - j, perm->bits[j]);
     add(s, ";\n}\n");
+    if (!perm->unit) {
+      // The phases u_l, exact (hexadecimal literals).  The conjugation's row
+      // pass gives u x as one complex multiply-add from +0 (its other terms
+      // are products with exact zeros), the column pass conj(u') times that:
+      // the same operations here.
+      add(s, "__device__ const double gate_ur[8] = {");
+      for (int l = 0; l < 8; ++l) add(s, "%s%a", l ? ", " : "", perm->ur[l]);
+      add(s, "};\n__device__ const double gate_ui[8] = {");
+      for (int l = 0; l < 8; ++l) add(s, "%s%a", l ? ", " : "", perm->ui[l]);
+      add(s, "};\n");
+      s += R"(__device__ __forceinline__ double2 cmad0(double ux, double uy, double2 x) {
+  double2 a = make_double2(0.0, 0.0);
+  a.x = __fma_rn(ux, x.x, a.x);
+  a.x = __fma_rn(-uy, x.y, a.x);
+  a.y = __fma_rn(ux, x.y, a.y);
+  a.y = __fma_rn(uy, x.x, a.y);
+  return a;
+}
+)";
+    }
   }
   add(s, "extern \"C\" __global__ __launch_bounds__(%d) void %s(const double2 *__restrict__ rho, "
          "double2 *__restrict__ out, const CT *__restrict__ tables, u32 *tickets, double p_keep, "
@@ -726,17 +748,25 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
     add(s, "    acc%d.y = __fma_rn(p_keep, own%d.y, acc%d.y);\n", a, a, a);
   }
   for (int a = 0; a < 4; ++a) {
-    add(s, "    { const dbl2v w = {acc%d.x, acc%d.y};\n", a, a);
     if (perm) {
       // output (n, m) of this thread goes to (pi(n), pi(m))
       const uint32_t d = ((a & 1) ? 1u << e0 : 0u) | ((a & 2) ? 1u << e1 : 0u);
-      add(s, "      const u32 n2 = gate_perm(nb | %uu | r), m2 = gate_perm((mb ^ %uu) | c);\n", d, d);
+      add(s, "    { const u32 n1 = nb | %uu | r, m1 = (mb ^ %uu) | c;\n", d, d);
+      if (perm->unit) {
+        add(s, "      const dbl2v w = {acc%d.x, acc%d.y};\n", a, a);
+      } else {
+        add(s, "      const u32 ln = gate_l(n1), lm = gate_l(m1);\n");
+        add(s, "      const double2 t = cmad0(gate_ur[lm], -gate_ui[lm], cmad0(gate_ur[ln], gate_ui[ln], acc%d));\n", a);
+        add(s, "      const dbl2v w = {t.x, t.y};\n");
+      }
+      add(s, "      const u32 n2 = gate_perm(n1), m2 = gate_perm(m1);\n");
       if (2 * nq + 4 <= 32)  // the byte offset fits 32 bits: scalar base plus a 32-bit offset
         add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (((n2 << %d) | m2) << 4))); }\n", nq);
       else
         add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + ((((u64)n2 << %d) | m2) << 4))); }\n",
             nq);
     } else {
+      add(s, "    { const dbl2v w = {acc%d.x, acc%d.y};\n", a, a);
       add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (u0 ^ %lluull) + tv)); }\n",
           (unsigned long long)db[a]);
     }
@@ -1007,7 +1037,15 @@ const TiledChannel::Launch *perm_launch(const TiledChannel *t, const OutPerm &p)
   if (!t->spec) return nullptr;
   std::vector<int> key = {p.k};
   for (int j = 0; j < p.k; ++j) key.push_back(p.bits[j]);
-  for (int l = 0; l < (1 << p.k); ++l) key.push_back(p.table[l]);
+  for (int l = 0; l < (1 << p.k); ++l) {
+    key.push_back(p.table[l]);
+    for (const double v : {p.ur[l], p.ui[l]}) {
+      int32_t w[2];
+      memcpy(w, &v, sizeof(v));
+      key.push_back(w[0]);
+      key.push_back(w[1]);
+    }
+  }
   std::lock_guard<std::mutex> lk(t->perm_mu);
   auto it = t->perm_kernels.find(key);
   if (it != t->perm_kernels.end()) return it->second.k ? &it->second : nullptr;

@@ -531,29 +531,31 @@ int parse_terms(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *
   return QCW_OK;
 }
 
-// U as a permutation of the gate's local basis (entries exactly 1 and 0):
-// U |l> = |table[l]>.
-bool gate_permutation(int k, const Geom &g, const qcw_c64 *U, OutPerm *p) {
+// U as a monomial matrix of the gate's local basis (one nonzero entry in
+// each column, in distinct rows): U |l> = u_l |table[l]>.
+bool gate_monomial(int k, const Geom &g, const qcw_c64 *U, OutPerm *p) {
   const int m = 1 << k;
+  memset(p, 0, sizeof(*p));
   p->k = k;
-  for (int j = 0; j < 3; ++j) p->bits[j] = j < k ? g.bit[j] : 0;
+  for (int j = 0; j < k; ++j) p->bits[j] = g.bit[j];
   bool used[8] = {};
+  p->unit = 1;
   for (int col = 0; col < m; ++col) {
     int row = -1;
     for (int r = 0; r < m; ++r) {
       const qcw_c64 v = U[r * m + col];
-      if (v.re == 1.0 && v.im == 0.0) {
+      if (v.re != 0.0 || v.im != 0.0) {
         if (row >= 0) return false;
         row = r;
-      } else if (v.re != 0.0 || v.im != 0.0) {
-        return false;
       }
     }
     if (row < 0 || used[row]) return false;
     used[row] = true;
     p->table[col] = (uint8_t)row;
+    p->ur[col] = U[row * m + col].re;
+    p->ui[col] = U[row * m + col].im;
+    if (p->ur[col] != 1.0 || p->ui[col] != 0.0) p->unit = 0;
   }
-  for (int l = m; l < 8; ++l) p->table[l] = 0;
   return true;
 }
 
@@ -674,7 +676,7 @@ int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 
   int rc = make_geom(c->nq, k, targets, &g);
   if (rc) return rc;
   OutPerm p;
-  if (c->tiled && !c->force_gather && !c->tiled_generic && gate_permutation(k, g, U, &p) &&
+  if (c->tiled && !c->force_gather && !c->tiled_generic && gate_monomial(k, g, U, &p) &&
       tiled_channel_perm_ready(c->tiled, p)) {
     const uint64_t bytes = (1ull << (2 * c->nq)) * sizeof(qcw_c64);
     const uint64_t a = (uint64_t)(uintptr_t)rho_in, b = (uint64_t)(uintptr_t)rho_out;
@@ -740,7 +742,7 @@ int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, co
     Geom g;
     if ((rc = make_geom(nq, gate_k, gate_targets, &g))) return rc;
     if (!gate_U) return fail(QCW_EINVAL, "gate_U is NULL");
-    with_gate = gate_permutation(gate_k, g, gate_U, &perm);
+    with_gate = gate_monomial(gate_k, g, gate_U, &perm);
   }
   *len = 0;
   if (gate_k != 0 && !with_gate) {  // not a permutation gate: no kernel of its own

@@ -84,10 +84,10 @@ def test_bad_terms_rejected(L):
 
 
 def test_permutation_gate_gets_a_kernel_of_its_own(L):
-    """qcw_channel_apply_gate folds a permutation gate into the compiled
-    kernel's stores: its source differs from the plain one only there, names
-    the gate's bits, and compiles; a gate that is not a permutation matrix
-    (H) has no kernel of its own."""
+    """qcw_channel_apply_gate folds a monomial gate (a permutation with
+    phases) into the compiled kernel's stores: its source differs from the
+    plain one only there, names the gate's bits, and compiles; a gate that
+    mixes basis states (H) has no kernel of its own."""
     nq = 10
     terms = _pauli(np.random.default_rng(9), nq)
     plain = L.channel_kernel_source(nq, terms)[0]
@@ -97,5 +97,9 @@ def test_permutation_gate_gets_a_kernel_of_its_own(L):
     assert "(((n >> 9) & 1u) << 1) | (((n >> 0) & 1u) << 0)" in src
     assert f"{0 | 1 << 3 | 3 << 6 | 2 << 9}u" in src
     assert L.channel_kernel_source(nq, terms, gate=(qi.H, (1,)))[0] == ""
+    assert "gate_ur" not in src  # a plain permutation multiplies nothing
+    # a monomial gate (phases) carries its phases, exactly
+    z, codez, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(np.diag([1.0, 1j]), (4,)))
+    assert "gate_ur" in z and "0x1p+0" in z and codez > 1000
     toff, code3, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(qi.TOFFOLI, (1, 2, 3)))
     assert "gate_perm" in toff and code3 > 1000

@@ -196,23 +196,35 @@ def test_compiled_tiled_kernel_equals_generic(L, kind, nq, seed):
 
 
 def _step_gates(nq):
-    """Algorithm gates for the one-call step: permutation matrices with
-    targets among the tile's thread bits (the last qubits), its E bits or
-    the rest, and two that are not permutations (the two-kernel path)."""
+    """Algorithm gates for the one-call step: permutation and monomial
+    matrices (phases, Y, CZ, a phased swap) with targets among the tile's
+    thread bits (the last qubits), its E bits or the rest, and two that mix
+    basis states (the two-kernel path)."""
     S = np.diag([1.0, 1j])
+    CZ = np.diag([1.0, 1.0, 1.0, -1.0]).astype(np.complex128)
+    phased_swap = np.array([[np.exp(0.3j), 0, 0, 0], [0, 0, -1j, 0], [0, np.exp(-1.1j), 0, 0],
+                            [0, 0, 0, 0.6 - 0.8j]])
+    rot = np.array([[np.cos(0.4), -np.sin(0.4)], [np.sin(0.4), np.cos(0.4)]], dtype=np.complex128)
     return [(qi.CNOT, (1, 2)), (qi.CNOT, (nq, 1)), (qi.CNOT, (nq - 1, nq)), (qi.CNOT, (3, nq - 2)),
             (qi.X, (nq // 2,)), (qi.SWAP, (2, nq)), (qi.TOFFOLI, (nq, 1, nq - 3)),
-            (qi.H, (1,)), (S, (nq - 1,))]
+            (S, (nq - 1,)), (qi.Z, (1,)), (qi.Y, (nq,)), (CZ, (nq - 2, 2)),
+            (phased_swap, (nq, nq // 2)), (qi.H, (1,)), (rot, (nq - 1,))]
+
+
+def _monomial(U):
+    nz = np.abs(U) != 0
+    return bool(np.all(nz.sum(0) == 1) and np.all(nz.sum(1) == 1))
 
 
 @pytest.mark.parametrize("kind,nq,seed", [("pauli", 9, 1), ("phase", 8, 3), ("zheavy", 8, 5),
                                           ("pairs", 9, 6), ("pauli", 12, 8)])
 def test_channel_apply_gate_equals_channel_then_conjugation(L, kind, nq, seed):
     """One multiverse step in one call (qcw_channel_apply_gate): for a
-    permutation gate the compiled kernel stores output (n, m) at
-    (pi(n), pi(m)), so the step is one pass; it must equal the channel
-    followed by qcw_rho_conjugate exactly (values equal; only zeros may
-    differ in sign).  The timing counters show which path ran."""
+    monomial gate (U|l> = u_l |pi(l)>) the compiled kernel stores output
+    (n, m), times u_l(n) conj(u_l(m)), at (pi(n), pi(m)), so the step is one
+    pass; it must equal the channel followed by qcw_rho_conjugate exactly
+    (values equal; only zeros may differ in sign).  The timing counters show
+    which path ran."""
     print(f"[gpu] channel + gate in one call {kind} nq={nq}", flush=True)
     rng = np.random.default_rng(3000 + seed)
     terms = _pauli_terms(rng, nq) if kind == "pauli" else _tiled_case(kind, nq, seed)
@@ -223,7 +235,7 @@ def test_channel_apply_gate_equals_channel_then_conjugation(L, kind, nq, seed):
     a = torch.complex(torch.randn(NN, dtype=torch.float64, device="cuda", generator=g),
                       torch.randn(NN, dtype=torch.float64, device="cuda", generator=g))
     for U, t in _step_gates(nq):
-        perm = bool(np.all((U == 0) | (U == 1)))
+        perm = _monomial(U)
         b1 = torch.full_like(a, float("nan"))
         b2 = torch.full_like(a, float("nan"))
         torch.cuda.synchronize()
