@@ -627,6 +627,69 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="p
             "fidelity_after": ob["fidelity"], **spectral}
 
 
+def bench_multiverse_obs(torch, L, qi, nq, seed, steps=10, n_p=16, eps=0.2):
+    """Multiverse steps with the observables of §5 (trace, purity, fidelity
+    against |0..0>) after every step.  qcw_channel_step_obs sums them in the
+    channel's own pass (asynchronously, into device memory), against the
+    step followed by qcw_rho_observables (a further pass over rho, and a
+    synchronisation) every step.  The same channel and GHZ-chain gates as
+    the multiverse sections."""
+    rng = np.random.default_rng([seed, 7])
+    P = [qi.X, qi.Y, qi.Z]
+    terms = []
+    for s_, ps in ((1, 0.95), (2, 0.05)):
+        for _ in range(n_p):
+            qs = [int(x) + 1 for x in rng.choice(nq, s_, replace=False)]
+            terms.append((eps * ps / n_p, {q: P[int(rng.integers(3))] for q in qs}))
+    ch = L.Channel(nq, 1 - eps, terms)
+    psi0 = qi.basis_state(nq, 0)
+    psi0_d = torch.from_numpy(psi0).to("cuda")
+    rho0 = torch.from_numpy(np.outer(psi0, psi0.conj()).reshape(-1)).to("cuda")
+    a, b = rho0.clone(), torch.empty_like(rho0)
+    obs = torch.empty(4, dtype=torch.float64, device="cuda")
+    gates = [(qi.H, (1,))] + [(qi.CNOT, (1, t)) for t in range(2, nq + 1)]
+    hist = np.empty((steps, 4))
+    for i in range(min(len(gates), steps)):  # compile both kernels of each gate before the timing
+        U, t = gates[i]
+        ch.step_obs(a, b, obs, U, t, psi0=psi0_d)
+        ch.apply_gate(a, b, U, t)
+    torch.cuda.synchronize()
+
+    def run(fused):
+        x, y = a, b
+        x.copy_(rho0)
+        torch.cuda.synchronize()
+        L.qcw_timing_reset()
+        L.qcw_timing_enable(True)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            U, t = gates[i % len(gates)]
+            if fused:
+                ch.step_obs(x, y, obs, U, t, psi0=psi0_d)
+                hist[i] = obs.cpu().numpy()  # read back each step, as a driver loop would
+            else:
+                ch.apply_gate(x, y, U, t)
+                o = L.qcw_rho_observables(y, psi0=psi0)
+                hist[i] = [o["trace"].real, o["trace"].imag, o["purity"], o["fidelity"]]
+            x, y = y, x
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps * 1e3
+        L.qcw_timing_enable(False)
+        n, cms = L.qcw_timing_read(L.QCW_KERNEL_CHANNEL)
+        return dt, hist.copy(), cms / max(n, 1)
+
+    ms_f, h_f, ch_f = run(True)
+    ms_s, h_s, ch_s = run(False)
+    ch.close()
+    return {"nq": nq, "steps": steps, "ms_per_step_observed_in_pass": ms_f,
+            "ms_per_step_with_observables_call": ms_s,
+            "channel_ms_observing": ch_f, "channel_ms_plain": ch_s,
+            "speedup": ms_s / ms_f,
+            "max_abs_diff_observables": float(np.max(np.abs(h_f - h_s))),
+            "fidelity_after": float(h_f[-1, 3]), "purity_after": float(h_f[-1, 2]),
+            "what": "host clock per step including reading the observables back every step"}
+
+
 def bench_config0(torch, L, qi, reps=10000):
     """Config 0: the paper's first worked-example size (nq = 3), one 12-gate
     random circuit (seed 0) on the plain path, one solve at a time: latency of
@@ -977,6 +1040,7 @@ def extra_sections(torch, L, qi, a):
         "multiverse_nq13": lambda: bench_multiverse(torch, L, qi, 13, 5, steps=10),
         "multiverse_nq13_generic": lambda: bench_multiverse(torch, L, qi, 13, 5, steps=10, kernel=2),
         "multiverse_nq14": lambda: bench_multiverse(torch, L, qi, 14, 5, steps=5),
+        "multiverse_nq13_observed": lambda: bench_multiverse_obs(torch, L, qi, 13, 5),
         "eigen_batch_nq5": lambda: bench_eigen(torch, L, 5),
         "eigen_batch_nq6": lambda: bench_eigen(torch, L, 6),
         "multiverse_nq5": lambda: bench_multiverse(torch, L, qi, 5, 5, steps=200),

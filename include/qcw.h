@@ -436,6 +436,23 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
  */
 int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out, int k,
                            const int *targets, const qcw_c64 *U, void *stream);
+/*
+ * The same step (k = 0: the channel alone), also reducing the new rho's
+ * observables of §5 into obs (DEVICE, 4 doubles, written asynchronously on
+ * stream): Tr rho (re, im), Tr rho^2 as sum |rho_nm|^2, and the root fidelity
+ * sqrt(<psi0|rho|psi0>) against psi0 (DEVICE, 2^nq amplitudes; NULL: NaN), the
+ * first four values of qcw_rho_observables.  When the step runs as the
+ * compiled kernel (a monomial gate or none), that kernel sums them as it
+ * stores rho, with no further pass over rho.  Otherwise the step is followed
+ * by the observables kernels.  The sums run in an order fixed by nq, so
+ * repeated calls give the same bits.  The channel keeps a partial-sum buffer
+ * (allocated on first use, up to 128 MB at nq = 15): steps of one channel
+ * must not run at the same time.  The first call may synchronise the device
+ * (to replace that buffer); later calls do not.
+ */
+int qcw_channel_step_obs(qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out, int k,
+                         const int *targets, const qcw_c64 *U, const qcw_c64 *psi0,
+                         double *obs, void *stream);
 int qcw_channel_destroy(qcw_channel *c);
 /* Real FP64 operations per output element of one application, as evaluated
  * by the kernel the channel runs (for roofline accounting).  Terms whose
@@ -480,7 +497,8 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info);
  * these terms (host call, no device needed; for tests).  Arguments as for
  * qcw_channel_create; gate_k != 0 asks instead for the kernel that
  * qcw_channel_apply_gate compiles for the gate (gate_k, gate_targets, gate_U),
- * which has none (length 0) unless the gate is monomial.  *len:
+ * which has none (length 0) unless the gate is monomial; observables != 0
+ * asks for the variant of qcw_channel_step_obs, which also sums them.  *len:
  * the source's length (0 when the channel has no tiled plan); when buf is
  * not NULL, up to cap - 1 bytes of it and a NUL are written there.  compile != 0: the source is also compiled for gfx950 with
  * the run-time compiler and *code_bytes set to the code object's size; a
@@ -491,8 +509,9 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info);
  */
 int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *mats,
                              int64_t nmats, int gate_k, const int *gate_targets,
-                             const qcw_c64 *gate_U, int compile, char *buf, size_t cap, size_t *len,
-                             size_t *code_bytes, int32_t *compiler_version);
+                             const qcw_c64 *gate_U, int observables, int compile, char *buf,
+                             size_t cap, size_t *len, size_t *code_bytes,
+                             int32_t *compiler_version);
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
 

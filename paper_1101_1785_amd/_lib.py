@@ -92,9 +92,10 @@ _SIGS = {
     "qcw_channel_destroy": ([_P], _i32),
     "qcw_channel_flops_per_element": ([_P], _i64),
     "qcw_debug_channel_plan": ([_P, _i32, _P], _i32),
-    "qcw_debug_channel_source": ([_i32, _P, _i32, _P, _i64, _i32, _P, _P, _i32, _P, ctypes.c_size_t,
-                                  _P, _P, _P], _i32),
+    "qcw_debug_channel_source": ([_i32, _P, _i32, _P, _i64, _i32, _P, _P, _i32, _i32, _P,
+                                  ctypes.c_size_t, _P, _P, _P], _i32),
     "qcw_channel_apply_gate": ([_P, _P, _P, _i32, _P, _P, _P], _i32),
+    "qcw_channel_step_obs": ([_P, _P, _P, _i32, _P, _P, _P, _P, _P], _i32),
     "qcw_rho_observables": ([_P, _i32, _P, _P, _P], _i32),
     "qcw_rho_eigvals": ([_P, _i32, _P, _P], _i32),
     "qcw_rho_eigvals_batch": ([_P, _i32, _i64, _i64, _P, _P, _P], _i32),
@@ -626,7 +627,7 @@ def pack_terms(terms):
     return tab, M
 
 
-def channel_kernel_source(nq, terms, compile=False, gate=None):
+def channel_kernel_source(nq, terms, compile=False, gate=None, observables=False):
     """(source, code_bytes, compiler_version) of the tiled kernel a Channel
     over these terms compiles at creation (qcw_debug_channel_source; host
     only), or with gate = (U, targets) the one apply_gate compiles for that
@@ -640,7 +641,8 @@ def channel_kernel_source(nq, terms, compile=False, gate=None):
         gk = len(gate[1])
         gt, gu = _targets(gate[1]), _mat(gate[0], gk)
     args = (int(nq), _hptr(tab) if len(tab) else None, len(tab), _hptr(mats), mats.size, gk,
-            _hptr(gt) if gt is not None else None, _hptr(gu) if gu is not None else None)
+            _hptr(gt) if gt is not None else None, _hptr(gu) if gu is not None else None,
+            int(bool(observables)))
     _check(_L.qcw_debug_channel_source(*args, 0, None, 0, ctypes.byref(n), None, None),
            "qcw_debug_channel_source")
     buf = ctypes.create_string_buffer(n.value + 1)
@@ -673,6 +675,19 @@ class Channel:
         U = _mat(U, k)
         _check(_L.qcw_channel_apply_gate(self.h, _dptr(rho_in), _dptr(rho_out), k, _hptr(t),
                                          _hptr(U), _stream(stream)), "qcw_channel_apply_gate")
+
+    def step_obs(self, rho_in, rho_out, obs, U=None, targets=(), psi0=None, stream=None):
+        """qcw_channel_step_obs: rho_out = U channel(rho_in) U^dagger (no gate
+        when U is None) and its trace (re, im), purity and root fidelity
+        against psi0 (a device tensor, or None) into obs (a device float64
+        tensor of 4), asynchronously."""
+        k = 0 if U is None else len(targets)
+        t = _targets(targets) if k else None
+        Um = _mat(U, k) if k else None
+        _check(_L.qcw_channel_step_obs(self.h, _dptr(rho_in), _dptr(rho_out), k,
+                                       _hptr(t) if k else None, _hptr(Um) if k else None,
+                                       _dptr(psi0) if psi0 is not None else None, _dptr_f64(obs),
+                                       _stream(stream)), "qcw_channel_step_obs")
 
     def flops_per_element(self):
         return int(_L.qcw_channel_flops_per_element(self.h))

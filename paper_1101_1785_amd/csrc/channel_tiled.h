@@ -81,10 +81,11 @@ int tiled_channel_apply(const TiledChannel *t, const double2 *in, double2 *out, 
                         bool generic);
 void tiled_channel_free(TiledChannel *t);
 // Source of the kernel specialised to the plan of these terms, storing its
-// outputs at their places after the permutation gate `perm` when it is not
-// NULL (host only; empty when the channel does not suit the tiled kernel).
+// outputs at their places after the monomial gate `perm` when it is not
+// NULL, and summing the observables when obs (host only; empty when the
+// channel does not suit the tiled kernel).
 std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms,
-                                 const OutPerm *perm = nullptr);
+                                 const OutPerm *perm = nullptr, bool obs = false);
 // The channel followed by conjugation with a monomial gate, in one pass:
 // the compiled kernel stores output (n, m), times u_l(n) conj(u_l(m)), at
 // (pi(n), pi(m)).  The kernel for
@@ -94,6 +95,16 @@ int tiled_channel_apply_perm(const TiledChannel *t, const OutPerm &perm, const d
                              double2 *out, hipStream_t s);
 // Whether tiled_channel_apply_perm would run (compiling the kernel if needed).
 bool tiled_channel_perm_ready(const TiledChannel *t, const OutPerm &perm);
+// The same kernels (perm may be NULL: no gate) that also reduce the stored
+// rho's trace (re, im), sum |rho|^2 and Re <psi0|rho|psi0> (psi0: device,
+// 2^nq amplitudes, or NULL): each wave writes its four sums for its part
+// of a tile to part, at a place fixed by the tile (tiled_channel_obs_records
+// records of four doubles), to be summed in a fixed order.  QCW_EAGAIN when
+// no compiled kernel is available.
+int tiled_channel_apply_obs(const TiledChannel *t, const OutPerm *perm, const double2 *in,
+                            double2 *out, const double2 *psi0, double *part, hipStream_t s);
+bool tiled_channel_obs_ready(const TiledChannel *t, const OutPerm *perm, bool fidelity);
+uint64_t tiled_channel_obs_records(const TiledChannel *t);
 // Compiles such a source for gfx950 without loading it (no device needed);
 // sets the code object's size.
 int tiled_channel_compile_check(const std::string &src, size_t *code_bytes);

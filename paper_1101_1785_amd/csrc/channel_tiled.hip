@@ -533,7 +533,10 @@ constexpr const char *kSpecName = "qcw_channel_tiled_spec";
 // three 0.132, four 0.166); at nq = 14 two and three tie.
 int spec_blocks_per_cu(int nq) { return nq <= 12 ? 2 : 3; }
 
-std::string tiled_source(const GenPlan &G, const OutPerm *perm) {
+// obs: 0 no observables; 1 trace and purity; 2 also the fidelity against
+// psi0.  (Two variants rather than a branch on psi0: with the branch the
+// compiler's code for the tile loop needed 286 VGPRs instead of 130.)
+std::string tiled_source(const GenPlan &G, const OutPerm *perm, int obs) {
   const int nq = G.nq, e0 = G.e0, e1 = G.e1;
   const std::vector<TPartner> &P = *G.partners;
   const std::vector<TRead> &R = *G.reads;
@@ -605,7 +608,8 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   }
   add(s, "extern \"C\" __global__ __launch_bounds__(%d) void %s(const double2 *__restrict__ rho, "
          "double2 *__restrict__ out, const CT *__restrict__ tables, u32 *tickets, double p_keep, "
-         "u32 xcd_blocks, u32 nsub) {\n", kTileThreads, kSpecName);
+         "u32 xcd_blocks, u32 nsub%s) {\n", kTileThreads, kSpecName,
+      obs ? ", const double2 *__restrict__ psi0, double *__restrict__ part" : "");
   if (G.own_staged) add(s, "  __shared__ double2 own_slot[%d];\n", kTileElems);
   if (G.any_staged) add(s, "  __shared__ double2 part_slot[%d];\n", kTileElems);
   if (G.tab_entries) {
@@ -747,6 +751,18 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
     add(s, "    acc%d.x = __fma_rn(p_keep, own%d.x, acc%d.x);\n", a, a, a);
     add(s, "    acc%d.y = __fma_rn(p_keep, own%d.y, acc%d.y);\n", a, a, a);
   }
+  if (obs) add(s, "    double o_tr = 0.0, o_ti = 0.0, o_pu = 0.0, o_fi = 0.0;\n");
+  // Observables of the stored output w at (n2, m2): trace, sum |w|^2, and
+  // Re conj(psi0[n2]) w psi0[m2], in a fixed order per thread.
+  auto observe = [&](const char *n2, const char *m2) {
+    if (!obs) return;
+    add(s, "      if (%s == %s) { o_tr += w.x; o_ti += w.y; }\n", n2, m2);
+    add(s, "      o_pu = __fma_rn(w.x, w.x, o_pu); o_pu = __fma_rn(w.y, w.y, o_pu);\n");
+    if (obs < 2) return;
+    add(s, "      { const double2 pn = psi0[%s], pm = psi0[%s];\n", n2, m2);
+    add(s, "        const double tx = w.x * pm.x - w.y * pm.y, ty = w.x * pm.y + w.y * pm.x;\n");
+    add(s, "        o_fi += pn.x * tx + pn.y * ty; }\n");
+  };
   for (int a = 0; a < 4; ++a) {
     if (perm) {
       // output (n, m) of this thread goes to (pi(n), pi(m))
@@ -761,15 +777,32 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
       }
       add(s, "      const u32 n2 = gate_perm(n1), m2 = gate_perm(m1);\n");
       if (2 * nq + 4 <= 32)  // the byte offset fits 32 bits: scalar base plus a 32-bit offset
-        add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (((n2 << %d) | m2) << 4))); }\n", nq);
+        add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (((n2 << %d) | m2) << 4)));\n", nq);
       else
-        add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + ((((u64)n2 << %d) | m2) << 4))); }\n",
+        add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + ((((u64)n2 << %d) | m2) << 4)));\n",
             nq);
+      observe("n2", "m2");
+      add(s, "    }\n");
     } else {
+      const uint32_t d = ((a & 1) ? 1u << e0 : 0u) | ((a & 2) ? 1u << e1 : 0u);
       add(s, "    { const dbl2v w = {acc%d.x, acc%d.y};\n", a, a);
-      add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (u0 ^ %lluull) + tv)); }\n",
+      add(s, "      __builtin_nontemporal_store(w, (dbl2v *)((char *)out + (u0 ^ %lluull) + tv));\n",
           (unsigned long long)db[a]);
+      if (obs) add(s, "      const u32 n2 = nb | %uu | r, m2 = (mb ^ %uu) | c;\n", d, d);
+      observe("n2", "m2");
+      add(s, "    }\n");
     }
+  }
+  if (obs) {
+    // The wave's sums (a butterfly: lane 0's total is the same on every
+    // call), one record of four per (tile, wave) at a fixed place, so the
+    // final sum does not depend on which block took which tile.
+    add(s, "    for (int sft = 32; sft > 0; sft >>= 1) {\n");
+    add(s, "      o_tr += __shfl_xor(o_tr, sft); o_ti += __shfl_xor(o_ti, sft);\n");
+    add(s, "      o_pu += __shfl_xor(o_pu, sft); o_fi += __shfl_xor(o_fi, sft);\n    }\n");
+    add(s, "    if ((tid & 63u) == 0) {\n");
+    add(s, "      double *q = part + (((u64)x * %uull + j) * 4u + (tid >> 6)) * 4u;\n", G.xcd_tiles);
+    add(s, "      q[0] = o_tr; q[1] = o_ti; q[2] = o_pu; q[3] = o_fi;\n    }\n");
   }
   add(s, "  }\n");
   add(s, "  u32 *done = tickets + (%uu + x) * %uu;\n", 8 * kTicketSubs, kTicketStride);
@@ -931,7 +964,7 @@ bool plan_host(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms, 
   gp.partners = &partners;
   gp.reads = &reads;
   gp.recs = &recs;
-  const std::string spec_src = tiled_source(gp, nullptr);
+  const std::string spec_src = tiled_source(gp, nullptr, 0);
   H.gen = gp;
   H.partners = partners;
   H.reads = reads;
@@ -979,14 +1012,14 @@ bool plan_host(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms, 
 }  // namespace
 
 std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms,
-                                 const OutPerm *perm) {
+                                 const OutPerm *perm, bool obs) {
   HostPlan H;
   if (!plan_host(nq, terms, H)) return std::string();
-  if (!perm) return H.src;
+  if (!perm && !obs) return H.src;
   H.gen.partners = &H.partners;
   H.gen.reads = &H.reads;
   H.gen.recs = &H.recs;
-  return tiled_source(H.gen, perm);
+  return tiled_source(H.gen, perm, obs ? 2 : 0);
 }
 
 int tiled_channel_compile_check(const std::string &src, size_t *code_bytes) {
@@ -1017,29 +1050,32 @@ bool spec_launch(const TiledChannel *t, const RtcKernel *k, TiledChannel::Launch
 }
 
 int launch_spec(const TiledChannel *t, const TiledChannel::Launch &ls, const double2 *in, double2 *out,
-                hipStream_t s) {
+                hipStream_t s, const double2 *psi0 = nullptr, double *part = nullptr) {
   const double2 *a_in = in;
   double2 *a_out = out;
   const void *a_tab = t->args.tables;
   uint32_t *a_tk = t->args.tickets;
   double a_p = t->args.p_keep;
   uint32_t a_xb = ls.xcd_blocks, a_ns = ls.nsub;
-  void *args[] = {&a_in, &a_out, &a_tab, &a_tk, &a_p, &a_xb, &a_ns};
+  const double2 *a_psi = psi0;
+  double *a_part = part;
+  void *args[] = {&a_in, &a_out, &a_tab, &a_tk, &a_p, &a_xb, &a_ns, &a_psi, &a_part};  // the last
+  // two only for a kernel with observables (extra entries are not read)
   if (hipModuleLaunchKernel(ls.k->fn, ls.grid, 1, 1, kTileThreads, 1, 1, 0, s, args, nullptr) !=
       hipSuccess)
     return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(hipGetLastError()));
   return QCW_OK;
 }
 
-// The compiled kernel with permuted stores for this gate (compiled on first
-// use), or nullptr.
-const TiledChannel::Launch *perm_launch(const TiledChannel *t, const OutPerm &p) {
+// The compiled kernel variant for a folded gate (p, or none) and with or
+// without observables (compiled on first use), or nullptr.
+const TiledChannel::Launch *variant_launch(const TiledChannel *t, const OutPerm *p, int obs) {
   if (!t->spec) return nullptr;
-  std::vector<int> key = {p.k};
-  for (int j = 0; j < p.k; ++j) key.push_back(p.bits[j]);
-  for (int l = 0; l < (1 << p.k); ++l) {
-    key.push_back(p.table[l]);
-    for (const double v : {p.ur[l], p.ui[l]}) {
+  std::vector<int> key = {obs, p ? p->k : 0};
+  for (int j = 0; p && j < p->k; ++j) key.push_back(p->bits[j]);
+  for (int l = 0; p && l < (1 << p->k); ++l) {
+    key.push_back(p->table[l]);
+    for (const double v : {p->ur[l], p->ui[l]}) {
       int32_t w[2];
       memcpy(w, &v, sizeof(v));
       key.push_back(w[0]);
@@ -1051,7 +1087,7 @@ const TiledChannel::Launch *perm_launch(const TiledChannel *t, const OutPerm &p)
   if (it != t->perm_kernels.end()) return it->second.k ? &it->second : nullptr;
   TiledChannel::Launch ls;
   const RtcKernel *k = nullptr;
-  if (rtc_get(tiled_source(t->gen, &p), kSpecName, &k) != QCW_OK || !spec_launch(t, k, &ls)) ls = {};
+  if (rtc_get(tiled_source(t->gen, p, obs), kSpecName, &k) != QCW_OK || !spec_launch(t, k, &ls)) ls = {};
   clear_error();
   auto &e = t->perm_kernels[key];
   e = ls;
@@ -1061,14 +1097,29 @@ const TiledChannel::Launch *perm_launch(const TiledChannel *t, const OutPerm &p)
 }  // namespace
 
 bool tiled_channel_perm_ready(const TiledChannel *t, const OutPerm &perm) {
-  return t && perm_launch(t, perm) != nullptr;
+  return t && variant_launch(t, &perm, 0) != nullptr;
 }
 
 int tiled_channel_apply_perm(const TiledChannel *t, const OutPerm &perm, const double2 *in,
                              double2 *out, hipStream_t s) {
-  const TiledChannel::Launch *ls = t ? perm_launch(t, perm) : nullptr;
+  const TiledChannel::Launch *ls = t ? variant_launch(t, &perm, 0) : nullptr;
   if (!ls) return QCW_EAGAIN;
   return launch_spec(t, *ls, in, out, s);
+}
+
+bool tiled_channel_obs_ready(const TiledChannel *t, const OutPerm *perm, bool fidelity) {
+  return t && variant_launch(t, perm, fidelity ? 2 : 1) != nullptr;
+}
+
+uint64_t tiled_channel_obs_records(const TiledChannel *t) {
+  return t ? (uint64_t)t->args.xcd_tiles * 8u * 4u : 0;
+}
+
+int tiled_channel_apply_obs(const TiledChannel *t, const OutPerm *perm, const double2 *in,
+                            double2 *out, const double2 *psi0, double *part, hipStream_t s) {
+  const TiledChannel::Launch *ls = t ? variant_launch(t, perm, psi0 ? 2 : 1) : nullptr;
+  if (!ls) return QCW_EAGAIN;
+  return launch_spec(t, *ls, in, out, s, psi0, part);
 }
 
 int tiled_channel_create(int nq, double p_keep,

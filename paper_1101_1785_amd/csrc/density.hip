@@ -356,6 +356,23 @@ __global__ __launch_bounds__(kObsThreads) void obs_partial_kernel(const double2 
     for (int i = 0; i < 4; ++i) partial[blockIdx.x * 4 + i] = v[i];
 }
 
+// Records of four partial sums (part[4 r + v]) summed block by block: block b
+// takes records [b * per, (b + 1) * per) (thread t the records t, t + 256,
+// ... of that range), then the block's fixed tree; the grid depends only on
+// the record count, so the result is the same on every call.
+__global__ __launch_bounds__(kObsThreads) void obs_records_kernel(const double *__restrict__ part,
+                                                                  uint64_t nrec, uint64_t per,
+                                                                  double *__restrict__ partial) {
+  __shared__ double red[kObsThreads];
+  double v[4] = {0, 0, 0, 0};
+  const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = b0 + per < nrec ? b0 + per : nrec;
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kObsThreads)
+    for (int k = 0; k < 4; ++k) v[k] += part[i * 4 + k];
+  block_sum<4>(v, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) partial[blockIdx.x * 4 + k] = v[k];
+}
+
 // One block per (qubit, component): P = Tr[sigma^(q) rho], read off the 2x2
 // blocks of rho on that qubit.
 __global__ __launch_bounds__(kObsThreads) void obs_polar_kernel(const double2 *__restrict__ rho,
@@ -417,6 +434,8 @@ struct qcw_channel {
   TiledChannel *tiled = nullptr;  // tiled plan (permutation terms only, 7 <= nq <= 15)
   int force_gather = 0;           // run the gather kernel even with a tiled plan
   int tiled_generic = 0;          // run the generic tiled kernel even with a compiled one
+  double *obs_part = nullptr;     // partial observables of qcw_channel_step_obs (on first use)
+  size_t obs_part_bytes = 0;
 };
 
 namespace {
@@ -425,6 +444,7 @@ void channel_free(qcw_channel *c) {
   (void)hipFree(c->coef_d);
   (void)hipFree(c->groups_d);
   (void)hipFree(c->perm_d);
+  (void)hipFree(c->obs_part);
   tiled_channel_free(c->tiled);
   delete c;
 }
@@ -691,6 +711,80 @@ int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 
   return qcw_rho_conjugate(k, targets, U, rho_out, c->nq, stream);
 }
 
+int qcw_channel_step_obs(qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out, int k,
+                         const int *targets, const qcw_c64 *U, const qcw_c64 *psi0,
+                         double *obs, void *stream) {
+  clear_error();
+  if (!c) return fail(QCW_EINVAL, "channel is NULL");
+  if (!obs) return fail(QCW_EINVAL, "obs is NULL");
+  const int nq = c->nq;
+  const uint64_t N = 1ull << nq, bytes = N * N * sizeof(qcw_c64);
+  int rc;
+  if ((rc = check_device_range(obs, 4 * sizeof(double), "obs"))) return rc;
+  if (psi0 && (rc = check_device_range(psi0, N * sizeof(qcw_c64), "psi0"))) return rc;
+  OutPerm p;
+  bool mono = false;
+  if (k != 0) {
+    if (!U) return fail(QCW_EINVAL, "U is NULL");
+    Geom g;
+    if ((rc = make_geom(nq, k, targets, &g))) return rc;
+    mono = gate_monomial(k, g, U, &p);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool fused = c->tiled && !c->force_gather && !c->tiled_generic && (k == 0 || mono) &&
+                     tiled_channel_obs_ready(c->tiled, mono ? &p : nullptr, psi0 != nullptr);
+  const uint64_t records = fused ? tiled_channel_obs_records(c->tiled) : (uint64_t)obs_blocks(nq);
+  // the kernel's records are first summed by up to kObsMaxBlocks blocks
+  const uint64_t nred = fused ? std::min<uint64_t>(records, kObsMaxBlocks) : 0;
+  const size_t need = (records + nred) * 4 * sizeof(double);
+  if (c->obs_part_bytes < need) {
+    // the previous buffer may still be read by this channel's queued work
+    if (c->obs_part && hipDeviceSynchronize() != hipSuccess) return fail(QCW_EHIP, "observables buffer sync");
+    (void)hipFree(c->obs_part);
+    c->obs_part = nullptr;
+    c->obs_part_bytes = 0;
+    if (hipMalloc(&c->obs_part, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(QCW_ENOMEM, "observables buffer of %zu bytes", need);
+    }
+    c->obs_part_bytes = need;
+  }
+  const double2 *in = reinterpret_cast<const double2 *>(rho_in);
+  double2 *out = reinterpret_cast<double2 *>(rho_out);
+  const double2 *ps = reinterpret_cast<const double2 *>(psi0);
+  if (fused) {
+    const uint64_t a = (uint64_t)(uintptr_t)rho_in, b = (uint64_t)(uintptr_t)rho_out;
+    if (a < b + bytes && b < a + bytes) return fail(QCW_EINVAL, "rho_in and rho_out overlap");
+    if ((rc = check_device_range(rho_in, bytes, "rho_in")) || (rc = check_device_range(rho_out, bytes, "rho_out")))
+      return rc;
+    {
+      TimedLaunch t(QCW_KERNEL_CHANNEL, s);
+      rc = tiled_channel_apply_obs(c->tiled, mono ? &p : nullptr, in, out, ps, c->obs_part, s);
+    }
+    if (rc) return rc;
+  } else {
+    rc = k == 0 ? qcw_channel_apply(c, rho_in, rho_out, stream)
+                : qcw_channel_apply_gate(c, rho_in, rho_out, k, targets, U, stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(obs_partial_kernel, dim3((unsigned)records), dim3(kObsThreads), 0, s, out, nq,
+                       ps, c->obs_part);
+  }
+  if (fused) {
+    double *red = c->obs_part + records * 4;
+    const uint64_t per = (records + nred - 1) / nred;
+    hipLaunchKernelGGL(obs_records_kernel, dim3((unsigned)nred), dim3(kObsThreads), 0, s, c->obs_part,
+                       records, per, red);
+    hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, red, (int)nred, obs,
+                       psi0 ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, c->obs_part, (int)records, obs,
+                       psi0 ? 1 : 0);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(QCW_EHIP, "step observables: %s", hipGetErrorString(e));
+  return QCW_OK;
+}
+
 int qcw_channel_destroy(qcw_channel *c) {
   clear_error();
   if (c) channel_free(c);
@@ -726,8 +820,9 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info) {
 
 int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, const qcw_c64 *mats,
                              int64_t nmats, int gate_k, const int *gate_targets,
-                             const qcw_c64 *gate_U, int compile, char *buf, size_t cap, size_t *len,
-                             size_t *code_bytes, int32_t *compiler_version) {
+                             const qcw_c64 *gate_U, int observables, int compile, char *buf,
+                             size_t cap, size_t *len, size_t *code_bytes,
+                             int32_t *compiler_version) {
   clear_error();
   if (compiler_version) *compiler_version = tiled_channel_compiler_version();
   if (!len) return fail(QCW_EINVAL, "len is NULL");
@@ -750,8 +845,9 @@ int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, co
     if (compile) *code_bytes = 0;
     return QCW_OK;
   }
-  const std::string src =
-      dt.empty() ? tiled_channel_source(nq, pt, with_gate ? &perm : nullptr) : std::string();
+  const std::string src = dt.empty() ? tiled_channel_source(nq, pt, with_gate ? &perm : nullptr,
+                                                           observables != 0)
+                                     : std::string();
   *len = src.size();
   if (buf && cap > 0) {
     const size_t n = std::min(cap - 1, src.size());

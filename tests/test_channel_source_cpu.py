@@ -103,3 +103,15 @@ def test_permutation_gate_gets_a_kernel_of_its_own(L):
     assert "gate_ur" in z and "0x1p+0" in z and codez > 1000
     toff, code3, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(qi.TOFFOLI, (1, 2, 3)))
     assert "gate_perm" in toff and code3 > 1000
+
+
+def test_observables_variant_compiles(L):
+    """The kernel of qcw_channel_step_obs sums the observables as it stores:
+    with and without a folded gate it compiles, and it writes one record of
+    four sums per (tile, wave)."""
+    nq = 9
+    terms = _pauli(np.random.default_rng(4), nq)
+    for gate in (None, (qi.CNOT, (1, nq)), (np.diag([1.0, -1.0]), (3,))):
+        src, code, _ = L.channel_kernel_source(nq, terms, compile=True, gate=gate, observables=True)
+        assert "o_pu" in src and "double *__restrict__ part" in src and code > 1000
+    assert "o_pu" not in L.channel_kernel_source(nq, terms)[0]

@@ -277,6 +277,48 @@ def test_channel_apply_gate_other_kernels(L):
         ch.close()
 
 
+@pytest.mark.parametrize("kind,nq,seed,choice", [("pauli", 9, 1, -1), ("phase", 8, 3, -1),
+                                                 ("pauli", 12, 8, -1), ("pauli", 6, 2, -1),
+                                                 ("pauli", 8, 4, 1), ("pauli", 8, 5, 2)])
+def test_channel_step_obs_matches_observables(L, kind, nq, seed, choice):
+    """qcw_channel_step_obs: the step equals qcw_channel_apply_gate (or the
+    channel alone), and its four observables equal qcw_rho_observables of the
+    result to 1e-12, the same bits on a repeated call.  Summed in the
+    compiled kernel (nq = 8, 9, 12 with the default kernel choice) or by the
+    observables kernels (nq = 6; the gather and generic tiled kernels)."""
+    print(f"[gpu] step with observables {kind} nq={nq} kernel={choice}", flush=True)
+    rng = np.random.default_rng(5000 + seed)
+    terms = _pauli_terms(rng, nq) if kind == "pauli" else _tiled_case(kind, nq, seed)
+    ch = L.Channel(nq, 0.8, terms)
+    ch.plan(choice)
+    rho0 = _rand_rho(rng, nq)
+    psi = rng.normal(size=1 << nq) + 1j * rng.normal(size=1 << nq)
+    psi /= np.linalg.norm(psi)
+    psi_d = torch.from_numpy(psi).to("cuda")
+    a = dev(rho0)
+    obs = torch.empty(4, dtype=torch.float64, device="cuda")
+    for U, t in ((qi.CNOT, (1, nq)), (qi.Z, (2,)), (qi.H, (1,)), (None, ())):
+        b1 = torch.full_like(a, float("nan"))
+        b2 = torch.full_like(a, float("nan"))
+        ch.step_obs(a, b1, obs, U, t, psi0=psi_d)
+        o1 = obs.cpu().numpy().copy()
+        ch.step_obs(a, b1, obs, U, t, psi0=psi_d)
+        o2 = obs.cpu().numpy().copy()
+        assert np.array_equal(o1, o2), t
+        if U is None:
+            ch.apply(a, b2)
+        else:
+            ch.apply_gate(a, b2, U, t)
+        torch.cuda.synchronize()
+        assert torch.equal(b1, b2), t
+        ref = L.qcw_rho_observables(b2, psi0=psi)
+        want = [ref["trace"].real, ref["trace"].imag, ref["purity"], ref["fidelity"]]
+        assert np.max(np.abs(o1 - np.array(want))) <= 1e-12, (t, o1, want)
+    ch.step_obs(a, b1, obs, qi.CNOT, (1, 2))  # no psi0: NaN fidelity
+    assert np.isnan(obs.cpu().numpy()[3])
+    ch.close()
+
+
 def test_channel_apply_gate_rejects_bad_input(L):
     ch = L.Channel(8, 0.8, _pauli_terms(np.random.default_rng(1), 8))
     a = torch.zeros(1 << 16, dtype=torch.complex128, device="cuda")
