@@ -629,7 +629,7 @@ def bench_multiverse(torch, L, qi, nq, seed, n_p=16, eps=0.2, steps=20, noise="p
 
 def bench_multiverse_obs(torch, L, qi, nq, seed, steps=10, n_p=16, eps=0.2):
     """Multiverse steps with the observables of §5 (trace, purity, fidelity
-    against |0..0>) after every step.  qcw_channel_step_obs sums them in the
+    against |0..0>, polarisations) after every step.  qcw_channel_step_obs sums them in the
     channel's own pass (asynchronously, into device memory), against the
     step followed by qcw_rho_observables (a further pass over rho, and a
     synchronisation) every step.  The same channel and GHZ-chain gates as
@@ -646,9 +646,9 @@ def bench_multiverse_obs(torch, L, qi, nq, seed, steps=10, n_p=16, eps=0.2):
     psi0_d = torch.from_numpy(psi0).to("cuda")
     rho0 = torch.from_numpy(np.outer(psi0, psi0.conj()).reshape(-1)).to("cuda")
     a, b = rho0.clone(), torch.empty_like(rho0)
-    obs = torch.empty(4, dtype=torch.float64, device="cuda")
+    obs = torch.empty(4 + 3 * nq, dtype=torch.float64, device="cuda")
     gates = [(qi.H, (1,))] + [(qi.CNOT, (1, t)) for t in range(2, nq + 1)]
-    hist = np.empty((steps, 4))
+    hist = np.empty((steps, 4 + 3 * nq))
     for i in range(min(len(gates), steps)):  # compile both kernels of each gate before the timing
         U, t = gates[i]
         ch.step_obs(a, b, obs, U, t, psi0=psi0_d)
@@ -670,7 +670,8 @@ def bench_multiverse_obs(torch, L, qi, nq, seed, steps=10, n_p=16, eps=0.2):
             else:
                 ch.apply_gate(x, y, U, t)
                 o = L.qcw_rho_observables(y, psi0=psi0)
-                hist[i] = [o["trace"].real, o["trace"].imag, o["purity"], o["fidelity"]]
+                hist[i] = [o["trace"].real, o["trace"].imag, o["purity"], o["fidelity"],
+                           *o["polarization"].reshape(-1)]
             x, y = y, x
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps * 1e3

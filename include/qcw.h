@@ -438,13 +438,15 @@ int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 
                            const int *targets, const qcw_c64 *U, void *stream);
 /*
  * The same step (k = 0: the channel alone), also reducing the new rho's
- * observables of §5 into obs (DEVICE, 4 doubles, written asynchronously on
- * stream): Tr rho (re, im), Tr rho^2 as sum |rho_nm|^2, and the root fidelity
- * sqrt(<psi0|rho|psi0>) against psi0 (DEVICE, 2^nq amplitudes; NULL: NaN), the
- * first four values of qcw_rho_observables.  When the step runs as the
- * compiled kernel (a monomial gate or none), that kernel sums them as it
- * stores rho, with no further pass over rho.  Otherwise the step is followed
- * by the observables kernels.  The sums run in an order fixed by nq, so
+ * observables of §5 into obs (DEVICE, 4 + 3 nq doubles, written
+ * asynchronously on stream), laid out as qcw_rho_observables: Tr rho (re,
+ * im), Tr rho^2 as sum |rho_nm|^2, the root fidelity sqrt(<psi0|rho|psi0>)
+ * against psi0 (DEVICE, 2^nq amplitudes; NULL: NaN), and each qubit's
+ * polarisation.  When the step runs as the compiled kernel (a monomial gate
+ * or none), that kernel sums the first four as it stores rho, with no
+ * further pass over rho; the polarisations read the 2 x 2 blocks on each
+ * qubit afterwards.  Otherwise the step is followed by the observables
+ * kernels.  The sums run in an order fixed by nq, so
  * repeated calls give the same bits.  The channel keeps a partial-sum buffer
  * (allocated on first use, up to 128 MB at nq = 15): steps of one channel
  * must not run at the same time.  The first call may synchronise the device

@@ -678,9 +678,10 @@ class Channel:
 
     def step_obs(self, rho_in, rho_out, obs, U=None, targets=(), psi0=None, stream=None):
         """qcw_channel_step_obs: rho_out = U channel(rho_in) U^dagger (no gate
-        when U is None) and its trace (re, im), purity and root fidelity
-        against psi0 (a device tensor, or None) into obs (a device float64
-        tensor of 4), asynchronously."""
+        when U is None) and its trace (re, im), purity, root fidelity against
+        psi0 (a device tensor, or None) and polarisations into obs (a device
+        float64 tensor of 4 + 3 nq, laid out as qcw_rho_observables),
+        asynchronously."""
         k = 0 if U is None else len(targets)
         t = _targets(targets) if k else None
         Um = _mat(U, k) if k else None

@@ -720,7 +720,7 @@ int qcw_channel_step_obs(qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out
   const int nq = c->nq;
   const uint64_t N = 1ull << nq, bytes = N * N * sizeof(qcw_c64);
   int rc;
-  if ((rc = check_device_range(obs, 4 * sizeof(double), "obs"))) return rc;
+  if ((rc = check_device_range(obs, (4 + 3 * (size_t)nq) * sizeof(double), "obs"))) return rc;
   if (psi0 && (rc = check_device_range(psi0, N * sizeof(qcw_c64), "psi0"))) return rc;
   OutPerm p;
   bool mono = false;
@@ -780,6 +780,8 @@ int qcw_channel_step_obs(qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out
     hipLaunchKernelGGL(obs_final_kernel, dim3(1), dim3(kObsThreads), 0, s, c->obs_part, (int)records, obs,
                        psi0 ? 1 : 0);
   }
+  // the polarisations read only the 2 x 2 blocks on each qubit
+  hipLaunchKernelGGL(obs_polar_kernel, dim3(3 * nq), dim3(kObsThreads), 0, s, out, nq, obs);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(QCW_EHIP, "step observables: %s", hipGetErrorString(e));
   return QCW_OK;

@@ -285,7 +285,9 @@ def test_channel_step_obs_matches_observables(L, kind, nq, seed, choice):
     channel alone), and its four observables equal qcw_rho_observables of the
     result to 1e-12, the same bits on a repeated call.  Summed in the
     compiled kernel (nq = 8, 9, 12 with the default kernel choice) or by the
-    observables kernels (nq = 6; the gather and generic tiled kernels)."""
+    observables kernels (nq = 6; the gather and generic tiled kernels).  The
+    polarisations come from the same kernel as qcw_rho_observables': equal
+    bits."""
     print(f"[gpu] step with observables {kind} nq={nq} kernel={choice}", flush=True)
     rng = np.random.default_rng(5000 + seed)
     terms = _pauli_terms(rng, nq) if kind == "pauli" else _tiled_case(kind, nq, seed)
@@ -296,7 +298,7 @@ def test_channel_step_obs_matches_observables(L, kind, nq, seed, choice):
     psi /= np.linalg.norm(psi)
     psi_d = torch.from_numpy(psi).to("cuda")
     a = dev(rho0)
-    obs = torch.empty(4, dtype=torch.float64, device="cuda")
+    obs = torch.empty(4 + 3 * nq, dtype=torch.float64, device="cuda")
     for U, t in ((qi.CNOT, (1, nq)), (qi.Z, (2,)), (qi.H, (1,)), (None, ())):
         b1 = torch.full_like(a, float("nan"))
         b2 = torch.full_like(a, float("nan"))
@@ -313,7 +315,8 @@ def test_channel_step_obs_matches_observables(L, kind, nq, seed, choice):
         assert torch.equal(b1, b2), t
         ref = L.qcw_rho_observables(b2, psi0=psi)
         want = [ref["trace"].real, ref["trace"].imag, ref["purity"], ref["fidelity"]]
-        assert np.max(np.abs(o1 - np.array(want))) <= 1e-12, (t, o1, want)
+        assert np.max(np.abs(o1[:4] - np.array(want))) <= 1e-12, (t, o1[:4], want)
+        assert np.array_equal(o1[4:].reshape(nq, 3), ref["polarization"]), t
     ch.step_obs(a, b1, obs, qi.CNOT, (1, 2))  # no psi0: NaN fidelity
     assert np.isnan(obs.cpu().numpy()[3])
     ch.close()
