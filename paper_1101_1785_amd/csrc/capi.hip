@@ -119,7 +119,7 @@ const char *qcw_strerror(int code) {
 
 const char *qcw_last_error(void) { return last_error(); }
 
-int qcw_version(void) { return 100; }
+int qcw_version(void) { return 200; }  // 0.2.0: compiled channel kernels, one-call and observed steps
 
 int qcw_opk_to(int k, const int *targets, const qcw_c64 *U, const qcw_c64 *psi_in,
                qcw_c64 *psi_out, int nq, void *stream) {
