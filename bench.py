@@ -1042,6 +1042,7 @@ def extra_sections(torch, L, qi, a):
         "multiverse_nq13_generic": lambda: bench_multiverse(torch, L, qi, 13, 5, steps=10, kernel=2),
         "multiverse_nq14": lambda: bench_multiverse(torch, L, qi, 14, 5, steps=5),
         "multiverse_nq13_observed": lambda: bench_multiverse_obs(torch, L, qi, 13, 5),
+        "multiverse_nq15": lambda: bench_multiverse(torch, L, qi, 15, 5, steps=3),
         "eigen_batch_nq5": lambda: bench_eigen(torch, L, 5),
         "eigen_batch_nq6": lambda: bench_eigen(torch, L, 6),
         "multiverse_nq5": lambda: bench_multiverse(torch, L, qi, 5, 5, steps=200),

@@ -37,6 +37,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <set>
 #include <string>
@@ -392,6 +393,11 @@ struct GenPlan {
   uint32_t xcd_tiles;
   bool real, own_staged, any_staged;
   size_t tab_entries;
+  // Order of the tiles of a family: member = sum over set bits k of the
+  // ticket's member field of member_basis[k] (XOR); coset_order false: the
+  // member is the field itself.
+  bool coset_order;
+  uint32_t member_basis[32];
   const std::vector<TPartner> *partners;
   const std::vector<TRead> *reads;
   const std::vector<TRec> *recs;  // entry_b still the table entry index
@@ -635,7 +641,17 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   // needs none.
   add(s, "    u32 tv = t0b;\n    asm volatile(\"\" : \"+v\"(tv));\n");
   add(s, "    const u32 family = ((j >> %d) << 3) | x;\n", G.mb_bits);
-  add(s, "    u32 nb = (j & %uu) << 4;\n", (1u << G.mb_bits) - 1u);
+  if (G.coset_order) {
+    // A tile's partners differ from it by members in the span of the
+    // partner flips.  With that span's basis first, the tiles of one coset
+    // (closed under every flip) take consecutive tickets, so the partner
+    // tiles in use on an XCD stay within a coset rather than the family.
+    add(s, "    const u32 jm = j & %uu;\n    u32 nb = 0u", (1u << G.mb_bits) - 1u);
+    for (int k = 0; k < G.mb_bits; ++k) add(s, " ^ (((jm >> %d) & 1u) * %uu)", k, G.member_basis[k]);
+    add(s, ";\n    nb <<= 4;\n");
+  } else {
+    add(s, "    u32 nb = (j & %uu) << 4;\n", (1u << G.mb_bits) - 1u);
+  }
   add(s, "    nb = ((nb >> %d) << %d) | (nb & %uu);\n", e0, e0 + 1, (1u << e0) - 1u);
   add(s, "    nb = ((nb >> %d) << %d) | (nb & %uu);\n", e1, e1 + 1, (1u << e1) - 1u);
   add(s, "    const u32 mb = nb ^ (family << 4);\n");
@@ -961,6 +977,33 @@ bool plan_host(int nq, const std::vector<std::pair<uint64_t, PermTerm>> &terms, 
   gp.own_staged = sm.own_staged != 0;
   gp.any_staged = sm.staged > 0;
   gp.tab_entries = tab.size();
+  // Member-space vectors of the partner flips (tile base bits 4.. without
+  // E0, E1, packed), a basis of their span first, then unit vectors.
+  {
+    std::vector<int> pos;
+    for (int b = 4; b < nq; ++b)
+      if (b != e0 && b != e1) pos.push_back(b);
+    const int mbits = (int)pos.size();  // == nq - 6
+    std::vector<uint32_t> basis, reduced;  // reduced: echelon copies for the rank test
+    auto try_add = [&](uint32_t v) {
+      uint32_t w = v;
+      for (uint32_t r : reduced)
+        if ((w ^ r) < w) w ^= r;  // r's leading bit is set in w: clear it
+      if (!w) return;
+      basis.push_back(v);
+      reduced.push_back(w);
+      std::sort(reduced.begin(), reduced.end(), std::greater<uint32_t>());
+    };
+    for (const auto &pk : plan) {
+      uint32_t h = 0;
+      for (int i = 0; i < mbits; ++i) h |= ((pk.first >> pos[i]) & 1u) << i;
+      if (h) try_add(h);
+    }
+    const size_t rank = basis.size();
+    for (int i = 0; i < mbits; ++i) try_add(1u << i);
+    gp.coset_order = rank < (size_t)mbits;
+    for (int k = 0; k < mbits && k < 32; ++k) gp.member_basis[k] = basis[k];
+  }
   gp.partners = &partners;
   gp.reads = &reads;
   gp.recs = &recs;
