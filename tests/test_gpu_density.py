@@ -332,6 +332,11 @@ def test_channel_apply_gate_rejects_bad_input(L):
         ch.apply_gate(a, b, qi.CNOT, (1, 9))       # target outside [1, nq]
     with pytest.raises(RuntimeError):
         ch.apply_gate(a, a, qi.CNOT, (1, 2))       # rho_in == rho_out
+    obs = torch.empty(4 + 3 * 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError):
+        ch.step_obs(a, b, obs, qi.CNOT, (2, 2))    # repeated target
+    with pytest.raises(RuntimeError):
+        ch.step_obs(a, a, obs, qi.CNOT, (1, 2))    # rho_in == rho_out
     ch.close()
 
 
