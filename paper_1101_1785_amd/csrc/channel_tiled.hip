@@ -579,6 +579,29 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return a;
 }
 )";
+  if (obs) {
+    // A wave's sum of one double with data-parallel-primitive moves: pairs
+    // and quads (quad permutations), rows of 16 (half-row and row mirrors),
+    // then the row-15 and row-31 broadcasts carry the row totals up, so that
+    // lane 63 ends with all 64.  Masked-off rows take the +0 start value.
+    s += R"(template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double v) {
+  const u64 b = __builtin_bit_cast(u64, v);
+  const u32 lo = __builtin_amdgcn_update_dpp(0, (int)(u32)b, CTRL, ROWS, 0xF, false);
+  const u32 hi = __builtin_amdgcn_update_dpp(0, (int)(u32)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, ((u64)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_take<0xB1, 0xF>(v);   // quad_perm 1,0,3,2
+  v += dpp_take<0x4E, 0xF>(v);   // quad_perm 2,3,0,1
+  v += dpp_take<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_take<0x140, 0xF>(v);  // row_mirror
+  v += dpp_take<0x142, 0xA>(v);  // row_bcast 15, into rows 1 and 3
+  v += dpp_take<0x143, 0xC>(v);  // row_bcast 31, into rows 2 and 3
+  return v;
+}
+)";
+  }
   if (perm) {
     // pi on a row or column index: the gate's local index l from its bits,
     // pi(l) from a packed table of 3-bit entries, the changed bits flipped.
@@ -810,13 +833,13 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
     }
   }
   if (obs) {
-    // The wave's sums (a butterfly: lane 0's total is the same on every
-    // call), one record of four per (tile, wave) at a fixed place, so the
-    // final sum does not depend on which block took which tile.
-    add(s, "    for (int sft = 32; sft > 0; sft >>= 1) {\n");
-    add(s, "      o_tr += __shfl_xor(o_tr, sft); o_ti += __shfl_xor(o_ti, sft);\n");
-    add(s, "      o_pu += __shfl_xor(o_pu, sft); o_fi += __shfl_xor(o_fi, sft);\n    }\n");
-    add(s, "    if ((tid & 63u) == 0) {\n");
+    // The wave's sums (register moves between lanes, in a fixed order: lane
+    // 63's total is the same on every call), one record of four per (tile,
+    // wave) at a fixed place, so the final sum does not depend on which
+    // block took which tile.
+    add(s, "    o_tr = wave_sum(o_tr); o_ti = wave_sum(o_ti);\n");
+    add(s, "    o_pu = wave_sum(o_pu); o_fi = wave_sum(o_fi);\n");
+    add(s, "    if ((tid & 63u) == 63u) {\n");
     add(s, "      double *q = part + (((u64)x * %uull + j) * 4u + (tid >> 6)) * 4u;\n", G.xcd_tiles);
     add(s, "      q[0] = o_tr; q[1] = o_ti; q[2] = o_pu; q[3] = o_fi;\n    }\n");
   }

@@ -114,4 +114,5 @@ def test_observables_variant_compiles(L):
     for gate in (None, (qi.CNOT, (1, nq)), (np.diag([1.0, -1.0]), (3,))):
         src, code, _ = L.channel_kernel_source(nq, terms, compile=True, gate=gate, observables=True)
         assert "o_pu" in src and "double *__restrict__ part" in src and code > 1000
+        assert "wave_sum(o_pu)" in src  # register moves between lanes, no LDS round trip
     assert "o_pu" not in L.channel_kernel_source(nq, terms)[0]
