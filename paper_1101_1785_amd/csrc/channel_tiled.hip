@@ -798,7 +798,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     add(s, "      if (%s == %s) { o_tr += w.x; o_ti += w.y; }\n", n2, m2);
     add(s, "      o_pu = __fma_rn(w.x, w.x, o_pu); o_pu = __fma_rn(w.y, w.y, o_pu);\n");
     if (obs < 2) return;
-    add(s, "      { const double2 pn = psi0[%s], pm = psi0[%s];\n", n2, m2);
+    if (nq + 4 <= 32)  // scalar base plus a 32-bit byte offset, no 64-bit address adds
+      add(s, "      { const double2 pn = *(const double2 *)((const char *)psi0 + (%s << 4)),\n"
+             "          pm = *(const double2 *)((const char *)psi0 + (%s << 4));\n", n2, m2);
+    else
+      add(s, "      { const double2 pn = psi0[%s], pm = psi0[%s];\n", n2, m2);
     add(s, "        const double tx = w.x * pm.x - w.y * pm.y, ty = w.x * pm.y + w.y * pm.x;\n");
     add(s, "        o_fi += pn.x * tx + pn.y * ty; }\n");
   };
