@@ -45,12 +45,20 @@ struct TiledChannel;
 // bit of the local index l): U |l> = u_l |pi(l)>, table[l] = pi(l).  The
 // conjugation rho -> U rho U^dagger moves element (n, m) to (pi(n), pi(m))
 // and multiplies it by u_l(n) conj(u_l(m)).
+//
+// With general set, the gate is any k-qubit matrix on bits among 0..3 (the
+// four lowest qubits), whose rows and columns a tile holds complete: the
+// kernel applies it to the tile's outputs in LDS, and its matrix (gate_u
+// below: m x m, row-major, (re, im) pairs) arrives with each launch, so one
+// compiled kernel serves every matrix on those qubits.  table, ur, ui and
+// unit are then unused.
 struct OutPerm {
   int k;
   int bits[3];
   uint8_t table[8];
   double ur[8], ui[8];  // u_l
   int unit;             // every u_l is exactly 1: a plain permutation
+  int general;          // a general gate on bits 0..3 (see above)
 };
 
 // Shape of a tiled plan (for tests and reports).
@@ -92,7 +100,7 @@ std::string tiled_channel_source(int nq, const std::vector<std::pair<uint64_t, P
 // each gate is compiled on first use.  QCW_EAGAIN when no compiled kernel is
 // available (the caller then applies the channel and the gate separately).
 int tiled_channel_apply_perm(const TiledChannel *t, const OutPerm &perm, const double2 *in,
-                             double2 *out, hipStream_t s);
+                             double2 *out, hipStream_t s, const double *gate_u = nullptr);
 // Whether tiled_channel_apply_perm would run (compiling the kernel if needed).
 bool tiled_channel_perm_ready(const TiledChannel *t, const OutPerm &perm);
 // The same kernels (perm may be NULL: no gate) that also reduce the stored
@@ -102,7 +110,8 @@ bool tiled_channel_perm_ready(const TiledChannel *t, const OutPerm &perm);
 // records of four doubles), to be summed in a fixed order.  QCW_EAGAIN when
 // no compiled kernel is available.
 int tiled_channel_apply_obs(const TiledChannel *t, const OutPerm *perm, const double2 *in,
-                            double2 *out, const double2 *psi0, double *part, hipStream_t s);
+                            double2 *out, const double2 *psi0, double *part, hipStream_t s,
+                            const double *gate_u = nullptr);
 bool tiled_channel_obs_ready(const TiledChannel *t, const OutPerm *perm, bool fidelity);
 uint64_t tiled_channel_obs_records(const TiledChannel *t);
 // Compiles such a source for gfx950 without loading it (no device needed);

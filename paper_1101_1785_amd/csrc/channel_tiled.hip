@@ -431,6 +431,8 @@ struct TiledChannel {
     const RtcKernel *k = nullptr;
     unsigned grid = 0;
     uint32_t xcd_blocks = 0, nsub = 0;
+    int obs = 0;         // the kernel takes psi0 and part
+    int gate_words = 0;  // doubles of a general gate's matrix argument (0: none)
   };
   mutable std::mutex perm_mu;
   mutable std::map<std::vector<int>, Launch> perm_kernels;  // by gate (k, bits, table)
@@ -542,8 +544,15 @@ int spec_blocks_per_cu(int nq) { return nq <= 12 ? 2 : 3; }
 // obs: 0 no observables; 1 trace and purity; 2 also the fidelity against
 // psi0.  (Two variants rather than a branch on psi0: with the branch the
 // compiler's code for the tile loop needed 286 VGPRs instead of 130.)
-std::string tiled_source(const GenPlan &G, const OutPerm *perm, int obs) {
+std::string tiled_source(const GenPlan &G, const OutPerm *gate, int obs) {
   const int nq = G.nq, e0 = G.e0, e1 = G.e1;
+  // a monomial gate moves the stores; a general gate on bits 0..3 runs on
+  // the tile's outputs in LDS (its matrix arrives with each launch)
+  const OutPerm *perm = gate && !gate->general ? gate : nullptr;
+  const OutPerm *low = gate && gate->general ? gate : nullptr;
+  const int gm = low ? 1 << low->k : 0;
+  uint32_t gmask = 0;
+  for (int j = 0; low && j < low->k; ++j) gmask |= 1u << low->bits[j];
   const std::vector<TPartner> &P = *G.partners;
   const std::vector<TRead> &R = *G.reads;
   const std::vector<TRec> &S = *G.recs;
@@ -635,10 +644,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 )";
     }
   }
-  add(s, "extern \"C\" __global__ __launch_bounds__(%d) void %s(const double2 *__restrict__ rho, "
+  if (low) add(s, "struct GateU { double v[%d]; };  // U row-major, (re, im) pairs\n", 2 * gm * gm);
+  // (with the gate's passes the compiler would otherwise take a few VGPRs
+  // past what three blocks per CU allow)
+  add(s, "extern \"C\" __global__ __launch_bounds__(%d)%s void %s(const double2 *__restrict__ rho, "
          "double2 *__restrict__ out, const CT *__restrict__ tables, u32 *tickets, double p_keep, "
-         "u32 xcd_blocks, u32 nsub%s) {\n", kTileThreads, kSpecName,
-      obs ? ", const double2 *__restrict__ psi0, double *__restrict__ part" : "");
+         "u32 xcd_blocks, u32 nsub%s%s) {\n", kTileThreads,
+      low ? " __attribute__((amdgpu_waves_per_eu(3)))" : "", kSpecName,
+      obs ? ", const double2 *__restrict__ psi0, double *__restrict__ part" : "",
+      low ? ", const GateU gu" : "");
+  if (low) {
+    add(s, "  __shared__ double2 gx[%d];\n  __shared__ double2 gU[%d];\n", kTileElems, gm * gm);
+    add(s, "  if (threadIdx.x < %du) gU[threadIdx.x] = make_double2(gu.v[2u * threadIdx.x], "
+           "gu.v[2u * threadIdx.x + 1u]);\n", gm * gm);
+  }
   if (G.own_staged) add(s, "  __shared__ double2 own_slot[%d];\n", kTileElems);
   if (G.any_staged) add(s, "  __shared__ double2 part_slot[%d];\n", kTileElems);
   if (G.tab_entries) {
@@ -789,6 +808,49 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int a = 0; a < 4; ++a) {
     add(s, "    acc%d.x = __fma_rn(p_keep, own%d.x, acc%d.x);\n", a, a, a);
     add(s, "    acc%d.y = __fma_rn(p_keep, own%d.y, acc%d.y);\n", a, a, a);
+  }
+  if (low) {
+    // The gate on bits 0..3 of n and m, which the tile's rows (r) and columns
+    // (c) hold complete: as the conjugation computes it, first every row
+    // group with U, then every column group with conj(U), each output a
+    // chain of complex multiply-adds from +0 over the group's local index.
+    // The tile's outputs pass through LDS between the two.
+    auto dep = [&](int l) {  // bits of local index l at the gate's positions
+      uint32_t d = 0;
+      for (int j = 0; j < low->k; ++j)
+        if ((l >> (low->k - 1 - j)) & 1) d |= 1u << low->bits[j];
+      return d;
+    };
+    auto local = [&](int shift) {
+      std::string e = "0u";
+      for (int j = 0; j < low->k; ++j) {
+        char b[64];
+        snprintf(b, sizeof(b), " | (((tid >> %d) & 1u) << %d)", low->bits[j] + shift, low->k - 1 - j);
+        e += b;
+      }
+      return e;
+    };
+    for (int a = 0; a < 4; ++a) add(s, "    gx[%du | tid] = acc%d;\n", a << 8, a);
+    add(s, "    __syncthreads();\n    {\n");
+    add(s, "      const u32 gl = (%s) * %du, gb = tid & %uu;\n", local(4).c_str(), gm, ~(gmask << 4) & 255u);
+    for (int l = 0; l < gm; ++l) add(s, "      const double2 ur%d = gU[gl + %du];\n", l, l);
+    for (int a = 0; a < 4; ++a) {
+      add(s, "      acc%d = make_double2(0.0, 0.0);\n", a);
+      for (int l = 0; l < gm; ++l)
+        add(s, "      madd(acc%d, ur%d, gx[%uu | gb | %uu]);\n", a, l, (uint32_t)a << 8, dep(l) << 4);
+    }
+    add(s, "    }\n    __syncthreads();\n");
+    for (int a = 0; a < 4; ++a) add(s, "    gx[%du | tid] = acc%d;\n", a << 8, a);
+    add(s, "    __syncthreads();\n    {\n");
+    add(s, "      const u32 gl = (%s) * %du, gb = tid & %uu;\n", local(0).c_str(), gm, ~gmask & 255u);
+    for (int l = 0; l < gm; ++l)
+      add(s, "      const double2 uc%d = make_double2(gU[gl + %du].x, -gU[gl + %du].y);\n", l, l, l);
+    for (int a = 0; a < 4; ++a) {
+      add(s, "      acc%d = make_double2(0.0, 0.0);\n", a);
+      for (int l = 0; l < gm; ++l)
+        add(s, "      madd(acc%d, uc%d, gx[%uu | gb | %uu]);\n", a, l, (uint32_t)a << 8, dep(l));
+    }
+    add(s, "    }\n");
   }
   if (obs) add(s, "    double o_tr = 0.0, o_ti = 0.0, o_pu = 0.0, o_fi = 0.0;\n");
   // Observables of the stored output w at (n2, m2): trace, sum |w|^2, and
@@ -1120,7 +1182,8 @@ bool spec_launch(const TiledChannel *t, const RtcKernel *k, TiledChannel::Launch
 }
 
 int launch_spec(const TiledChannel *t, const TiledChannel::Launch &ls, const double2 *in, double2 *out,
-                hipStream_t s, const double2 *psi0 = nullptr, double *part = nullptr) {
+                hipStream_t s, const double2 *psi0 = nullptr, double *part = nullptr,
+                const double *gate_u = nullptr) {
   const double2 *a_in = in;
   double2 *a_out = out;
   const void *a_tab = t->args.tables;
@@ -1129,8 +1192,18 @@ int launch_spec(const TiledChannel *t, const TiledChannel::Launch &ls, const dou
   uint32_t a_xb = ls.xcd_blocks, a_ns = ls.nsub;
   const double2 *a_psi = psi0;
   double *a_part = part;
-  void *args[] = {&a_in, &a_out, &a_tab, &a_tk, &a_p, &a_xb, &a_ns, &a_psi, &a_part};  // the last
-  // two only for a kernel with observables (extra entries are not read)
+  double a_gu[128];  // the gate's matrix, passed by value
+  void *args[10] = {&a_in, &a_out, &a_tab, &a_tk, &a_p, &a_xb, &a_ns};
+  int n = 7;
+  if (ls.obs) {
+    args[n++] = &a_psi;
+    args[n++] = &a_part;
+  }
+  if (ls.gate_words) {
+    if (!gate_u) return fail(QCW_EINVAL, "the folded gate's matrix is missing");
+    memcpy(a_gu, gate_u, sizeof(double) * (size_t)ls.gate_words);
+    args[n++] = a_gu;
+  }
   if (hipModuleLaunchKernel(ls.k->fn, ls.grid, 1, 1, kTileThreads, 1, 1, 0, s, args, nullptr) !=
       hipSuccess)
     return fail(QCW_EHIP, "channel launch: %s", hipGetErrorString(hipGetLastError()));
@@ -1141,7 +1214,7 @@ int launch_spec(const TiledChannel *t, const TiledChannel::Launch &ls, const dou
 // without observables (compiled on first use), or nullptr.
 const TiledChannel::Launch *variant_launch(const TiledChannel *t, const OutPerm *p, int obs) {
   if (!t->spec) return nullptr;
-  std::vector<int> key = {obs, p ? p->k : 0};
+  std::vector<int> key = {obs, p ? p->k : 0, p ? p->general : 0};
   for (int j = 0; p && j < p->k; ++j) key.push_back(p->bits[j]);
   for (int l = 0; p && l < (1 << p->k); ++l) {
     key.push_back(p->table[l]);
@@ -1157,7 +1230,12 @@ const TiledChannel::Launch *variant_launch(const TiledChannel *t, const OutPerm 
   if (it != t->perm_kernels.end()) return it->second.k ? &it->second : nullptr;
   TiledChannel::Launch ls;
   const RtcKernel *k = nullptr;
-  if (rtc_get(tiled_source(t->gen, p, obs), kSpecName, &k) != QCW_OK || !spec_launch(t, k, &ls)) ls = {};
+  if (rtc_get(tiled_source(t->gen, p, obs), kSpecName, &k) != QCW_OK || !spec_launch(t, k, &ls)) {
+    ls = {};
+  } else {
+    ls.obs = obs;
+    ls.gate_words = p && p->general ? 2 << (2 * p->k) : 0;
+  }
   clear_error();
   auto &e = t->perm_kernels[key];
   e = ls;
@@ -1171,10 +1249,10 @@ bool tiled_channel_perm_ready(const TiledChannel *t, const OutPerm &perm) {
 }
 
 int tiled_channel_apply_perm(const TiledChannel *t, const OutPerm &perm, const double2 *in,
-                             double2 *out, hipStream_t s) {
+                             double2 *out, hipStream_t s, const double *gate_u) {
   const TiledChannel::Launch *ls = t ? variant_launch(t, &perm, 0) : nullptr;
   if (!ls) return QCW_EAGAIN;
-  return launch_spec(t, *ls, in, out, s);
+  return launch_spec(t, *ls, in, out, s, nullptr, nullptr, gate_u);
 }
 
 bool tiled_channel_obs_ready(const TiledChannel *t, const OutPerm *perm, bool fidelity) {
@@ -1186,10 +1264,11 @@ uint64_t tiled_channel_obs_records(const TiledChannel *t) {
 }
 
 int tiled_channel_apply_obs(const TiledChannel *t, const OutPerm *perm, const double2 *in,
-                            double2 *out, const double2 *psi0, double *part, hipStream_t s) {
+                            double2 *out, const double2 *psi0, double *part, hipStream_t s,
+                            const double *gate_u) {
   const TiledChannel::Launch *ls = t ? variant_launch(t, perm, psi0 ? 2 : 1) : nullptr;
   if (!ls) return QCW_EAGAIN;
-  return launch_spec(t, *ls, in, out, s, psi0, part);
+  return launch_spec(t, *ls, in, out, s, psi0, part, gate_u);
 }
 
 int tiled_channel_create(int nq, double p_keep,

@@ -579,6 +579,26 @@ bool gate_monomial(int k, const Geom &g, const qcw_c64 *U, OutPerm *p) {
   return true;
 }
 
+// A gate that is not monomial, with every target among the four lowest
+// qubits (state bits 0..3): the compiled kernel applies it to each tile's
+// outputs, its matrix passed with the launch.
+bool gate_low(int k, const Geom &g, OutPerm *p) {
+  memset(p, 0, sizeof(*p));
+  p->k = k;
+  p->general = 1;
+  for (int j = 0; j < k; ++j) {
+    if (g.bit[j] > 3) return false;
+    p->bits[j] = g.bit[j];
+  }
+  return true;
+}
+
+// The folded form of a gate for the compiled kernel (monomial, or general on
+// the lowest qubits), or false.
+bool gate_fold(int k, const Geom &g, const qcw_c64 *U, OutPerm *p) {
+  return gate_monomial(k, g, U, p) || gate_low(k, g, p);
+}
+
 }  // namespace
 
 int qcw_channel_create(qcw_channel **out, int nq, double p_keep, const qcw_kraus_term *terms,
@@ -696,7 +716,7 @@ int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 
   int rc = make_geom(c->nq, k, targets, &g);
   if (rc) return rc;
   OutPerm p;
-  if (c->tiled && !c->force_gather && !c->tiled_generic && gate_monomial(k, g, U, &p) &&
+  if (c->tiled && !c->force_gather && !c->tiled_generic && gate_fold(k, g, U, &p) &&
       tiled_channel_perm_ready(c->tiled, p)) {
     const uint64_t bytes = (1ull << (2 * c->nq)) * sizeof(qcw_c64);
     const uint64_t a = (uint64_t)(uintptr_t)rho_in, b = (uint64_t)(uintptr_t)rho_out;
@@ -705,7 +725,8 @@ int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 
       return rc;
     TimedLaunch t(QCW_KERNEL_CHANNEL, (hipStream_t)stream);
     return tiled_channel_apply_perm(c->tiled, p, reinterpret_cast<const double2 *>(rho_in),
-                                    reinterpret_cast<double2 *>(rho_out), (hipStream_t)stream);
+                                    reinterpret_cast<double2 *>(rho_out), (hipStream_t)stream,
+                                    reinterpret_cast<const double *>(U));
   }
   if ((rc = qcw_channel_apply(c, rho_in, rho_out, stream))) return rc;
   return qcw_rho_conjugate(k, targets, U, rho_out, c->nq, stream);
@@ -723,16 +744,16 @@ int qcw_channel_step_obs(qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out
   if ((rc = check_device_range(obs, (4 + 3 * (size_t)nq) * sizeof(double), "obs"))) return rc;
   if (psi0 && (rc = check_device_range(psi0, N * sizeof(qcw_c64), "psi0"))) return rc;
   OutPerm p;
-  bool mono = false;
+  bool folded = false;
   if (k != 0) {
     if (!U) return fail(QCW_EINVAL, "U is NULL");
     Geom g;
     if ((rc = make_geom(nq, k, targets, &g))) return rc;
-    mono = gate_monomial(k, g, U, &p);
+    folded = gate_fold(k, g, U, &p);  // a gate the compiled kernel can take
   }
   hipStream_t s = (hipStream_t)stream;
-  const bool fused = c->tiled && !c->force_gather && !c->tiled_generic && (k == 0 || mono) &&
-                     tiled_channel_obs_ready(c->tiled, mono ? &p : nullptr, psi0 != nullptr);
+  const bool fused = c->tiled && !c->force_gather && !c->tiled_generic && (k == 0 || folded) &&
+                     tiled_channel_obs_ready(c->tiled, folded ? &p : nullptr, psi0 != nullptr);
   const uint64_t records = fused ? tiled_channel_obs_records(c->tiled) : (uint64_t)obs_blocks(nq);
   // the kernel's records are first summed by up to kObsMaxBlocks blocks
   const uint64_t nred = fused ? std::min<uint64_t>(records, kObsMaxBlocks) : 0;
@@ -759,7 +780,8 @@ int qcw_channel_step_obs(qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_out
       return rc;
     {
       TimedLaunch t(QCW_KERNEL_CHANNEL, s);
-      rc = tiled_channel_apply_obs(c->tiled, mono ? &p : nullptr, in, out, ps, c->obs_part, s);
+      rc = tiled_channel_apply_obs(c->tiled, folded ? &p : nullptr, in, out, ps, c->obs_part, s,
+                                   reinterpret_cast<const double *>(U));
     }
     if (rc) return rc;
   } else {
@@ -839,10 +861,10 @@ int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, co
     Geom g;
     if ((rc = make_geom(nq, gate_k, gate_targets, &g))) return rc;
     if (!gate_U) return fail(QCW_EINVAL, "gate_U is NULL");
-    with_gate = gate_monomial(gate_k, g, gate_U, &perm);
+    with_gate = gate_fold(gate_k, g, gate_U, &perm);
   }
   *len = 0;
-  if (gate_k != 0 && !with_gate) {  // not a permutation gate: no kernel of its own
+  if (gate_k != 0 && !with_gate) {  // neither monomial nor on the lowest qubits: no kernel of its own
     if (buf && cap > 0) buf[0] = 0;
     if (compile) *code_bytes = 0;
     return QCW_OK;

@@ -116,3 +116,29 @@ def test_observables_variant_compiles(L):
         assert "o_pu" in src and "double *__restrict__ part" in src and code > 1000
         assert "wave_sum(o_pu)" in src  # register moves between lanes, no LDS round trip
     assert "o_pu" not in L.channel_kernel_source(nq, terms)[0]
+
+
+def test_general_gate_on_the_last_qubits_gets_a_kernel(L):
+    """A gate that mixes basis states is folded when every target is among
+    the four last qubits (state bits 0..3, whose rows and columns each tile
+    holds complete): the kernel runs U over the rows and conj(U) over the
+    columns of the tile's outputs in LDS, its matrix passed with the launch.
+    So the source depends on the targets, not on the matrix.  A target
+    outside those qubits: no kernel of its own."""
+    nq = 10
+    rng = np.random.default_rng(12)
+    terms = _pauli(rng, nq)
+    h, code, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(qi.H, (nq,)))
+    assert "struct GateU { double v[8]; }" in h and "gu.v" in h and code > 1000
+    assert "gate_perm" not in h  # no moved stores
+    rot = qi.random_unitary(rng, 2)
+    assert L.channel_kernel_source(nq, terms, gate=(rot, (nq,)))[0] == h  # the matrix is an argument
+    assert L.channel_kernel_source(nq, terms, gate=(qi.H, (nq - 1,)))[0] != h
+    for U, t in ((qi.random_unitary(rng, 4), (nq, nq - 3)),
+                 (qi.random_unitary(rng, 8), (nq - 1, nq - 3, nq))):
+        for obs in (False, True):
+            src, code, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(U, t), observables=obs)
+            assert f"double v[{2 * len(U) ** 2}]" in src and code > 1000
+    for t in ((nq - 4,), (1,)):
+        assert L.channel_kernel_source(nq, terms, gate=(qi.H, t))[0] == ""
+    assert L.channel_kernel_source(nq, terms, gate=(qi.random_unitary(rng, 4), (nq, 2)))[0] == ""

@@ -198,8 +198,10 @@ def test_compiled_tiled_kernel_equals_generic(L, kind, nq, seed):
 def _step_gates(nq):
     """Algorithm gates for the one-call step: permutation and monomial
     matrices (phases, Y, CZ, a phased swap) with targets among the tile's
-    thread bits (the last qubits), its E bits or the rest, and two that mix
-    basis states (the two-kernel path)."""
+    thread bits (the last qubits), its E bits or the rest; gates that mix
+    basis states on the four last qubits (H, a rotation, dense two- and
+    three-qubit unitaries: also one pass); and two that mix basis states with
+    a target outside them (the two-kernel path)."""
     S = np.diag([1.0, 1j])
     CZ = np.diag([1.0, 1.0, 1.0, -1.0]).astype(np.complex128)
     phased_swap = np.array([[np.exp(0.3j), 0, 0, 0], [0, 0, -1j, 0], [0, np.exp(-1.1j), 0, 0],
@@ -208,7 +210,10 @@ def _step_gates(nq):
     return [(qi.CNOT, (1, 2)), (qi.CNOT, (nq, 1)), (qi.CNOT, (nq - 1, nq)), (qi.CNOT, (3, nq - 2)),
             (qi.X, (nq // 2,)), (qi.SWAP, (2, nq)), (qi.TOFFOLI, (nq, 1, nq - 3)),
             (S, (nq - 1,)), (qi.Z, (1,)), (qi.Y, (nq,)), (CZ, (nq - 2, 2)),
-            (phased_swap, (nq, nq // 2)), (qi.H, (1,)), (rot, (nq - 1,))]
+            (phased_swap, (nq, nq // 2)), (qi.H, (1,)), (rot, (nq - 1,)), (qi.H, (nq,)),
+            (qi.random_unitary(np.random.default_rng(nq), 4), (nq, nq - 3)),
+            (qi.random_unitary(np.random.default_rng(nq + 1), 8), (nq - 1, nq - 3, nq)),
+            (qi.random_unitary(np.random.default_rng(nq + 2), 4), (nq - 2, 2))]
 
 
 def _monomial(U):
@@ -216,15 +221,24 @@ def _monomial(U):
     return bool(np.all(nz.sum(0) == 1) and np.all(nz.sum(1) == 1))
 
 
+def _one_pass(U, t, nq):
+    """Whether the compiled kernel takes the gate in the channel's pass: a
+    monomial gate anywhere, any other gate with every target among the four
+    last qubits (state bits 0..3, complete in each tile)."""
+    return _monomial(U) or all(nq - q <= 3 for q in t)
+
+
 @pytest.mark.parametrize("kind,nq,seed", [("pauli", 9, 1), ("phase", 8, 3), ("zheavy", 8, 5),
-                                          ("pairs", 9, 6), ("pauli", 12, 8)])
+                                          ("pairs", 9, 6), ("pauli", 12, 8), ("pauli", 13, 9)])
 def test_channel_apply_gate_equals_channel_then_conjugation(L, kind, nq, seed):
     """One multiverse step in one call (qcw_channel_apply_gate): for a
     monomial gate (U|l> = u_l |pi(l)>) the compiled kernel stores output
-    (n, m), times u_l(n) conj(u_l(m)), at (pi(n), pi(m)), so the step is one
-    pass; it must equal the channel followed by qcw_rho_conjugate exactly
-    (values equal; only zeros may differ in sign).  The timing counters show
-    which path ran."""
+    (n, m), times u_l(n) conj(u_l(m)), at (pi(n), pi(m)); for any other gate
+    on the four last qubits it applies U to the rows and conj(U) to the
+    columns of each tile's outputs in LDS; either way the step is one pass.
+    It must equal the channel followed by qcw_rho_conjugate exactly (values
+    equal; only zeros may differ in sign).  The timing counters show which
+    path ran."""
     print(f"[gpu] channel + gate in one call {kind} nq={nq}", flush=True)
     rng = np.random.default_rng(3000 + seed)
     terms = _pauli_terms(rng, nq) if kind == "pauli" else _tiled_case(kind, nq, seed)
@@ -235,7 +249,7 @@ def test_channel_apply_gate_equals_channel_then_conjugation(L, kind, nq, seed):
     a = torch.complex(torch.randn(NN, dtype=torch.float64, device="cuda", generator=g),
                       torch.randn(NN, dtype=torch.float64, device="cuda", generator=g))
     for U, t in _step_gates(nq):
-        perm = _monomial(U)
+        perm = _one_pass(U, t, nq)
         b1 = torch.full_like(a, float("nan"))
         b2 = torch.full_like(a, float("nan"))
         torch.cuda.synchronize()
@@ -299,7 +313,8 @@ def test_channel_step_obs_matches_observables(L, kind, nq, seed, choice):
     psi_d = torch.from_numpy(psi).to("cuda")
     a = dev(rho0)
     obs = torch.empty(4 + 3 * nq, dtype=torch.float64, device="cuda")
-    for U, t in ((qi.CNOT, (1, nq)), (qi.Z, (2,)), (qi.H, (1,)), (None, ())):
+    for U, t in ((qi.CNOT, (1, nq)), (qi.Z, (2,)), (qi.H, (1,)), (qi.H, (nq,)),
+                 (qi.random_unitary(rng, 4), (nq - 1, nq - 2)), (None, ())):
         b1 = torch.full_like(a, float("nan"))
         b2 = torch.full_like(a, float("nan"))
         ch.step_obs(a, b1, obs, U, t, psi0=psi_d)
