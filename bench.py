@@ -691,6 +691,55 @@ def bench_multiverse_obs(torch, L, qi, nq, seed, steps=10, n_p=16, eps=0.2):
             "what": "host clock per step including reading the observables back every step"}
 
 
+def bench_multiverse_low_gates(torch, L, qi, nq, seed, reps=20, n_p=16, eps=0.2):
+    """Multiverse steps whose gate mixes basis states on the last qubits (H,
+    a random two-qubit and a random three-qubit unitary, the compiled kernel
+    applying it to each tile's outputs in LDS), in one call
+    (qcw_channel_apply_gate) against the channel followed by
+    qcw_rho_conjugate; both must give the same bits.  The same channel as
+    the multiverse sections; rho is random."""
+    rng = np.random.default_rng([seed, 7])
+    P = [qi.X, qi.Y, qi.Z]
+    terms = []
+    for s_, ps in ((1, 0.95), (2, 0.05)):
+        for _ in range(n_p):
+            qs = [int(x) + 1 for x in rng.choice(nq, s_, replace=False)]
+            terms.append((eps * ps / n_p, {q: P[int(rng.integers(3))] for q in qs}))
+    ch = L.Channel(nq, 1 - eps, terms)
+    NN = 1 << (2 * nq)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    a = torch.complex(torch.randn(NN, dtype=torch.float64, device="cuda", generator=g),
+                      torch.randn(NN, dtype=torch.float64, device="cuda", generator=g))
+    b, c = torch.empty_like(a), torch.empty_like(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"nq": nq, "reps": reps}
+    for name, U, t in (("H_on_qubit_nq", qi.H, (nq,)),
+                       ("u2_on_last_qubits", qi.random_unitary(rng, 4), (nq, nq - 3)),
+                       ("u3_on_last_qubits", qi.random_unitary(rng, 8), (nq - 1, nq - 3, nq))):
+        print(f"[bench] multiverse nq={nq}: {name} in the channel's pass", file=sys.stderr, flush=True)
+        ch.apply_gate(a, b, U, t)  # compiles the kernel for these targets
+        ch.apply(a, c)
+        L.qcw_rho_conjugate(len(t), t, U, c)
+        torch.cuda.synchronize()
+        one = timed(lambda: ch.apply_gate(a, b, U, t))
+        two = timed(lambda: (ch.apply(a, c), L.qcw_rho_conjugate(len(t), t, U, c)))
+        out[name] = {"ms_one_pass": one, "ms_channel_then_conjugation": two,
+                     "bit_equal": bool(torch.equal(b, c))}
+    out["channel_alone_ms"] = timed(lambda: ch.apply(a, c))
+    ch.close()
+    return out
+
+
 def bench_config0(torch, L, qi, reps=10000):
     """Config 0: the paper's first worked-example size (nq = 3), one 12-gate
     random circuit (seed 0) on the plain path, one solve at a time: latency of
@@ -1042,6 +1091,7 @@ def extra_sections(torch, L, qi, a):
         "multiverse_nq13_generic": lambda: bench_multiverse(torch, L, qi, 13, 5, steps=10, kernel=2),
         "multiverse_nq14": lambda: bench_multiverse(torch, L, qi, 14, 5, steps=5),
         "multiverse_nq13_observed": lambda: bench_multiverse_obs(torch, L, qi, 13, 5),
+        "multiverse_nq13_last_qubit_gates": lambda: bench_multiverse_low_gates(torch, L, qi, 13, 5),
         "multiverse_nq15": lambda: bench_multiverse(torch, L, qi, 15, 5, steps=3),
         "eigen_batch_nq5": lambda: bench_eigen(torch, L, 5),
         "eigen_batch_nq6": lambda: bench_eigen(torch, L, 6),

@@ -428,8 +428,14 @@ int qcw_channel_apply(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 *rho_
  * and column: X, CNOT, SWAP, Toffoli, Z, S, T, Y, CZ, ...), and the channel
  * runs its compiled tiled kernel, the conjugation is folded into that
  * kernel: output (n, m), times u_l(n) conj(u_l(m)), is stored at
- * (pi(n), pi(m)), one pass over rho instead of two.  The kernel for each such
- * gate is compiled on its first use (about a second, synchronous).
+ * (pi(n), pi(m)), one pass over rho instead of two.  Any other gate whose
+ * targets are all among the four last qubits (nq - 3 .. nq: state bits
+ * 0..3, whose rows and columns each tile of the kernel holds complete) is
+ * folded as well: the kernel applies U to the rows and conj(U) to the
+ * columns of each tile's outputs in LDS, with the same operations as
+ * qcw_rho_conjugate, and U is passed with the launch.  The kernel for each
+ * such gate (for the latter, each target list) is compiled on its first use
+ * (under a second, synchronous).
  * Otherwise it is qcw_channel_apply followed by qcw_rho_conjugate on rho_out.
  * Either way the result is the same, bit for bit up to the sign of zeros.
  * rho_in and rho_out must not overlap.
@@ -442,8 +448,8 @@ int qcw_channel_apply_gate(const qcw_channel *c, const qcw_c64 *rho_in, qcw_c64 
  * asynchronously on stream), laid out as qcw_rho_observables: Tr rho (re,
  * im), Tr rho^2 as sum |rho_nm|^2, the root fidelity sqrt(<psi0|rho|psi0>)
  * against psi0 (DEVICE, 2^nq amplitudes; NULL: NaN), and each qubit's
- * polarisation.  When the step runs as the compiled kernel (a monomial gate
- * or none), that kernel sums the first four as it stores rho, with no
+ * polarisation.  When the step runs as the compiled kernel (a gate folded as
+ * above, or none), that kernel sums the first four as it stores rho, with no
  * further pass over rho; the polarisations read the 2 x 2 blocks on each
  * qubit afterwards.  Otherwise the step is followed by the observables
  * kernels.  The sums run in an order fixed by nq, so
@@ -499,7 +505,8 @@ int qcw_debug_channel_plan(qcw_channel *c, int kernel, int32_t *info);
  * these terms (host call, no device needed; for tests).  Arguments as for
  * qcw_channel_create; gate_k != 0 asks instead for the kernel that
  * qcw_channel_apply_gate compiles for the gate (gate_k, gate_targets, gate_U),
- * which has none (length 0) unless the gate is monomial; observables != 0
+ * which has none (length 0) unless the gate is monomial or has every target
+ * among the four last qubits; observables != 0
  * asks for the variant of qcw_channel_step_obs, which also sums them.  *len:
  * the source's length (0 when the channel has no tiled plan); when buf is
  * not NULL, up to cap - 1 bytes of it and a NUL are written there.  compile != 0: the source is also compiled for gfx950 with
