@@ -131,6 +131,7 @@ def test_general_gate_on_the_last_qubits_gets_a_kernel(L):
     h, code, _ = L.channel_kernel_source(nq, terms, compile=True, gate=(qi.H, (nq,)))
     assert "struct GateU { double v[8]; }" in h and "gu.v" in h and code > 1000
     assert "gate_perm" not in h  # no moved stores
+    assert "gx[" in h  # the tile's outputs pass through LDS between the two passes
     rot = qi.random_unitary(rng, 2)
     assert L.channel_kernel_source(nq, terms, gate=(rot, (nq,)))[0] == h  # the matrix is an argument
     assert L.channel_kernel_source(nq, terms, gate=(qi.H, (nq - 1,)))[0] != h

@@ -212,6 +212,7 @@ def _step_gates(nq):
             (S, (nq - 1,)), (qi.Z, (1,)), (qi.Y, (nq,)), (CZ, (nq - 2, 2)),
             (phased_swap, (nq, nq // 2)), (qi.H, (1,)), (rot, (nq - 1,)), (qi.H, (nq,)),
             (qi.random_unitary(np.random.default_rng(nq), 4), (nq, nq - 3)),
+            (qi.random_unitary(np.random.default_rng(nq + 3), 4), (nq, nq - 1)),
             (qi.random_unitary(np.random.default_rng(nq + 1), 8), (nq - 1, nq - 3, nq)),
             (qi.random_unitary(np.random.default_rng(nq + 2), 4), (nq - 2, 2))]
 
