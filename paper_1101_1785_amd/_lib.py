@@ -631,7 +631,8 @@ def channel_kernel_source(nq, terms, compile=False, gate=None, observables=False
     """(source, code_bytes, compiler_version) of the tiled kernel a Channel
     over these terms compiles at creation (qcw_debug_channel_source; host
     only), or with gate = (U, targets) the one apply_gate compiles for that
-    gate ("" unless U is a permutation matrix).  source is "" when the
+    gate ("" unless U is monomial or every target is among the four last
+    qubits).  source is "" when the
     channel has no tiled plan; code_bytes is None unless compile;
     compiler_version is major * 100 + minor."""
     tab, mats = pack_terms(terms)
@@ -669,7 +670,8 @@ class Channel:
 
     def apply_gate(self, rho_in, rho_out, U, targets, stream=None):
         """rho_out = U channel(rho_in) U^dagger (qcw_channel_apply_gate): one
-        pass when U is a permutation matrix and the compiled tiled kernel runs."""
+        pass when the compiled tiled kernel runs and U is monomial or acts on
+        the four last qubits only."""
         k = len(targets)
         t = _targets(targets)
         U = _mat(U, k)
