@@ -18,6 +18,11 @@ Nothing here is shared with the HIP library.
   (§5, the ideal and noisy channels; the storage case).
 * eigen_observables: eigenvalues, von Neumann entropy (in bits, so that the
   classical limit is nq) via numpy's Hermitian eigensolver, for pins only.
+* pair_polarization(rho, a, b): the 15 parameters of the two-qubit form in
+  the footnote to §5's density-matrix paragraph, for qubits a and b: the
+  polarisations P1 = Tr[(sigma x 1) rho], P2 = Tr[(1 x sigma) rho] and the
+  3 x 3 spin correlation tensor C_ij = Tr[(sigma_i x sigma_j) rho] (the
+  footnote's traces omit rho; read as in the one-qubit case before it).
 """
 from __future__ import annotations
 
@@ -95,6 +100,18 @@ def observables(rho, psi0=None) -> dict:
             P[q - 1, i] = np.real(np.trace(embed({q: s}, nq) @ rho))
     out["polarization"] = P
     return out
+
+
+def pair_polarization(rho, a: int, b: int) -> np.ndarray:
+    """[P1 (x, y, z), P2 (x, y, z), C row-major (i for qubit a, j for b)]:
+    traces of rho with Pauli operators on qubits a and b (1-based,
+    distinct), each operator embedded as a full 2^nq matrix."""
+    nq = _nq(rho)
+    S = (SX, SY, SZ)
+    out = [np.real(np.trace(embed({a: s}, nq) @ rho)) for s in S]
+    out += [np.real(np.trace(embed({b: s}, nq) @ rho)) for s in S]
+    out += [np.real(np.trace(embed({a: si, b: sj}, nq) @ rho)) for si in S for sj in S]
+    return np.array(out)
 
 
 def eigen_observables(rho) -> dict:

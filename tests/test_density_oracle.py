@@ -176,3 +176,55 @@ def test_eigen_pins():
     assert abs(np.sum(D.eigen_observables(r)["eigenvalues"]) - 1) <= 1e-14
     assert abs(D.fidelity_general(r, r) - 1) <= 1e-7
     assert abs(D.fidelity_general(D.pure(qi.basis_state(2, 0)), D.pure(qi.basis_state(2, 3)))) <= 1e-7
+
+
+def _bloch(P):
+    """One-qubit rho = (1 + P . sigma) / 2 (§5, the one-qubit form)."""
+    return (np.eye(2) + P[0] * D.SX + P[1] * D.SY + P[2] * D.SZ) / 2
+
+
+def test_pair_polarization_pins():
+    """The two-qubit form of §5's footnote, rho = (1 + P1 . sigma x 1 + P2 .
+    1 x sigma + C . sigma x sigma) / 4:
+    * a product of one-qubit states (1 + P . sigma)/2 has polarisations P
+      and C_ij = P1_i P2_j, with the pair anywhere in a larger product and in
+      either order (C transposes);
+    * the Bell state (|00> + |11>)/sqrt2 has P1 = P2 = 0 and C = diag(1, -1, 1);
+    * for any rho the 15 numbers rebuild the pair's reduced matrix by the
+      footnote's formula."""
+    rng = np.random.default_rng(21)
+    Ps = [rng.normal(size=3) for _ in range(4)]
+    Ps = [P / np.linalg.norm(P) * rng.uniform(0.2, 1.0) for P in Ps]
+    rho = _bloch(Ps[0])
+    for P in Ps[1:]:
+        rho = np.kron(rho, _bloch(P))                      # qubits 1..4
+    for a, b in ((1, 2), (2, 4), (4, 1), (3, 1)):
+        v = D.pair_polarization(rho, a, b)
+        Pa, Pb = Ps[a - 1], Ps[b - 1]
+        assert np.max(np.abs(v[:3] - Pa)) <= 1e-15 and np.max(np.abs(v[3:6] - Pb)) <= 1e-15
+        assert np.max(np.abs(v[6:].reshape(3, 3) - np.outer(Pa, Pb))) <= 1e-15
+    bell = D.conjugate(D.conjugate(D.pure(qi.basis_state(2, 0)), qi.H, (1,)), qi.CNOT, (1, 2))
+    v = D.pair_polarization(bell, 1, 2)
+    assert np.max(np.abs(v[:6])) <= 8 * EPS
+    assert np.max(np.abs(v[6:].reshape(3, 3) - np.diag([1.0, -1.0, 1.0]))) <= 8 * EPS
+    S = (D.SX, D.SY, D.SZ)
+    r = _rand_rho(rng, 4)
+    for a, b in ((1, 3), (2, 4)):
+        v = D.pair_polarization(r, a, b)
+        re = np.eye(4, dtype=np.complex128)
+        for i in range(3):
+            re = re + v[i] * np.kron(S[i], np.eye(2)) + v[3 + i] * np.kron(np.eye(2), S[i])
+            for j in range(3):
+                re = re + v[6 + 3 * i + j] * np.kron(S[i], S[j])
+        assert np.max(np.abs(re / 4 - D.partial_trace(r, [a, b]))) <= 1e-15
+    assert np.max(np.abs(D.pair_polarization(r, 2, 4)[:3] - D.observables(r)["polarization"][1])) <= 1e-15
+
+
+def test_planted_pair_index_mistake_caught():
+    """The pins fail for a plausible slip: C with its indices swapped."""
+    rng = np.random.default_rng(22)
+    Pa, Pb = rng.normal(size=3), rng.normal(size=3)
+    rho = np.kron(_bloch(Pa / 2), _bloch(Pb / 3))
+    v = D.pair_polarization(rho, 1, 2)
+    swapped = v[6:].reshape(3, 3).T
+    assert np.max(np.abs(swapped - np.outer(Pa / 2, Pb / 3))) > 1e-3
