@@ -523,6 +523,21 @@ int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, co
                              int32_t *compiler_version);
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host,
                         double *out_host, void *stream);
+/*
+ * The 15 parameters of two qubits qa and qb (1-based, distinct) of rho, in
+ * the two-qubit form of the footnote to §5's density-matrix paragraph,
+ *   rho_ab = (1 + P1 . (sigma x 1) + P2 . (1 x sigma) + C . (sigma x sigma)) / 4,
+ * rho_ab being the reduced density matrix of (qa, qb) in that order: out
+ * (DEVICE, 15 doubles) gets P1 = Tr[(sigma x 1) rho] (x, y, z), P2 =
+ * Tr[(1 x sigma) rho], and the spin correlation tensor C_ij = Tr[(sigma_i x
+ * sigma_j) rho], row-major (i for qa).  The footnote's traces omit rho; they
+ * are read as in the one-qubit case P = Tr[sigma rho] before it.  P1 is
+ * qa's polarisation from qcw_rho_observables (to rounding).  Asynchronous on
+ * stream, sums in an order fixed by nq.  QCW_EINVAL for nq outside [2, 17]
+ * or bad qubits.
+ */
+int qcw_rho_pair_polarization(const qcw_c64 *rho, int nq, int qa, int qb, double *out,
+                              void *stream);
 
 /*
  * Eigenvalue-based observables (§5, classical-limit discussion: the paper

@@ -102,6 +102,7 @@ _SIGS = {
     "qcw_rho_fidelity_batch": ([_P, _i64, _P, _i64, _i32, _i64, _P, _P], _i32),
     "qcw_rho_fidelity": ([_P, _P, _i32, _P, _P], _i32),
     "qcw_rho_partial_trace": ([_P, _i32, _P, _i32, _P, _P], _i32),
+    "qcw_rho_pair_polarization": ([_P, _i32, _i32, _i32, _P, _P], _i32),
     "qcw_server_create": ([_P, _P], _i32),
     "qcw_server_submit": ([_P, _P, _P], _i32),
     "qcw_server_poll": ([_P, ctypes.c_uint64, _P, _P], _i32),
@@ -789,6 +790,17 @@ def qcw_rho_fidelity_batch(rho, rho0, nq, count, rho_stride=None, rho0_stride=No
         out = torch.empty(count, dtype=torch.float64, device=rho.device)
     _check(_L.qcw_rho_fidelity_batch(_dptr(rho), rho_stride, _dptr(rho0), rho0_stride, nq, count,
                                      _dptr_f64(out), _stream(stream)), "qcw_rho_fidelity_batch")
+    return out
+
+
+def qcw_rho_pair_polarization(rho, qa, qb, nq=None, stream=None):
+    """[P1 (3), P2 (3), C (3 x 3 row-major)] of qubits qa, qb (a device
+    tensor of 15 doubles; qcw_rho_pair_polarization)."""
+    import torch
+    nq = _rho_nq(rho, nq)
+    out = torch.empty(15, dtype=torch.float64, device=rho.device)
+    _check(_L.qcw_rho_pair_polarization(_dptr(rho), nq, int(qa), int(qb), _dptr_f64(out),
+                                        _stream(stream)), "qcw_rho_pair_polarization")
     return out
 
 

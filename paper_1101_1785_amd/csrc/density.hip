@@ -397,6 +397,50 @@ __global__ __launch_bounds__(kObsThreads) void obs_polar_kernel(const double2 *_
   if (threadIdx.x == 0) out[4 + blockIdx.x] = v[0];
 }
 
+// One block per parameter of the two-qubit form (§5, the footnote to the
+// density-matrix paragraph) of qubits at state bits ba (first) and bb: block
+// b < 3 gives P1 = Tr[(sigma_(b+1) x 1) rho], b < 6 P2 = Tr[(1 x sigma) rho],
+// then C_ij = Tr[(sigma_i x sigma_j) rho] row-major.  Operators are coded
+// 0 = 1, 1 = X, 2 = Y, 3 = Z.  Each Pauli row l has one nonzero, in column
+// l (1, Z) or 1 - l (X, Y), so Tr[(A x B) rho] = sum over rows (la, lb) and
+// over the other bits s of A[la][ka] B[lb][kb] rho[(s, ka, kb), (s, la, lb)].
+__device__ __forceinline__ int pauli_col(int op, int l) { return op == 1 || op == 2 ? 1 - l : l; }
+__device__ __forceinline__ double2 pauli_coef(int op, int l) {
+  switch (op) {
+    case 2: return make_double2(0.0, l ? 1.0 : -1.0);  // [[0, -i], [i, 0]]
+    case 3: return make_double2(l ? -1.0 : 1.0, 0.0);
+    default: return make_double2(1.0, 0.0);
+  }
+}
+__global__ __launch_bounds__(kObsThreads) void pair_pol_kernel(const double2 *__restrict__ rho,
+                                                               int nq, int ba, int bb,
+                                                               double *__restrict__ out) {
+  __shared__ double red[kObsThreads];
+  const int b = blockIdx.x;
+  const int A = b < 3 ? b + 1 : b < 6 ? 0 : 1 + (b - 6) / 3;
+  const int B = b < 3 ? 0 : b < 6 ? b - 2 : 1 + (b - 6) % 3;
+  const int lo = ba < bb ? ba : bb, hi = ba < bb ? bb : ba;
+  const uint64_t N = 1ull << nq, rest = 1ull << (nq - 2);
+  double v[1] = {0};
+  for (uint64_t s = threadIdx.x; s < rest; s += blockDim.x) {
+    uint64_t base = ((s >> lo) << (lo + 1)) | (s & ((1ull << lo) - 1));
+    base = ((base >> hi) << (hi + 1)) | (base & ((1ull << hi) - 1));
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int la = l >> 1, lb = l & 1;
+      const int ka = pauli_col(A, la), kb = pauli_col(B, lb);
+      const double2 ca = pauli_coef(A, la), cb = pauli_coef(B, lb);
+      const double2 c = make_double2(ca.x * cb.x - ca.y * cb.y, ca.x * cb.y + ca.y * cb.x);
+      const uint64_t row = base | ((uint64_t)ka << ba) | ((uint64_t)kb << bb);
+      const uint64_t col = base | ((uint64_t)la << ba) | ((uint64_t)lb << bb);
+      const double2 x = rho[row * N + col];
+      v[0] += c.x * x.x - c.y * x.y;  // Re(c x); c is 1, -1, i or -i
+    }
+  }
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) out[b] = v[0];
+}
+
 // The blocks' partial sums, in a fixed order (thread t takes blocks t,
 // t + kObsThreads, ..., then the block's fixed tree), so the result does not
 // depend on timing.  One block of kObsThreads threads.
@@ -882,6 +926,21 @@ int qcw_debug_channel_source(int nq, const qcw_kraus_term *terms, int nterms, co
     *code_bytes = 0;
     if (!src.empty() && (rc = tiled_channel_compile_check(src, code_bytes))) return rc;
   }
+  return QCW_OK;
+}
+
+int qcw_rho_pair_polarization(const qcw_c64 *rho, int nq, int qa, int qb, double *out,
+                              void *stream) {
+  clear_error();
+  if (nq < 2 || nq > kRhoMaxQubits) return fail(QCW_EINVAL, "nq=%d outside [2, %d]", nq, kRhoMaxQubits);
+  if (qa < 1 || qa > nq || qb < 1 || qb > nq || qa == qb)
+    return fail(QCW_EINVAL, "qubits (%d, %d): need two distinct qubits in [1, %d]", qa, qb, nq);
+  int rc = check_device_range(rho, ((uint64_t)1 << (2 * nq)) * sizeof(qcw_c64), "rho");
+  if (rc || (rc = check_device_range(out, 15 * sizeof(double), "out"))) return rc;
+  hipLaunchKernelGGL(pair_pol_kernel, dim3(15), dim3(kObsThreads), 0, (hipStream_t)stream,
+                     reinterpret_cast<const double2 *>(rho), nq, nq - qa, nq - qb, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(QCW_EHIP, "pair polarisation: %s", hipGetErrorString(e));
   return QCW_OK;
 }
 

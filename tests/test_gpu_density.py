@@ -883,3 +883,47 @@ def test_pauli_channel_16_qubits_basis_state(L):
     assert abs(complex(b.sum().item()) - 1.0) <= 1e-14
     del b
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("nq,pairs", [(2, ((1, 2), (2, 1))), (3, ((1, 3), (3, 2))),
+                                      (5, ((2, 4), (5, 1), (4, 5))), (8, ((1, 8), (7, 3), (6, 7)))])
+def test_pair_polarization_matches_oracle(L, nq, pairs):
+    """qcw_rho_pair_polarization: P1, P2 and the correlation tensor of two
+    qubits (the two-qubit form of §5's footnote) against the oracle's traces
+    with full Pauli operators, to 1e-13; the same bits on a repeated call."""
+    print(f"[gpu] pair polarisation nq={nq}", flush=True)
+    rng = np.random.default_rng(900 + nq)
+    rho0 = _rand_rho(rng, nq)
+    a = dev(rho0)
+    for qa, qb in pairs:
+        got = L.qcw_rho_pair_polarization(a, qa, qb).cpu().numpy()
+        again = L.qcw_rho_pair_polarization(a, qa, qb).cpu().numpy()
+        assert np.array_equal(got, again)
+        want = D.pair_polarization(rho0, qa, qb)
+        assert np.max(np.abs(got - want)) <= 1e-13, (qa, qb, got - want)
+
+
+def test_pair_polarization_product_state_closed_form(L):
+    """At nq = 12 (beyond the oracle's full operators): for a product of
+    one-qubit states (1 + P . sigma)/2 the pair's polarisations are the
+    factors' P and C = P_a P_b^T; P1 also equals qcw_rho_observables'
+    polarisation of qa."""
+    nq = 12
+    print(f"[gpu] pair polarisation product state nq={nq}", flush=True)
+    rng = np.random.default_rng(77)
+    Ps = [rng.normal(size=3) for _ in range(nq)]
+    Ps = [P / np.linalg.norm(P) * rng.uniform(0.3, 1.0) for P in Ps]
+    rho = np.array([[1.0 + 0j]])
+    for P in Ps:
+        rho = np.kron(rho, (np.eye(2) + P[0] * D.SX + P[1] * D.SY + P[2] * D.SZ) / 2)
+    a = dev(rho)
+    obs = L.qcw_rho_observables(a)
+    for qa, qb in ((1, 12), (12, 1), (5, 6), (3, 10)):
+        v = L.qcw_rho_pair_polarization(a, qa, qb).cpu().numpy()
+        Pa, Pb = Ps[qa - 1], Ps[qb - 1]
+        assert np.max(np.abs(v[:3] - Pa)) <= 1e-13 and np.max(np.abs(v[3:6] - Pb)) <= 1e-13
+        assert np.max(np.abs(v[6:].reshape(3, 3) - np.outer(Pa, Pb))) <= 1e-13
+        assert np.max(np.abs(v[:3] - obs["polarization"][qa - 1])) <= 1e-13
+    for bad in ((3, 3), (0, 2), (2, 13)):
+        with pytest.raises(RuntimeError):
+            L.qcw_rho_pair_polarization(a, *bad)
