@@ -382,16 +382,29 @@ __global__ __launch_bounds__(kObsThreads) void obs_polar_kernel(const double2 *_
   const int q = blockIdx.x / 3 + 1, comp = blockIdx.x % 3;
   const int b = nq - q;
   const uint64_t N = 1ull << nq, st = 1ull << b;
+  // Rows n = tid, tid + blockDim.x, ... in ascending order; eight rows'
+  // loads are issued before their terms are added (in that order), since
+  // every element lies in a row of its own.
+  constexpr int U = 8;
   double v[1] = {0};
-  for (uint64_t n = threadIdx.x; n < N; n += blockDim.x) {
-    if (comp == 2) {
-      const double d = rho[n * N + n].x;
-      v[0] += ((n >> b) & 1) ? -d : d;
-    } else if (!((n >> b) & 1)) {
-      const double2 a = rho[n * N + (n | st)];   // <n|rho|n'>, qubit q: 0 -> 1
-      const double2 c = rho[(n | st) * N + n];   // <n'|rho|n>
-      v[0] += comp == 0 ? (a.x + c.x) : (c.y - a.y);
+  for (uint64_t n0 = threadIdx.x; n0 < N; n0 += U * (uint64_t)blockDim.x) {
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t n = n0 + (uint64_t)u * blockDim.x;
+      t[u] = 0.0;
+      if (n >= N) continue;
+      if (comp == 2) {
+        const double d = rho[n * N + n].x;
+        t[u] = ((n >> b) & 1) ? -d : d;
+      } else if (!((n >> b) & 1)) {
+        const double2 a = rho[n * N + (n | st)];   // <n|rho|n'>, qubit q: 0 -> 1
+        const double2 c = rho[(n | st) * N + n];   // <n'|rho|n>
+        t[u] = comp == 0 ? (a.x + c.x) : (c.y - a.y);
+      }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[0] += t[u];
   }
   block_sum<1>(v, red);
   if (threadIdx.x == 0) out[4 + blockIdx.x] = v[0];
