@@ -238,8 +238,9 @@ def test_channel_apply_gate_equals_channel_then_conjugation(L, kind, nq, seed):
     on the four last qubits it applies U to the rows and conj(U) to the
     columns of each tile's outputs in LDS; either way the step is one pass.
     It must equal the channel followed by qcw_rho_conjugate exactly (values
-    equal; only zeros may differ in sign).  The timing counters show which
-    path ran."""
+    equal; only zeros may differ in sign), and, up to nq = 9, the oracle's
+    channel and conjugation to 1e-12.  The timing counters show which path
+    ran."""
     print(f"[gpu] channel + gate in one call {kind} nq={nq}", flush=True)
     rng = np.random.default_rng(3000 + seed)
     terms = _pauli_terms(rng, nq) if kind == "pauli" else _tiled_case(kind, nq, seed)
@@ -266,6 +267,9 @@ def test_channel_apply_gate_equals_channel_then_conjugation(L, kind, nq, seed):
         torch.cuda.synchronize()
         assert not bool(torch.isnan(b1).any()), t
         assert torch.equal(b1, b2), t
+        if perm and nq <= 9:  # the folded step against the oracle directly
+            want = D.conjugate(D.channel(host(a, nq), 0.8, terms), U, t)
+            assert np.max(np.abs(host(b1, nq) - want)) <= TOL, t
     ch.close()
 
 
