@@ -113,3 +113,14 @@ def test_single_hip_runtime_in_process():
             "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))") % ROOT
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert out.stdout.strip() == "1", out.stdout + out.stderr
+
+
+def test_pair_polarization_rejects_bad_qubits(L):
+    """qcw_rho_pair_polarization checks nq and the two qubits before it looks
+    at device memory."""
+    lib = L.lib()
+    rho, out = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    for nq, qa, qb in ((1, 1, 2), (18, 1, 2), (5, 3, 3), (5, 0, 2), (5, 2, 6)):
+        rc = lib.qcw_rho_pair_polarization(rho, nq, qa, qb, out, None)
+        assert rc == L.QCW_EINVAL, (nq, qa, qb)
+        assert "qubit" in lib.qcw_last_error().decode() or "nq" in lib.qcw_last_error().decode()
