@@ -186,33 +186,50 @@ __device__ __forceinline__ void channel_one(
   for (int t = 0; t < nterms; ++t) {
     const DevTerm &T = terms[t];
     double2 acc = make_double2(0.0, 0.0);
+    // A hit on qubits outside lane_bits has one coefficient block per wave:
+    // its index comes from the first lane's n and m, so every lane reads the
+    // same entries (one cache line per load instead of up to four or
+    // sixteen; same values, same operations; the branch is the same in every
+    // lane).
     if (T.nops == 1) {
       const int b = T.bit0;
-      const int rb = (int)((n >> b) & 1), cb = (int)((m >> b) & 1);
       const uint64_t n0 = n & ~(1ull << b), m0 = m & ~(1ull << b);
-      const double2 *C = coef + T.coef_off + (rb * 2 + cb) * 4;
+      auto hit = [&](const double2 *C) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int e = 0; e < 2; ++e)
-          acc = cmad(acc, C[a * 2 + e],
-                     rho[((n0 | ((uint64_t)a << b)) << nq) | (m0 | ((uint64_t)e << b))]);
+          for (int e = 0; e < 2; ++e)
+            acc = cmad(acc, C[a * 2 + e],
+                       rho[((n0 | ((uint64_t)a << b)) << nq) | (m0 | ((uint64_t)e << b))]);
+      };
+      if (((1u << b) & lane_bits) == 0)
+        hit(coef + T.coef_off + (((nu >> b) & 1u) * 2 + ((mu >> b) & 1u)) * 4);
+      else
+        hit(coef + T.coef_off + (((n32 >> b) & 1u) * 2 + ((m32 >> b) & 1u)) * 4);
     } else {
       const int b0 = T.bit0, b1 = T.bit1;
-      const int ri = (int)((n >> b0) & 1) * 2 + (int)((n >> b1) & 1);
-      const int ci = (int)((m >> b0) & 1) * 2 + (int)((m >> b1) & 1);
       const uint64_t clr = ~((1ull << b0) | (1ull << b1));
       const uint64_t n0 = n & clr, m0 = m & clr;
-      const double2 *C = coef + T.coef_off + (ri * 4 + ci) * 16;
+      auto hit = [&](const double2 *C) {
 #pragma unroll
-      for (int ai = 0; ai < 4; ++ai) {
-        const uint64_t nn = n0 | ((uint64_t)(ai >> 1) << b0) | ((uint64_t)(ai & 1) << b1);
+        for (int ai = 0; ai < 4; ++ai) {
+          const uint64_t nn = n0 | ((uint64_t)(ai >> 1) << b0) | ((uint64_t)(ai & 1) << b1);
 #pragma unroll
-        for (int ei = 0; ei < 4; ++ei) {
-          const uint64_t mm = m0 | ((uint64_t)(ei >> 1) << b0) | ((uint64_t)(ei & 1) << b1);
-          acc = cmad(acc, C[ai * 4 + ei], rho[(nn << nq) | mm]);
+          for (int ei = 0; ei < 4; ++ei) {
+            const uint64_t mm = m0 | ((uint64_t)(ei >> 1) << b0) | ((uint64_t)(ei & 1) << b1);
+            acc = cmad(acc, C[ai * 4 + ei], rho[(nn << nq) | mm]);
+          }
         }
-      }
+      };
+      auto block = [&](uint32_t nv, uint32_t mv) {
+        const uint32_t ri = ((nv >> b0) & 1u) * 2 + ((nv >> b1) & 1u);
+        const uint32_t ci = ((mv >> b0) & 1u) * 2 + ((mv >> b1) & 1u);
+        return coef + T.coef_off + (ri * 4 + ci) * 16;
+      };
+      if ((((1u << b0) | (1u << b1)) & lane_bits) == 0)
+        hit(block(nu, mu));
+      else
+        hit(block(n32, m32));
     }
     acc_all.x = __fma_rn(T.weight, acc.x, acc_all.x);
     acc_all.y = __fma_rn(T.weight, acc.y, acc_all.y);
