@@ -1098,6 +1098,8 @@ def extra_sections(torch, L, qi, a):
         "multiverse_nq5": lambda: bench_multiverse(torch, L, qi, 5, 5, steps=200),
         "multiverse_nq5_rotation_noise": lambda: bench_multiverse(torch, L, qi, 5, 6, steps=200,
                                                                   noise="rotation"),
+        "multiverse_nq10_rotation_noise": lambda: bench_multiverse(torch, L, qi, 10, 6, steps=20,
+                                                                   noise="rotation"),
         "serving_config3": lambda: bench_serving(L, qi, 3, a.serve_rate, a.serve_seconds, 3, 9,
                                                  tt),
     }
