@@ -402,7 +402,9 @@ int qcw_batch_autotune(const char *out_path, int nq_lo, int nq_hi, int ninst,
  * fidelity Tr sqrt(sqrt(rho0) rho sqrt(rho0)) = sqrt(<psi0|rho|psi0>) against
  * the pure reference rho0 = |psi0><psi0| (psi0_host: 2^nq host amplitudes, or
  * NULL, then NaN); and for qubit q = 1..nq the polarisation Tr[sigma_x,y,z^(q)
- * rho] (§5, the ideal and noisy channels).
+ * rho] (§5, the ideal and noisy channels).  It keeps a device scratch buffer
+ * per device (about 2 MB, allocated on the first call and kept) and
+ * serialises concurrent calls on it.
  */
 typedef struct {
   int32_t nops;   /* 1 or 2 */

@@ -974,6 +974,45 @@ int qcw_rho_pair_polarization(const qcw_c64 *rho, int nq, int qa, int qb, double
   return QCW_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device scratch of qcw_rho_observables (partial sums, outputs, psi0): one
+// per device, sized for the largest state, allocated on first use and kept
+// (freeing it would synchronise the device on every call).  The lock is
+// held from the first launch to the copy's completion, so concurrent calls
+// do not share it.
+std::mutex g_obs_mu;
+std::map<int, double *> g_obs_scratch;
+constexpr size_t kObsScratchBytes = sizeof(double) * (kObsMaxBlocks * 4 + 4 + 3 * kRhoMaxQubits) +
+                                    sizeof(qcw_c64) * ((size_t)1 << kRhoMaxQubits);
+
+int obs_scratch(double **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QCW_EHIP, "cannot query the device");
+  }
+  auto it = g_obs_scratch.find(dev);
+  if (it != g_obs_scratch.end()) {
+    *out = it->second;
+    return QCW_OK;
+  }
+  double *d = nullptr;
+  if (hipMalloc(&d, kObsScratchBytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QCW_ENOMEM, "observables scratch");
+  }
+  g_obs_scratch[dev] = d;
+  *out = d;
+  return QCW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host, double *out_host,
                         void *stream) {
   clear_error();
@@ -984,13 +1023,10 @@ int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host, do
   hipStream_t s = (hipStream_t)stream;
   const int nout = 4 + 3 * nq;
   const size_t N = (size_t)1 << nq;
+  std::lock_guard<std::mutex> lk(g_obs_mu);
   double *scratch = nullptr;  // partials, outputs, then psi0
+  if ((rc = obs_scratch(&scratch))) return rc;
   const int nblocks = obs_blocks(nq);
-  const size_t bytes = sizeof(double) * (nblocks * 4 + nout) + (psi0_host ? N * sizeof(qcw_c64) : 0);
-  if (hipMalloc(&scratch, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(QCW_ENOMEM, "observables scratch");
-  }
   double *partial = scratch, *out = scratch + nblocks * 4;
   double2 *psi_d = psi0_host ? reinterpret_cast<double2 *>(out + nout) : nullptr;
   hipError_t e = hipSuccess;
@@ -1006,7 +1042,6 @@ int qcw_rho_observables(const qcw_c64 *rho, int nq, const qcw_c64 *psi0_host, do
   }
   if (e == hipSuccess) e = hipMemcpyAsync(out_host, out, sizeof(double) * nout, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(scratch);
   if (e != hipSuccess) return fail(QCW_EHIP, "observables: %s", hipGetErrorString(e));
   return QCW_OK;
 }
